@@ -1,0 +1,161 @@
+"""Benchmark: sweep cell-direction updates/s and GMRES solve time (FP64 vs mixed).
+
+One step = one application of the reduced operator K x of the reconstructed
+low-memory scheme (all four quadrant sweeps with their angular reductions, the
+B_11 stencil and the combine) on the 256 x 256, S8 (40 directions) workload with
+eps = 1e-3 and seeded 8 x 8 block cross sections.  value = n_cells * n_dir * steps
+/ timed seconds.  After the timed steps the same workload is solved to a true FP64
+relative residual of 1e-8 in FP64 mode and in mixed mode (FP32 sweeps), and the
+dominant kernel (the sweep) is timed live with HIP events on its launch stream for
+the roofline figure.  The CPU baseline times the CPU oracle's operator on a bounded
+sample of the same recipe (see cpu_baseline.sample).
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-solve]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def sweep_bytes_per_launch(ncell, scheme):
+    """Algorithmic HBM bytes of one operator sweep launch (FP64): per quadrant each cell's
+    inputs (x_0, the two slope moments of x_1, sigma_t|K|, sigma_s/eps |K|) are read once
+    and its per-quadrant reductions (6 for RLMDG, 3 LMDG, 4 STD) written once."""
+    n_in = 5 if scheme != "std" else 6
+    n_out = {"rlmdg": 6, "lmdg": 3, "std": 4}[scheme]
+    return 4 * ncell * (n_in + n_out) * 8
+
+
+def cpu_baseline(seconds):
+    """Oracle reduced operator (CPU, FP64) on a 128 x 128 sample of the same recipe."""
+    from oracle import schemes as S
+    from oracle.dg import Mesh
+    from oracle.quadrature import level_symmetric
+    from paper_1907_01027_amd.workloads import materials
+    n = (128, 128)
+    ss, sa, ep, q = materials(2, n=n)
+    om, w = level_symmetric(8, 2)
+    t0 = time.perf_counter()
+    prob = S.Problem(Mesh(n), om, w, ss, sa, ep, q=q[0])
+    red = S.LowMemoryReduced(prob, reconstructed=True)
+    setup = time.perf_counter() - t0
+    x = np.random.default_rng(0).normal(size=4 * n[0] * n[1])
+    k = 0
+    t0 = time.perf_counter()
+    while True:
+        red.apply(x)
+        k += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    ups = n[0] * n[1] * len(w) * k / el
+    return {"value": ups, "unit": "cell-direction updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle RLMDG reduced operator K x (sparse LU of each direction's sweep block, "
+                      f"FP64) on the 128x128 S8 mesh of the same seeded recipe; {k} applications in "
+                      f"{el:.1f} s after {setup:.1f} s of assembly and factorisation; single-threaded "
+                      f"SciPy/NumPy (host has {os.cpu_count()} logical CPUs)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); this build has no multi-GPU path. "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1907_01027_amd import lmdg
+    from paper_1907_01027_amd.workloads import WORKLOADS, materials
+
+    wl = WORKLOADS[2]
+    n = wl.n
+    scheme = wl.scheme
+    ss, sa, ep, q = materials(2)
+    omega, w = lmdg.lmdg_quadrature_level_symmetric(2, wl.order)
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
+    solver = lmdg.Solver(n, (1.0, 1.0), omega, w)
+    h = solver.h
+    lmdg.lmdg_set_materials(h, T(ss), T(sa), T(ep), T(q[0]))
+    ncell = n[0] * n[1]
+    N = 4 * ncell
+    x = T(np.random.default_rng(7).normal(size=N))
+    y = torch.empty(N, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        lmdg.lmdg_apply(h, scheme, "fp64", x, y)
+    torch.cuda.synchronize()
+    lmdg.lmdg_profile(h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lmdg.lmdg_apply(h, scheme, "fp64", x, y)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    k_ms, k_n = lmdg.lmdg_sweep_kernel_time(h)
+    lmdg.lmdg_profile(h, False)
+    ms_step = 1e3 * elapsed / args.steps
+    updates = ncell * len(w) * args.steps / elapsed
+    sweep_ms = k_ms / max(k_n, 1)
+    nbytes = sweep_bytes_per_launch(ncell, scheme)
+    achieved = nbytes / (sweep_ms * 1e-3) / 1e9
+    out = {
+        "metric": "sweep cell-direction updates/s + GMRES solve time to 1e-8, FP64 vs mixed",
+        "value": updates,
+        "unit": "cell-direction updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "256x256 unit square, S8 level-symmetric (40 directions), eps=1e-3, "
+                               "sigma_s/sigma_a on 8x8 blocks U[0.5,2], q U[0,1], vacuum inflow, "
+                               "low-memory DG with upwind reconstruction (RLMDG), FP64",
+                   "cells": ncell, "directions": len(w), "step": "one reduced-operator application K x"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "sweep2d_kernel<double, RLMDG>", "kernel_ms": sweep_ms,
+                     "bytes_per_launch": nbytes},
+    }
+    if not args.no_solve:
+        res = {}
+        xs = torch.zeros(N, dtype=torch.float64, device=dev)
+        phi = torch.zeros(N, dtype=torch.float64, device=dev)
+        for mode in ("fp64", "mixed"):
+            xs.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = lmdg.lmdg_solve(h, scheme, mode, 1e-8, 60, 20000, xs, phi, raise_on_nonconvergence=False)
+            torch.cuda.synchronize()
+            info["wall_s"] = time.perf_counter() - t0
+            res[mode] = info
+        out["solve"] = {"tol": 1e-8, "restart": 60, **res}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    solver.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

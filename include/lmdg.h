@@ -1,0 +1,192 @@
+/*
+ * lmdg.h - C ABI of the MI355X (gfx950) low-memory S_N-DG transport solver.
+ *
+ * The library solves the scaled steady linear transport equation
+ *     Omega . grad Psi + (sigma_s/eps + eps sigma_a) Psi = (sigma_s/eps) Psibar + eps q
+ * (Sun & Hauck, "Low-memory, discrete ordinates, discontinuous Galerkin methods for
+ * radiative transport", Sec. 1, eq-main) on a uniform Cartesian mesh of
+ * [0, length_0] x [0, length_1] with bilinear (Q^1) upwind DG in space and a discrete
+ * ordinates set in angle (Sec. 2.1), for three spaces:
+ *   LMDG_SCHEME_STD    standard S_N-DG                       (Sec. 2.1, eq-sndg-scheme)
+ *   LMDG_SCHEME_LMDG   low-memory space V_{h,0} + D_{h,1}    (Sec. 3.2, eq-gene-scheme)
+ *   LMDG_SCHEME_RLMDG  low-memory space with upwind slope reconstruction
+ *                                                            (Sec. 3.3, eq-rlmdg-vari)
+ * Each is solved through the paper's dimension-reduced system with a Krylov method
+ * (GMRES here); the operator of that system is applied with transport sweeps.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an int status (LMDG_OK on success).  No C++ exception and
+ *   no abort crosses this boundary.  lmdg_status_string() names a status; the handle
+ *   keeps a longer message for the last failure (lmdg_last_error()).
+ * - Cells are numbered x fastest: p = i + n_0 * j (2D).
+ * - A "moment vector" holds Legendre moments of a Q^1 field on every cell, moment
+ *   major: v[r * n_cells + p], r = 0..n_P-1 with the basis 1, xi, eta, xi*eta
+ *   (xi = 2(x - x_c)/h_0, eta = 2(y - y_c)/h_1), n_P = 4 in 2D.  Krylov vectors,
+ *   right-hand sides and scalar fluxes all use this layout (n_P * n_cells doubles).
+ *   For LMDG/RLMDG moment 0 is X_0 (per-cell scalar-flux average) and moments 1..3
+ *   are X_1 of Sec. 3.2 Step 3.
+ * - Pointers documented as "device" must point to memory of the handle's GPU
+ *   (e.g. torch CUDA tensors); "host" pointers are ordinary CPU memory.  The caller
+ *   owns every array it passes; the handle owns its internal workspaces.
+ * - `stream` is a hipStream_t (NULL = the default stream).  All device work of a
+ *   call is enqueued on it; calls that report iteration counts or residuals
+ *   synchronise it before returning.
+ * - A handle is not re-entrant: calls on one handle must not overlap.
+ * - Supported: dim = 2, vacuum inflow (alpha = 0), per-cell constant cross
+ *   sections, eps and sources.  Anything else returns LMDG_UNSUPPORTED.
+ */
+#ifndef LMDG_H
+#define LMDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LMDG_OK 0
+#define LMDG_INVALID_ARG 1
+#define LMDG_NOT_CONVERGED 2
+#define LMDG_NONFINITE 3
+#define LMDG_HIP_ERROR 4
+#define LMDG_UNSUPPORTED 5
+
+#define LMDG_SCHEME_STD 0
+#define LMDG_SCHEME_LMDG 1
+#define LMDG_SCHEME_RLMDG 2
+
+/* arithmetic of the sweeps (local solves and quadrature sums); reductions into
+ * moment vectors, B_11, GMRES and residuals are always FP64 */
+#define LMDG_PREC_FP64 0
+#define LMDG_PREC_FP32 1
+
+/* solve modes */
+#define LMDG_MODE_FP64 0   /* FP64 sweeps inside FP64 GMRES */
+#define LMDG_MODE_MIXED 1  /* FP32 sweeps inside FP64 GMRES, FP64 iterative refinement */
+
+typedef struct lmdg_handle lmdg_t;
+
+typedef struct lmdg_info {
+  int iterations;           /* total inner GMRES iterations (operator applications) */
+  int restarts;             /* GMRES restart cycles */
+  int ir_passes;            /* outer refinement passes (MIXED), 1 for FP64 */
+  int converged;            /* 1 when the true relative residual met tol */
+  double rel_residual;      /* ||b - K x||_2 / ||b||_2 with the FP64 operator */
+  double time_total_ms;     /* wall time of the call */
+  double time_apply_ms;     /* time in operator applications (event timed) */
+} lmdg_info;
+
+/* Message for a status code (static storage). */
+const char* lmdg_status_string(int status);
+
+/* Message of the last failure on this handle (static storage if h is NULL). */
+const char* lmdg_last_error(const lmdg_t* h);
+
+/*
+ * Level-symmetric LQ_N quadrature (host).  Sec. 2.1, eq-polyquad: positive weights,
+ * exact for polynomials of degree <= 2 in Omega.  Levels mu_i^2 = mu_1^2 +
+ * (i-1) 2(1-3 mu_1^2)/(N-2); octant points (mu_i, mu_j, mu_k), i+j+k = N/2+2;
+ * permutation classes share a weight solving the even-moment equations (minimum
+ * norm for N = 16); mu_1 makes the next even moment exact.  dim 2 keeps the
+ * Omega_z > 0 hemisphere projected to (Omega_x, Omega_y), weights renormalised.
+ *   order    N in {4, 6, 8, 12, 16}
+ *   capacity size of the caller's arrays in directions (>= N(N+2)/2 for dim 2,
+ *            N(N+2) for dim 3)
+ *   n_dir    out: number of directions
+ *   omega    out, host, n_dir x dim row-major
+ *   w        out, host, n_dir, sum 1
+ * Errors: INVALID_ARG for other orders/dims or too small capacity.
+ */
+int lmdg_quadrature_level_symmetric(int dim, int order, int capacity, int* n_dir,
+                                    double* omega, double* w);
+
+/*
+ * Create a handle on the current HIP device for a uniform mesh of n[0] x n[1] cells
+ * of [0, length[0]] x [0, length[1]] and the quadrature (omega, w) (host arrays,
+ * copied).  The quadrature must satisfy eq-polyquad (i)-(iii) to 1e-12, have
+ * positive weights and no zero component (the upwind direction along every axis
+ * must be defined), and at most 64 directions per quadrant.
+ * Errors: INVALID_ARG (NULL pointers, sizes < 1, quadrature violations),
+ *         UNSUPPORTED (dim != 2), HIP_ERROR (allocation).
+ */
+int lmdg_create(int dim, const int64_t* n, const double* length, int n_dir,
+                const double* omega, const double* w, lmdg_t** out);
+
+void lmdg_destroy(lmdg_t* h);
+
+/*
+ * Cross sections and source (device arrays, n_cells each, copied into the handle):
+ * sigma_s >= 0, sigma_a >= 0, eps > 0 per cell (eq-main; a per-cell eps describes a
+ * multiscale medium), q = per-cell constant source.  sigma_a may be 0 only if
+ * sigma_s > 0 in the same cell is not required by the algebra but the paper's
+ * analysis assumes sigma_a >= delta_a > 0.  alpha must be NULL (vacuum inflow).
+ * Errors: INVALID_ARG (NULL, negative or non-finite values, eps <= 0),
+ *         UNSUPPORTED (alpha != NULL).
+ */
+int lmdg_set_materials(lmdg_t* h, const double* sigma_s, const double* sigma_a,
+                       const double* eps, const double* q, const double* alpha,
+                       void* stream);
+
+/*
+ * One sweep of all directions followed by the angular reductions (Sec. 2.1.1 for
+ * STD, eq-nonrec-block for LMDG, Sec. 3.3.2 for RLMDG), without the identity/B_11
+ * part of the reduced operator.  Solves, per direction, L_l Psi_l = S_l with
+ *   S = M x + Q            (STD; x, Q optional)
+ *   S = M_0 x_0 + L_01 Sigma^T x_1 + Q~_0     (LMDG, RLMDG; L~_00 for RLMDG)
+ * and returns the per-cell sums over directions (device, out_moments x n_cells):
+ *   STD:   n_P moments of P Psi
+ *   LMDG:  [P_0 Psi ; Sigma L_10 Psi (xi, eta, xi*eta rows)]
+ *   RLMDG: [P_0 Psi ; Sigma (L_10 + L_11 R) Psi (3 rows) ; P_1 R Psi (xi, eta)]
+ *   x        device moment vector or NULL (= 0)
+ *   use_q    1 adds the source Q, 0 omits it
+ *   out      device, n_out * n_cells doubles (n_out = 4, 4, 6 for STD, LMDG, RLMDG)
+ *   psi      optional device output of the angular flux (cell averages for
+ *            LMDG/RLMDG, all n_P moments for STD), layout psi[(l*m + r)*n_cells + p]
+ *            with l the caller's direction index, m = 1 (LMDG/RLMDG) or n_P (STD);
+ *            FP64, NULL to skip.
+ */
+int lmdg_sweep(lmdg_t* h, int scheme, int prec, const double* x, int use_q,
+               double* out, double* psi, void* stream);
+
+/* K x of the reduced system (device moment vectors).  Unit of the
+ * cell-direction-updates/s metric: one call = n_cells * n_dir updates. */
+int lmdg_apply(lmdg_t* h, int scheme, int prec, const double* x, double* y, void* stream);
+
+/* Right-hand side b of the reduced system (device moment vector). */
+int lmdg_rhs(lmdg_t* h, int scheme, int prec, double* b, void* stream);
+
+/* Step 4 / eq-sndg-final-sweep: scalar-flux moments phi (device moment vector)
+ * from a solution x of the reduced system; psi as in lmdg_sweep (nullable). */
+int lmdg_recover(lmdg_t* h, int scheme, int prec, const double* x, double* phi,
+                 double* psi, void* stream);
+
+/*
+ * Solve K x = b with restarted GMRES(restart) from x0 (device, NULL = 0) until the
+ * true FP64 relative residual ||b - K x|| / ||b|| <= tol, then recover the scalar
+ * flux.  mode FP64: FP64 sweeps.  mode MIXED: an FP64 refinement loop around inner
+ * GMRES solves that use FP32 sweeps; the FP64 operator defines the residual.
+ *   x_out    device moment vector (solution of the reduced system)
+ *   phi_out  device moment vector (scalar flux), NULL to skip
+ *   info     host, filled also when NOT_CONVERGED is returned
+ * Errors: INVALID_ARG (tol <= 0, restart < 1, max_iter < 1), NOT_CONVERGED.
+ */
+int lmdg_solve(lmdg_t* h, int scheme, int mode, double tol, int restart, int max_iter,
+               const double* x0, double* x_out, double* phi_out, lmdg_info* info,
+               void* stream);
+
+/*
+ * Kernel timing for measurement: while enabled, every sweep-kernel launch of this
+ * handle is bracketed by HIP events recorded on its launch stream.
+ * lmdg_sweep_kernel_time() waits for the recorded events and returns the summed
+ * kernel time in milliseconds and the number of launches since the last query
+ * (or since enabling), then clears the record.  Host pointers.
+ */
+int lmdg_profile(lmdg_t* h, int enable);
+int lmdg_sweep_kernel_time(lmdg_t* h, double* total_ms, int* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LMDG_H */

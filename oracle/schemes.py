@@ -132,34 +132,33 @@ class Problem:
         lin = {k: exps.index(tuple(1 if m == k else 0 for m in range(d))) for k in range(d)}
         rows, cols, vals = [], [], []
         r_alpha = np.zeros((nd, nx, n_p - 1))
+        cells = np.arange(nx)
         for l in range(nd):
             om = self.omega[l]
             for k in range(d):
                 hk = mesh.h[k]
-                upwind_side = -1 if om[k] > 0 else 1  # s_k = -sign(Omega_k)
+                upwind_side = -1 if om[k] > 0 else 1          # s_k = -sign(Omega_k)
+                sgn = 1.0 if upwind_side == -1 else -1.0      # delta^- = (u_i - u_up)/h, delta^+ = (u_up - u_i)/h
                 nb = mesh.neighbor(k, upwind_side)
-                row = lambda p: (l * nx + p) * (n_p - 1) + (lin[k] - 1)
-                for p in range(nx):
-                    if nb[p] >= 0:
-                        # delta^- = (u_i - u_{i-1})/h ; delta^+ = (u_{i+1} - u_i)/h
-                        sgn = 1.0 if upwind_side == -1 else -1.0
-                        coef = (hk / 2.0) / hk
-                        rows += [row(p), row(p)]
-                        cols += [l * nx + p, l * nx + nb[p]]
-                        vals += [sgn * coef, -sgn * coef]
-                    else:
-                        # boundary cell: difference with alpha at the inflow face midpoint
-                        sgn = 1.0 if upwind_side == -1 else -1.0
-                        coef = (hk / 2.0) / (hk / 2.0)
-                        rows.append(row(p))
-                        cols.append(l * nx + p)
-                        vals.append(sgn * coef)
-                        if self.alpha is not None:
-                            x = mesh.centers[p].copy()
-                            x[k] = 0.0 if upwind_side == -1 else mesh.length[k]
-                            a = float(self.alpha(x[None, :], om)[0])
-                            r_alpha[l, p, lin[k] - 1] += -sgn * coef * a
-        R1 = sp.csr_matrix((vals, (rows, cols)), shape=(nd * nx * (n_p - 1), nd * nx))
+                row = (l * nx + cells) * (n_p - 1) + (lin[k] - 1)
+                inner = nb >= 0
+                coef = (hk / 2.0) / hk                         # interior: difference over h
+                rows += [row[inner], row[inner]]
+                cols += [l * nx + cells[inner], l * nx + nb[inner]]
+                vals += [np.full(inner.sum(), sgn * coef), np.full(inner.sum(), -sgn * coef)]
+                bnd = ~inner
+                coef_b = (hk / 2.0) / (hk / 2.0)               # inflow cell: difference over h/2
+                rows.append(row[bnd])
+                cols.append(l * nx + cells[bnd])
+                vals.append(np.full(bnd.sum(), sgn * coef_b))
+                if self.alpha is not None and bnd.any():
+                    # alpha at the midpoint of the inflow face of each boundary cell
+                    x = mesh.centers[bnd].copy()
+                    x[:, k] = 0.0 if upwind_side == -1 else mesh.length[k]
+                    a = np.asarray(self.alpha(x, om), dtype=float)
+                    r_alpha[l, cells[bnd], lin[k] - 1] += -sgn * coef_b * a
+        R1 = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                           shape=(nd * nx * (n_p - 1), nd * nx))
         return R1, r_alpha.ravel()
 
 
@@ -333,13 +332,20 @@ class LowMemoryReduced:
         self.B11_lu = spla.splu(self.B11)
         if reconstructed:
             R1, r_alpha = prob.reconstruction()
-            aniso = sp.identity(nd * n1, format="csr") - self.St @ self.P1
             self.R = R1
-            self.Lt00 = (self.L00 + self.L01 @ R1).tocsc()                 # L~_00
-            self.Lt10 = self.L10 + self.L11 @ aniso @ R1                     # L~_10
-            self.Qt0 = self.Q0 - self.L01 @ (aniso @ r_alpha)                # Q~_0
-            self.Qt1 = self.Q1 - self.L11 @ (aniso @ r_alpha)                # Q~_1
-            self.G = (self.S @ self.Lt10 + self.B11 @ self.P1 @ R1).tocsr()
+            # (I - Sigma^T P_1) is dense in angle; it is applied by distributing the
+            # products so that no n_dir^2 operator is formed:
+            #   L_11 (I - Sigma^T P_1) R = L_11 R - (L_11 Sigma^T)(P_1 R)
+            P1R = (self.P1 @ R1).tocsr()
+            P1r = self.P1 @ r_alpha
+            L11St = (self.L11 @ self.St).tocsr()
+            self.Lt00 = (self.L00 + self.L01 @ R1).tocsc()                       # L~_00
+            self.Qt0 = self.Q0 - self.L01 @ r_alpha + self.L01 @ (self.St @ P1r)  # Q~_0
+            self.Qt1 = self.Q1 - self.L11 @ r_alpha + L11St @ P1r                 # Q~_1
+            # Step 3 second block row: G = Sigma L~_10 + B_11 P_1 R with
+            # L~_10 = L_10 + L_11 (I - Sigma^T P_1) R
+            S_Lt10 = self.S @ self.L10 + self.S @ (self.L11 @ R1) - (self.S @ L11St) @ P1R
+            self.G = (S_Lt10 + self.B11 @ P1R).tocsr()
         else:
             self.R = None
             self.Lt00 = self.L00.tocsc()

@@ -1,0 +1,742 @@
+// Host side of the C ABI: quadrature generation, handle set-up, validation, and the
+// FP64 GMRES / iterative-refinement drivers around the device kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using lmdg::check_hip;
+using lmdg::set_error;
+
+namespace lmdg {
+
+int set_error(lmdg_handle* h, int status, const std::string& msg) {
+  if (h) h->last_error = msg;
+  return status;
+}
+
+int check_hip(lmdg_handle* h, hipError_t e, const char* what) {
+  if (e == hipSuccess) return LMDG_OK;
+  return set_error(h, LMDG_HIP_ERROR, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+// ------------------------------------------------------------------ quadrature
+// Small dense solve with partial pivoting (n <= 16), in place; returns false if singular.
+bool dense_solve(std::vector<double>& A, std::vector<double>& b, int n) {
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A[i * n + k]) > std::fabs(A[piv * n + k])) piv = i;
+    if (A[piv * n + k] == 0.0) return false;
+    if (piv != k) {
+      for (int j = 0; j < n; ++j) std::swap(A[k * n + j], A[piv * n + j]);
+      std::swap(b[k], b[piv]);
+    }
+    for (int i = k + 1; i < n; ++i) {
+      const double f = A[i * n + k] / A[k * n + k];
+      for (int j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+      b[i] -= f * b[k];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    double acc = b[k];
+    for (int j = k + 1; j < n; ++j) acc -= A[k * n + j] * b[j];
+    b[k] = acc / A[k * n + k];
+  }
+  return true;
+}
+
+struct Octant {
+  std::vector<double> mu;           // levels
+  std::vector<int> pi, pj, pk;      // level indices of the points
+  std::vector<int> cls;             // class of each point
+  int ncls = 0;
+};
+
+Octant octant(int order, double mu1) {
+  Octant o;
+  const int nl = order / 2;
+  const double step = 2.0 * (1.0 - 3.0 * mu1 * mu1) / (order - 2);
+  for (int i = 0; i < nl; ++i) o.mu.push_back(std::sqrt(mu1 * mu1 + step * i));
+  std::vector<std::vector<int>> keys;
+  for (int i = 1; i <= nl; ++i)
+    for (int j = 1; j <= nl; ++j) {
+      const int k = nl + 2 - i - j;
+      if (k < 1 || k > nl) continue;
+      std::vector<int> key = {i, j, k};
+      std::sort(key.begin(), key.end());
+      int c = (int)(std::find(keys.begin(), keys.end(), key) - keys.begin());
+      if (c == (int)keys.size()) keys.push_back(key);
+      o.pi.push_back(i - 1);
+      o.pj.push_back(j - 1);
+      o.pk.push_back(k - 1);
+      o.cls.push_back(c);
+    }
+  // classes numbered in sorted order of their index triples
+  std::vector<int> perm(keys.size());
+  for (size_t c = 0; c < keys.size(); ++c) perm[c] = (int)c;
+  std::sort(perm.begin(), perm.end(), [&](int a, int b) { return keys[a] < keys[b]; });
+  std::vector<int> rank(keys.size());
+  for (size_t c = 0; c < perm.size(); ++c) rank[perm[c]] = (int)c;
+  for (auto& c : o.cls) c = rank[c];
+  o.ncls = (int)keys.size();
+  return o;
+}
+
+// Even moments imposed on the class weights, and the one used to pick mu_1.
+void moments(int order, int ncls, std::vector<int>& imposed, int& check) {
+  imposed = {0};
+  const int top = (order == 16) ? 7 : ncls;  // N = 16: 8 classes, rank-7 system
+  for (int m = 2; m <= top; ++m) imposed.push_back(m);
+  check = std::max(imposed.back() + 1, 2);
+}
+
+// Minimum-norm class weights w = A^T (A A^T)^{-1} b of sum_octant w mu_z^(2m) = 1/(8(2m+1)).
+bool class_weights(int order, double mu1, std::vector<double>& wc, Octant& o) {
+  o = octant(order, mu1);
+  std::vector<int> imp;
+  int check;
+  moments(order, o.ncls, imp, check);
+  const int ne = (int)imp.size(), nc = o.ncls;
+  std::vector<double> A(ne * nc, 0.0), b(ne);
+  for (size_t p = 0; p < o.cls.size(); ++p)
+    for (int e = 0; e < ne; ++e) A[e * nc + o.cls[p]] += std::pow(o.mu[o.pk[p]], 2 * imp[e]);
+  for (int e = 0; e < ne; ++e) b[e] = 1.0 / (8.0 * (2 * imp[e] + 1));
+  std::vector<double> G(ne * ne, 0.0);
+  for (int a = 0; a < ne; ++a)
+    for (int c = 0; c < ne; ++c)
+      for (int k = 0; k < nc; ++k) G[a * ne + c] += A[a * nc + k] * A[c * nc + k];
+  if (!dense_solve(G, b, ne)) return false;
+  wc.assign(nc, 0.0);
+  for (int k = 0; k < nc; ++k)
+    for (int e = 0; e < ne; ++e) wc[k] += A[e * nc + k] * b[e];
+  return true;
+}
+
+double extra_moment_residual(int order, double mu1) {
+  std::vector<double> wc;
+  Octant o;
+  if (!class_weights(order, mu1, wc, o)) return NAN;
+  std::vector<int> imp;
+  int check;
+  moments(order, o.ncls, imp, check);
+  double acc = 0;
+  for (size_t p = 0; p < o.cls.size(); ++p) acc += wc[o.cls[p]] * std::pow(o.mu[o.pk[p]], 2 * check);
+  return 8.0 * acc - 1.0 / (2 * check + 1);
+}
+
+double mu1_guess(int order) {
+  switch (order) {
+    case 4: return 0.3500212;
+    case 6: return 0.2666355;
+    case 8: return 0.2182179;
+    case 12: return 0.1672126;
+    case 16: return 0.1389568;
+    default: return 0.0;
+  }
+}
+
+}  // namespace
+}  // namespace lmdg
+
+extern "C" {
+
+const char* lmdg_status_string(int status) {
+  switch (status) {
+    case LMDG_OK: return "ok";
+    case LMDG_INVALID_ARG: return "invalid argument";
+    case LMDG_NOT_CONVERGED: return "not converged";
+    case LMDG_NONFINITE: return "non-finite value";
+    case LMDG_HIP_ERROR: return "HIP runtime error";
+    case LMDG_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+  }
+}
+
+const char* lmdg_last_error(const lmdg_t* h) {
+  if (!h) return "no handle";
+  return h->last_error.c_str();
+}
+
+int lmdg_quadrature_level_symmetric(int dim, int order, int capacity, int* n_dir, double* omega, double* w) {
+  using namespace lmdg;
+  if ((dim != 2 && dim != 3) || mu1_guess(order) == 0.0 || !n_dir || !omega || !w) return LMDG_INVALID_ARG;
+  const int count = dim == 2 ? order * (order + 2) / 2 : order * (order + 2);
+  if (capacity < count) return LMDG_INVALID_ARG;
+  // bisection on the first non-imposed even moment, bracket +-10% around the table value
+  double lo = 0.9 * mu1_guess(order), hi = 1.1 * mu1_guess(order);
+  double flo = extra_moment_residual(order, lo), fhi = extra_moment_residual(order, hi);
+  if (!(flo * fhi < 0)) return LMDG_INVALID_ARG;
+  for (int it = 0; it < 200 && hi - lo > 1e-17; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    const double fm = extra_moment_residual(order, mid);
+    if (fm == 0.0) { lo = hi = mid; break; }
+    if ((fm < 0) == (flo < 0)) { lo = mid; flo = fm; } else { hi = mid; }
+  }
+  const double mu1 = 0.5 * (lo + hi);
+  std::vector<double> wc;
+  Octant o;
+  if (!class_weights(order, mu1, wc, o)) return LMDG_INVALID_ARG;
+  for (double v : wc)
+    if (!(v > 0)) return LMDG_INVALID_ARG;
+  const int npts = (int)o.cls.size();
+  const int noct = 1 << dim;
+  double total = 0;
+  int k = 0;
+  for (int oc = 0; oc < noct; ++oc)
+    for (int p = 0; p < npts; ++p) {
+      const double pt[3] = {o.mu[o.pi[p]], o.mu[o.pj[p]], o.mu[o.pk[p]]};
+      for (int a = 0; a < dim; ++a) omega[k * dim + a] = ((oc >> a) & 1) ? -pt[a] : pt[a];
+      w[k] = wc[o.cls[p]];
+      total += w[k];
+      ++k;
+    }
+  for (int i = 0; i < k; ++i) w[i] /= total;
+  *n_dir = k;
+  return LMDG_OK;
+}
+
+int lmdg_create(int dim, const int64_t* n, const double* length, int n_dir, const double* omega,
+                const double* w, lmdg_t** out) {
+  using namespace lmdg;
+  if (!out || !n || !length || !omega || !w) return LMDG_INVALID_ARG;
+  *out = nullptr;
+  if (dim != 2) return LMDG_UNSUPPORTED;
+  if (n[0] < 1 || n[1] < 1 || !(length[0] > 0) || !(length[1] > 0) || n_dir < 1) return LMDG_INVALID_ARG;
+  if (n[0] > (1 << 20) || n[1] > (1 << 20) || n[0] * n[1] > (1ll << 31)) return LMDG_INVALID_ARG;
+  // eq-polyquad (i)-(iii), positive weights, no zero component
+  double s0 = 0, s1[2] = {0, 0}, s2[2][2] = {{0, 0}, {0, 0}};
+  for (int l = 0; l < n_dir; ++l) {
+    if (!(w[l] > 0) || !std::isfinite(w[l])) return LMDG_INVALID_ARG;
+    for (int a = 0; a < 2; ++a)
+      if (!std::isfinite(omega[2 * l + a]) || omega[2 * l + a] == 0.0) return LMDG_INVALID_ARG;
+    s0 += w[l];
+    for (int a = 0; a < 2; ++a) {
+      s1[a] += w[l] * omega[2 * l + a];
+      for (int b = 0; b < 2; ++b) s2[a][b] += w[l] * omega[2 * l + a] * omega[2 * l + b];
+    }
+  }
+  const double tq = 1e-12;
+  if (std::fabs(s0 - 1) > tq) return LMDG_INVALID_ARG;
+  for (int a = 0; a < 2; ++a) {
+    if (std::fabs(s1[a]) > tq) return LMDG_INVALID_ARG;
+    for (int b = 0; b < 2; ++b)
+      if (std::fabs(s2[a][b] - (a == b ? 1.0 / 3.0 : 0.0)) > tq) return LMDG_INVALID_ARG;
+  }
+  lmdg_handle* h = new (std::nothrow) lmdg_handle();
+  if (!h) return LMDG_HIP_ERROR;
+  h->dim = 2;
+  for (int a = 0; a < 2; ++a) {
+    h->n[a] = n[a];
+    h->len[a] = length[a];
+    h->h[a] = length[a] / (double)n[a];
+  }
+  h->area = h->h[0] * h->h[1];
+  h->ncell = n[0] * n[1];
+  h->ndir = n_dir;
+  h->omega.assign(omega, omega + 2 * n_dir);
+  h->w.assign(w, w + n_dir);
+  // quadrant q: bit 0 set when Omega_x < 0, bit 1 when Omega_y < 0
+  std::vector<int> byq[4];
+  for (int l = 0; l < n_dir; ++l) {
+    const int q = (omega[2 * l] < 0 ? 1 : 0) | (omega[2 * l + 1] < 0 ? 2 : 0);
+    byq[q].push_back(l);
+  }
+  size_t dmax = 1;
+  for (auto& v : byq) dmax = std::max(dmax, v.size());
+  if (dmax > (size_t)kMaxSlots) {
+    delete h;
+    return LMDG_INVALID_ARG;
+  }
+  h->dslots = (int)((dmax + 3) / 4 * 4);
+  h->waves = h->dslots / 4;
+  h->nstrips = (int)((n[1] + kRows - 1) / kRows);
+  std::vector<double> tab(4 * h->dslots * kDirStride, 0.0);
+  h->slot_dir.assign(4 * h->dslots, -1);
+  for (int q = 0; q < 4; ++q) {
+    // padding slots copy a real direction of the quadrant (or the quadrant's sign
+    // pattern) with zero weight, so they compute finite values and contribute nothing
+    double ox = (q & 1) ? -0.5 : 0.5, oy = (q & 2) ? -0.5 : 0.5;
+    if (!byq[q].empty()) {
+      ox = omega[2 * byq[q][0]];
+      oy = omega[2 * byq[q][0] + 1];
+    }
+    for (int sl = 0; sl < h->dslots; ++sl) {
+      double* e = &tab[(q * h->dslots + sl) * kDirStride];
+      if (sl < (int)byq[q].size()) {
+        const int l = byq[q][sl];
+        e[0] = omega[2 * l];
+        e[1] = omega[2 * l + 1];
+        e[2] = w[l];
+        e[3] = l;
+        h->slot_dir[q * h->dslots + sl] = l;
+      } else {
+        e[0] = ox;
+        e[1] = oy;
+        e[2] = 0.0;
+        e[3] = -1;
+      }
+    }
+  }
+  for (int l = 0; l < n_dir; ++l)
+    for (int a = 0; a < 2; ++a) {
+      const double o = omega[2 * l + a];
+      if (o > 0) h->cplus[a] += w[l] * o; else h->cminus[a] += w[l] * (-o);
+    }
+  for (int l = 0; l < n_dir; ++l) {
+    const int q = (omega[2 * l] < 0 ? 1 : 0) | (omega[2 * l + 1] < 0 ? 2 : 0);
+    h->qw[q] += w[l];
+    h->qax[q] += w[l] * std::fabs(omega[2 * l]);
+    h->qay[q] += w[l] * std::fabs(omega[2 * l + 1]);
+  }
+  int dev = 0;
+  hipGetDevice(&dev);
+  h->device = dev;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+    h->n_cu = prop.multiProcessorCount;
+  const long long nc = h->ncell;
+  int st = LMDG_OK;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (st != LMDG_OK) return;
+    st = check_hip(h, hipMalloc(p, std::max<size_t>(bytes, 8)), "hipMalloc");
+  };
+  alloc((void**)&h->d_dirs, tab.size() * sizeof(double));
+  alloc((void**)&h->ws.part, (size_t)4 * 6 * nc * sizeof(double));
+  h->ws.edge_bytes = (size_t)4 * h->nstrips * n[0] * 3 * h->dslots * sizeof(double);
+  alloc(&h->ws.edge, h->ws.edge_bytes);
+  alloc((void**)&h->ws.prog, (size_t)4 * h->nstrips * sizeof(unsigned long long));
+  alloc((void**)&h->ws.ticket, sizeof(unsigned int));
+  alloc((void**)&h->ws.err, sizeof(int));
+  alloc((void**)&h->ws.vec, (size_t)kScratchVecs * 4 * nc * sizeof(double));
+  if (st == LMDG_OK) st = check_hip(h, hipMemcpy(h->d_dirs, tab.data(), tab.size() * sizeof(double),
+                                                 hipMemcpyHostToDevice), "copy directions");
+  if (st == LMDG_OK) st = check_hip(h, hipMemset(h->ws.prog, 0, (size_t)4 * h->nstrips * 8), "clear flags");
+  if (st == LMDG_OK) st = check_hip(h, hipMemset(h->ws.ticket, 0, sizeof(unsigned int)), "clear ticket");
+  if (st == LMDG_OK) st = check_hip(h, hipMemset(h->ws.err, 0, sizeof(int)), "clear error flag");
+  if (st == LMDG_OK) st = check_hip(h, hipDeviceSynchronize(), "create");
+  if (st != LMDG_OK) {
+    lmdg_destroy(h);
+    return st;
+  }
+  *out = h;
+  return LMDG_OK;
+}
+
+void lmdg_destroy(lmdg_t* h) {
+  if (!h) return;
+  hipDeviceSynchronize();
+  void* ptrs[] = {h->d_dirs, h->d_sigtA, h->d_scatA, h->d_absA, h->d_qA, h->ws.part, h->ws.edge,
+                  h->ws.prog, h->ws.ticket, h->ws.err, h->ws.vec, h->d_krylov, h->d_small};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  if (h->h_small) hipHostFree(h->h_small);
+  for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
+  delete h;
+}
+
+int lmdg_set_materials(lmdg_t* h, const double* sigma_s, const double* sigma_a, const double* eps,
+                       const double* q, const double* alpha, void* stream) {
+  if (!h) return LMDG_INVALID_ARG;
+  if (!sigma_s || !sigma_a || !eps || !q) return set_error(h, LMDG_INVALID_ARG, "NULL material array");
+  if (alpha) return set_error(h, LMDG_UNSUPPORTED, "only vacuum inflow (alpha = NULL) is supported");
+  hipStream_t st = (hipStream_t)stream;
+  const long long nc = h->ncell;
+  std::vector<double> ss(nc), sa(nc), ep(nc), qq(nc);
+  int rc = LMDG_OK;
+  const double* src[4] = {sigma_s, sigma_a, eps, q};
+  std::vector<double>* dst[4] = {&ss, &sa, &ep, &qq};
+  for (int k = 0; k < 4 && rc == LMDG_OK; ++k)
+    rc = check_hip(h, hipMemcpyAsync(dst[k]->data(), src[k], nc * sizeof(double), hipMemcpyDeviceToHost, st),
+                   "read materials");
+  if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "read materials");
+  if (rc != LMDG_OK) return rc;
+  std::vector<double> sigtA(nc), scatA(nc), absA(nc), qA(nc);
+  for (long long p = 0; p < nc; ++p) {
+    if (!std::isfinite(ss[p]) || !std::isfinite(sa[p]) || !std::isfinite(ep[p]) || !std::isfinite(qq[p]))
+      return set_error(h, LMDG_NONFINITE, "non-finite material value at cell " + std::to_string(p));
+    if (ss[p] < 0 || sa[p] < 0 || !(ep[p] > 0))
+      return set_error(h, LMDG_INVALID_ARG, "sigma < 0 or eps <= 0 at cell " + std::to_string(p));
+    // eq-main: sigma_t = sigma_s/eps + eps sigma_a, scattering sigma_s/eps, source eps q
+    sigtA[p] = (ss[p] / ep[p] + ep[p] * sa[p]) * h->area;
+    scatA[p] = ss[p] / ep[p] * h->area;
+    absA[p] = ep[p] * sa[p] * h->area;
+    qA[p] = ep[p] * qq[p] * h->area;
+  }
+  double** tgt[4] = {&h->d_sigtA, &h->d_scatA, &h->d_absA, &h->d_qA};
+  std::vector<double>* vals[4] = {&sigtA, &scatA, &absA, &qA};
+  for (int k = 0; k < 4 && rc == LMDG_OK; ++k) {
+    if (!*tgt[k]) rc = check_hip(h, hipMalloc((void**)tgt[k], nc * sizeof(double)), "hipMalloc materials");
+    if (rc == LMDG_OK)
+      rc = check_hip(h, hipMemcpyAsync(*tgt[k], vals[k]->data(), nc * sizeof(double), hipMemcpyHostToDevice, st),
+                     "write materials");
+  }
+  if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "write materials");
+  if (rc == LMDG_OK) h->have_mat = true;
+  return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+int check_call(lmdg_t* h, int scheme, int prec) {
+  if (!h) return LMDG_INVALID_ARG;
+  if (scheme < LMDG_SCHEME_STD || scheme > LMDG_SCHEME_RLMDG)
+    return set_error(h, LMDG_INVALID_ARG, "unknown scheme");
+  if (prec != LMDG_PREC_FP64 && prec != LMDG_PREC_FP32) return set_error(h, LMDG_INVALID_ARG, "unknown precision");
+  if (!h->have_mat) return set_error(h, LMDG_INVALID_ARG, "materials not set");
+  return LMDG_OK;
+}
+
+// K x in the defect form (see lm_source / std_source): the same operator as
+// eq-nonrec-block / eq-sndg-phi, arranged so that no O(sigma_s/eps) terms cancel
+// after the sweep; this is what keeps FP32 sweeps usable at small eps.
+int apply_op(lmdg_t* h, int scheme, int prec, const double* x, double* y, hipStream_t st) {
+  int rc = lmdg::launch_sweep(h, scheme, prec, x, false, nullptr, st, true);
+  if (rc != LMDG_OK) return rc;
+  lmdg::launch_combine(h, scheme, prec, lmdg::kApplyDefect, x, y, st);
+  return check_hip(h, hipGetLastError(), "combine");
+}
+
+int read_error_flag(lmdg_t* h, hipStream_t st) {
+  int flag = 0;
+  int rc = check_hip(h, hipMemcpyAsync(&flag, h->ws.err, sizeof(int), hipMemcpyDeviceToHost, st), "read flag");
+  if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "read flag");
+  if (rc == LMDG_OK && flag) {
+    hipMemsetAsync(h->ws.err, 0, sizeof(int), st);
+    return set_error(h, LMDG_HIP_ERROR, "sweep wait exceeded its spin limit");
+  }
+  return rc;
+}
+
+int ensure_small(lmdg_t* h, size_t doubles) {
+  if (h->small_doubles >= doubles) return LMDG_OK;
+  if (h->d_small) hipFree(h->d_small);
+  if (h->h_small) hipHostFree(h->h_small);
+  h->d_small = nullptr;
+  h->h_small = nullptr;
+  h->small_doubles = 0;
+  int rc = check_hip(h, hipMalloc((void**)&h->d_small, doubles * sizeof(double)), "hipMalloc small");
+  if (rc == LMDG_OK) rc = check_hip(h, hipHostMalloc((void**)&h->h_small, doubles * sizeof(double)), "pinned");
+  if (rc == LMDG_OK) h->small_doubles = doubles;
+  return rc;
+}
+
+int ensure_krylov(lmdg_t* h, size_t doubles) {
+  if (h->krylov_doubles >= doubles) return LMDG_OK;
+  if (h->d_krylov) hipFree(h->d_krylov);
+  h->d_krylov = nullptr;
+  h->krylov_doubles = 0;
+  int rc = check_hip(h, hipMalloc((void**)&h->d_krylov, doubles * sizeof(double)), "hipMalloc krylov");
+  if (rc == LMDG_OK) h->krylov_doubles = doubles;
+  return rc;
+}
+
+// Scratch layout of d_small / h_small (small_doubles entries each):
+//   [0, 256)                  GMRES coefficients (device) / both CGS passes (host)
+//   [256, 256 + nvec*parts)   partial sums of the dot kernels (device)
+//   [small_doubles - 1]       result slot of norm2 (device and host)
+size_t small_size(int restart) { return 256 + (size_t)(restart + 2) * (lmdg::dots_partials() + 4); }
+
+// ||v||_2 via the dot kernels, synchronising the stream.
+int norm2(lmdg_t* h, const double* v, long long n, double* out, hipStream_t st) {
+  double* part = h->d_small + 256;
+  double* dres = h->d_small + h->small_doubles - 1;
+  double* hres = h->h_small + h->small_doubles - 1;
+  lmdg::vec_dots(v, n, 1, v, n, part, dres, st);
+  int rc = check_hip(h, hipMemcpyAsync(hres, dres, sizeof(double), hipMemcpyDeviceToHost, st), "norm");
+  if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "norm");
+  *out = std::sqrt(std::max(0.0, *hres));
+  return rc;
+}
+
+// LMDG_VERBOSE=1 in the environment prints solver progress to stderr.
+bool verbose() {
+  static const bool v = [] {
+    const char* e = std::getenv("LMDG_VERBOSE");
+    return e && e[0] && e[0] != '0';
+  }();
+  return v;
+}
+
+struct GmresStats {
+  int iterations = 0, restarts = 0;
+  double apply_ms = 0;
+};
+
+// Restarted GMRES(m) with classical Gram-Schmidt applied twice, FP64 vectors.
+// Solves K_prec x = b starting from x (in/out); stops when the true FP64-operator
+// residual ||b - K x|| <= rtol * ||b|| (true_prec) or after max_iter applications.
+int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, double* x, double rtol, int m,
+          int max_iter, hipStream_t st, GmresStats& stats, double& relres, bool& converged) {
+  const long long N = 4 * h->ncell;
+  int rc = ensure_krylov(h, (size_t)(m + 2) * N);
+  if (rc == LMDG_OK) rc = ensure_small(h, small_size(m));
+  if (rc != LMDG_OK) return rc;
+  double* V = h->d_krylov;              // m + 1 basis vectors
+  double* r = V + (size_t)(m + 1) * N;  // residual work vector
+  double* dcoef = h->d_small;           // device coefficients (m + 2)
+  double* part = h->d_small + 256;
+  double* hc = h->h_small;
+  double bnorm;
+  rc = norm2(h, b, N, &bnorm, st);
+  if (rc != LMDG_OK) return rc;
+  converged = false;
+  relres = 1.0;
+  if (bnorm == 0.0) {
+    lmdg::vec_fill(x, 0.0, N, st);
+    converged = true;
+    relres = 0.0;
+    return check_hip(h, hipStreamSynchronize(st), "gmres");
+  }
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  auto timed_apply = [&](int p, const double* in, double* out) {
+    hipEventRecord(e0, st);
+    int r2 = apply_op(h, scheme, p, in, out, st);
+    hipEventRecord(e1, st);
+    return r2;
+  };
+  auto add_time = [&]() {
+    float ms = 0;
+    hipEventSynchronize(e1);
+    hipEventElapsedTime(&ms, e0, e1);
+    stats.apply_ms += ms;
+  };
+  while (rc == LMDG_OK) {
+    // true residual with the FP64 (or requested) operator
+    rc = timed_apply(true_prec, x, r);
+    if (rc != LMDG_OK) break;
+    lmdg::vec_axpby(r, 1.0, b, -1.0, N, st);  // r = b - K x
+    double beta;
+    rc = norm2(h, r, N, &beta, st);
+    add_time();
+    if (rc != LMDG_OK) break;
+    relres = beta / bnorm;
+    if (verbose())
+      std::fprintf(stderr, "lmdg GMRES(%d) %s: restart %d, %d its, true rel residual %.3e\n", m,
+                   prec == LMDG_PREC_FP64 ? "fp64" : "fp32", stats.restarts, stats.iterations, relres);
+    if (!std::isfinite(beta)) { rc = set_error(h, LMDG_NONFINITE, "non-finite residual"); break; }
+    if (relres <= rtol) { converged = true; break; }
+    if (stats.iterations >= max_iter) break;
+    stats.restarts += 1;
+    lmdg::vec_axpby(V, 1.0 / beta, r, 0.0, N, st);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m && stats.iterations < max_iter; ++j) {
+      double* w = V + (size_t)(j + 1) * N;
+      rc = timed_apply(prec, V + (size_t)j * N, w);
+      if (rc != LMDG_OK) break;
+      stats.iterations += 1;
+      // two passes of classical Gram-Schmidt, coefficients kept on the device
+      lmdg::vec_dots(V, N, j + 1, w, N, part, dcoef, st);
+      lmdg::vec_axpy_multi(w, V, N, j + 1, dcoef, -1.0, N, st);
+      rc = check_hip(h, hipMemcpyAsync(hc, dcoef, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, st), "h");
+      if (rc != LMDG_OK) break;
+      lmdg::vec_dots(V, N, j + 1, w, N, part, dcoef, st);
+      lmdg::vec_axpy_multi(w, V, N, j + 1, dcoef, -1.0, N, st);
+      rc = check_hip(h, hipMemcpyAsync(hc + (m + 1), dcoef, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, st),
+                     "h2");
+      if (rc != LMDG_OK) break;
+      double hn;
+      rc = norm2(h, w, N, &hn, st);  // synchronises: hc is valid afterwards
+      add_time();
+      if (rc != LMDG_OK) break;
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hc[i] + hc[m + 1 + i];
+      H[(size_t)(j + 1) * m + j] = hn;
+      for (int i = 0; i < j; ++i) {  // previous rotations
+        const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+      }
+      const double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
+      const double rr = std::hypot(a, c);
+      cs[j] = rr == 0 ? 1.0 : a / rr;
+      sn[j] = rr == 0 ? 0.0 : c / rr;
+      H[(size_t)j * m + j] = rr;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      k = j + 1;
+      if (!std::isfinite(hn)) { rc = set_error(h, LMDG_NONFINITE, "non-finite Krylov vector"); break; }
+      if (std::fabs(g[j + 1]) <= 0.5 * rtol * bnorm || hn == 0.0) break;
+      lmdg::vec_axpby(w, 1.0 / hn, w, 0.0, N, st);
+    }
+    if (rc != LMDG_OK) break;
+    // x += V y with H y = g (upper triangular)
+    for (int i = k - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int jj = i + 1; jj < k; ++jj) acc -= H[(size_t)i * m + jj] * y[jj];
+      y[i] = acc / H[(size_t)i * m + i];
+    }
+    if (k > 0) {
+      std::copy(y.begin(), y.begin() + k, hc);
+      rc = check_hip(h, hipMemcpyAsync(dcoef, hc, k * sizeof(double), hipMemcpyHostToDevice, st), "y");
+      if (rc != LMDG_OK) break;
+      lmdg::vec_axpy_multi(x, V, N, k, dcoef, 1.0, N, st);
+      rc = check_hip(h, hipStreamSynchronize(st), "update");  // hc is reused next cycle
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc == LMDG_OK) rc = read_error_flag(h, st);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lmdg_sweep(lmdg_t* h, int scheme, int prec, const double* x, int use_q, double* out, double* psi,
+               void* stream) {
+  int rc = check_call(h, scheme, prec);
+  if (rc != LMDG_OK) return rc;
+  if (!out) return set_error(h, LMDG_INVALID_ARG, "NULL output");
+  hipStream_t st = (hipStream_t)stream;
+  rc = lmdg::launch_sweep(h, scheme, prec, x, use_q != 0, psi, st);
+  if (rc != LMDG_OK) return rc;
+  lmdg::launch_sum_quadrants(h, scheme, prec, out, st);
+  return check_hip(h, hipGetLastError(), "sweep");
+}
+
+int lmdg_apply(lmdg_t* h, int scheme, int prec, const double* x, double* y, void* stream) {
+  int rc = check_call(h, scheme, prec);
+  if (rc != LMDG_OK) return rc;
+  if (!x || !y) return set_error(h, LMDG_INVALID_ARG, "NULL vector");
+  return apply_op(h, scheme, prec, x, y, (hipStream_t)stream);
+}
+
+int lmdg_rhs(lmdg_t* h, int scheme, int prec, double* b, void* stream) {
+  int rc = check_call(h, scheme, prec);
+  if (rc != LMDG_OK) return rc;
+  if (!b) return set_error(h, LMDG_INVALID_ARG, "NULL vector");
+  hipStream_t st = (hipStream_t)stream;
+  rc = lmdg::launch_sweep(h, scheme, prec, nullptr, true, nullptr, st);
+  if (rc != LMDG_OK) return rc;
+  lmdg::launch_combine(h, scheme, prec, lmdg::kRhs, nullptr, b, st);
+  return check_hip(h, hipGetLastError(), "rhs");
+}
+
+int lmdg_recover(lmdg_t* h, int scheme, int prec, const double* x, double* phi, double* psi, void* stream) {
+  int rc = check_call(h, scheme, prec);
+  if (rc != LMDG_OK) return rc;
+  if (!x || !phi) return set_error(h, LMDG_INVALID_ARG, "NULL vector");
+  hipStream_t st = (hipStream_t)stream;
+  rc = lmdg::launch_sweep(h, scheme, prec, x, true, psi, st);
+  if (rc != LMDG_OK) return rc;
+  lmdg::launch_combine(h, scheme, prec, lmdg::kRecover, x, phi, st);
+  return check_hip(h, hipGetLastError(), "recover");
+}
+
+int lmdg_solve(lmdg_t* h, int scheme, int mode, double tol, int restart, int max_iter, const double* x0,
+               double* x_out, double* phi_out, lmdg_info* info, void* stream) {
+  int rc = check_call(h, scheme, LMDG_PREC_FP64);
+  if (rc != LMDG_OK) return rc;
+  if (!x_out || !(tol > 0) || restart < 1 || restart > 250 || max_iter < 1 ||
+      (mode != LMDG_MODE_FP64 && mode != LMDG_MODE_MIXED))
+    return set_error(h, LMDG_INVALID_ARG, "bad solve arguments");
+  hipStream_t st = (hipStream_t)stream;
+  rc = ensure_small(h, small_size(restart));
+  if (rc != LMDG_OK) return rc;
+  const auto t_start = std::chrono::steady_clock::now();
+  const long long N = 4 * h->ncell;
+  double* b = h->ws.vec;
+  double* r = h->ws.vec + N;
+  double* d = h->ws.vec + 2 * N;
+  rc = lmdg_rhs(h, scheme, LMDG_PREC_FP64, b, st);
+  if (rc != LMDG_OK) return rc;
+  if (x0) lmdg::vec_copy(x_out, x0, N, st); else lmdg::vec_fill(x_out, 0.0, N, st);
+  GmresStats stats;
+  double relres = 1.0;
+  bool conv = false;
+  int passes = 0;
+  if (mode == LMDG_MODE_FP64) {
+    passes = 1;
+    rc = gmres(h, scheme, LMDG_PREC_FP64, LMDG_PREC_FP64, b, x_out, tol, restart, max_iter, st, stats, relres, conv);
+  } else {
+    // FP64 iterative refinement: r = b - K64 x; inner GMRES with FP32 sweeps on K d = r
+    double bnorm;
+    rc = norm2(h, b, N, &bnorm, st);
+    while (rc == LMDG_OK && stats.iterations < max_iter && passes < 100) {
+      rc = apply_op(h, scheme, LMDG_PREC_FP64, x_out, r, st);
+      if (rc != LMDG_OK) break;
+      lmdg::vec_axpby(r, 1.0, b, -1.0, N, st);
+      double rn;
+      rc = norm2(h, r, N, &rn, st);
+      if (rc != LMDG_OK) break;
+      relres = bnorm > 0 ? rn / bnorm : 0.0;
+      if (!std::isfinite(rn)) { rc = set_error(h, LMDG_NONFINITE, "non-finite residual"); break; }
+      if (relres <= tol) { conv = true; break; }
+      passes += 1;
+      lmdg::vec_fill(d, 0.0, N, st);
+      const double inner = std::max(1e-5, 0.5 * tol / relres);
+      bool iconv = false;
+      double irel = 1;
+      const int before = stats.iterations;
+      // max_iter bounds the cumulative count kept in stats
+      rc = gmres(h, scheme, LMDG_PREC_FP32, LMDG_PREC_FP32, r, d, std::min(inner, 0.5), restart, max_iter, st,
+                 stats, irel, iconv);
+      if (verbose())
+        std::fprintf(stderr, "lmdg IR pass %d: FP64 rel residual %.3e, inner %d its to %.3e (%s)\n", passes, relres,
+                     stats.iterations - before, irel, iconv ? "converged" : "not converged");
+      if (rc != LMDG_OK) break;
+      lmdg::vec_axpby(x_out, 1.0, d, 1.0, N, st);
+    }
+  }
+  if (rc == LMDG_OK && phi_out) rc = lmdg_recover(h, scheme, LMDG_PREC_FP64, x_out, phi_out, nullptr, st);
+  if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "solve");
+  const double total =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  if (info) {
+    info->iterations = stats.iterations;
+    info->restarts = stats.restarts;
+    info->ir_passes = passes;
+    info->converged = conv ? 1 : 0;
+    info->rel_residual = relres;
+    info->time_total_ms = total;
+    info->time_apply_ms = stats.apply_ms;
+  }
+  if (rc != LMDG_OK) return rc;
+  return conv ? LMDG_OK : set_error(h, LMDG_NOT_CONVERGED, "tolerance not reached");
+}
+
+int lmdg_profile(lmdg_t* h, int enable) {
+  if (!h) return LMDG_INVALID_ARG;
+  h->profiling = enable != 0;
+  h->ev_used = 0;
+  return LMDG_OK;
+}
+
+int lmdg_sweep_kernel_time(lmdg_t* h, double* total_ms, int* launches) {
+  if (!h || !total_ms || !launches) return LMDG_INVALID_ARG;
+  double total = 0;
+  for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
+    int rc = check_hip(h, hipEventSynchronize(h->ev_pool[k + 1]), "event sync");
+    if (rc != LMDG_OK) return rc;
+    float ms = 0;
+    rc = check_hip(h, hipEventElapsedTime(&ms, h->ev_pool[k], h->ev_pool[k + 1]), "event time");
+    if (rc != LMDG_OK) return rc;
+    total += ms;
+  }
+  *total_ms = total;
+  *launches = (int)(h->ev_used / 2);
+  h->ev_used = 0;
+  return LMDG_OK;
+}
+
+}  // extern "C"

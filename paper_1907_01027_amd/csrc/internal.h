@@ -1,0 +1,125 @@
+// Internal declarations of the low-memory S_N-DG library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lmdg.h"
+
+namespace lmdg {
+
+constexpr int kRows = 16;         // rows of one strip (lanes of one DPP row)
+constexpr int kMaxSlots = 64;     // direction slots per quadrant (16 waves x 4)
+constexpr int kDirStride = 8;     // doubles per direction-table entry
+
+// Raw outputs of a sweep per scheme: number of per-cell reductions and of
+// face-trace values handed from a cell to its downwind neighbours.
+template <int S> struct SchemeTraits;
+template <> struct SchemeTraits<LMDG_SCHEME_STD> { static constexpr int NOUT = 4, NF = 2; };
+template <> struct SchemeTraits<LMDG_SCHEME_LMDG> { static constexpr int NOUT = 3, NF = 1; };
+template <> struct SchemeTraits<LMDG_SCHEME_RLMDG> { static constexpr int NOUT = 6, NF = 3; };
+
+// Everything the 2D sweep kernel reads; passed by value.
+template <typename R>
+struct SweepParams {
+  int nx, ny, nstrips, cw, nchunks, dslots, n_items;
+  double hx, hy;
+  long long ncell;
+  const double* dirs;    // [4][dslots][kDirStride]: ox, oy, w, index
+  const double* x;       // moment vector (4 * ncell) or null
+  const double* sigtA;   // (sigma_s/eps + eps sigma_a) |K|
+  const double* scatA;   // (sigma_s/eps) |K|
+  const double* qA;      // eps q |K| or null
+  const double* absA;    // eps sigma_a |K|
+  int defect;            // 1: x enters through the defect source (see lm_source)
+  R* part;               // [4][NOUT][ncell] per-quadrant sums
+  R* edge;               // [4][nstrips][nx][NF][dslots] top-row traces
+  double* psi;           // optional angular flux
+  unsigned long long* prog;   // [4][nstrips] progress words
+  unsigned int* ticket;
+  int* err;
+  unsigned long long epoch;
+  unsigned int ticket_base;
+};
+
+struct Workspace {
+  double* part = nullptr;       // 4 * 6 * ncell doubles (reused as floats)
+  void* edge = nullptr;
+  size_t edge_bytes = 0;
+  unsigned long long* prog = nullptr;
+  unsigned int* ticket = nullptr;
+  int* err = nullptr;
+  double* vec = nullptr;        // scratch moment vectors (kScratchVecs * 4 * ncell)
+};
+
+}  // namespace lmdg
+
+struct lmdg_handle {
+  int dim = 2;
+  int64_t n[2] = {0, 0};
+  double len[2] = {1, 1}, h[2] = {1, 1}, area = 1;
+  long long ncell = 0;
+  int np = 4;
+  int ndir = 0;
+  std::vector<double> omega, w;
+  int dslots = 4, waves = 1, nstrips = 0;
+  std::vector<int> slot_dir;      // [4][dslots], -1 = padding
+  double* d_dirs = nullptr;
+  double cplus[2] = {0, 0}, cminus[2] = {0, 0};
+  // per-quadrant sums of w, w |Omega_x|, w |Omega_y| (used by the defect combine)
+  double qw[4] = {0, 0, 0, 0}, qax[4] = {0, 0, 0, 0}, qay[4] = {0, 0, 0, 0};
+  bool have_mat = false;
+  double* d_sigtA = nullptr;
+  double* d_scatA = nullptr;
+  double* d_absA = nullptr;        // eps sigma_a |K|
+  double* d_qA = nullptr;
+  lmdg::Workspace ws;
+  unsigned long long epoch = 1;
+  unsigned int ticket_base = 0;
+  int device = 0;
+  int n_cu = 256;
+  std::string last_error;
+  // sweep-kernel timing (lmdg_profile)
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  // Krylov workspace (grown on demand)
+  double* d_krylov = nullptr;
+  size_t krylov_doubles = 0;
+  double* d_small = nullptr;       // device scratch for dot products
+  double* h_small = nullptr;       // pinned host mirror
+  size_t small_doubles = 0;
+};
+
+namespace lmdg {
+
+constexpr int kScratchVecs = 4;
+
+// launchers (sweep2d.hip / ops.hip)
+int launch_sweep(lmdg_handle* h, int scheme, int prec, const double* x, bool use_q,
+                 double* psi, hipStream_t st, bool defect = false);
+void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double* x,
+                    double* out, hipStream_t st);
+void launch_sum_quadrants(lmdg_handle* h, int scheme, int prec, double* out, hipStream_t st);
+void launch_check_error(lmdg_handle* h, hipStream_t st);
+
+// kApplyDefect: K x from a sweep run with the defect source (same operator).
+enum CombineMode { kApply = 0, kRhs = 1, kRecover = 2, kApplyDefect = 3 };
+
+// GMRES vector kernels (ops.hip)
+void vec_dots(const double* V, long long ld, int nvec, const double* w, long long n,
+              double* partial, double* out, hipStream_t st);
+void vec_axpy_multi(double* w, const double* V, long long ld, int nvec, const double* coef,
+                    double sign, long long n, hipStream_t st);
+void vec_axpby(double* y, double a, const double* x, double b, long long n, hipStream_t st);
+void vec_copy(double* y, const double* x, long long n, hipStream_t st);
+void vec_fill(double* y, double v, long long n, hipStream_t st);
+int dots_partials();
+
+int set_error(lmdg_handle* h, int status, const std::string& msg);
+int check_hip(lmdg_handle* h, hipError_t e, const char* what);
+
+}  // namespace lmdg

@@ -1,0 +1,350 @@
+// Reductions into moment vectors, the B_11 stencil, and FP64 GMRES vector kernels.
+#include "internal.h"
+
+namespace lmdg {
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int grid_for(long long n, int per = kBlock) {
+  long long g = (n + per - 1) / per;
+  return (int)std::min<long long>(std::max<long long>(g, 1), 65535LL * 16);
+}
+
+// B_11 X_1 on one cell (Sec. 3.2, eq-lmdg-psi1, in the face form of Appendix C).
+// Slopes u = a xi + b eta + c xi*eta are isotropic, so the streaming volume term
+// sums to zero (condition (ii)) and only faces remain.  On a face with normal +e_k
+// between K- and K+, directions with Omega_k > 0 take the trace of K-, the others
+// that of K+; with c+ = sum_{Omega_k>0} w Omega_k and c- = sum_{Omega_k<0} w |Omega_k|
+// the face contributes int (c+ u_- - c- u_+)(v_- - v_+).  The exterior trace is zero,
+// which also covers boundary faces.  Mass term: eps sigma_a |K| diag(1/3, 1/3, 1/9).
+__device__ __forceinline__ void b11_cell(const double* x, long long nc, int nx, int ny, int i, int j,
+                                         double hx, double hy, double cxp, double cxm, double cyp,
+                                         double cym, double absA, double& ya, double& yb, double& yc) {
+  const long long p = (long long)j * nx + i;
+  const double* xa = x + nc;
+  const double* xb = x + 2 * nc;
+  const double* xc = x + 3 * nc;
+  const double a = xa[p], b = xb[p], c = xc[p];
+  ya = absA * (1.0 / 3.0) * a;
+  yb = absA * (1.0 / 3.0) * b;
+  yc = absA * (1.0 / 9.0) * c;
+  const double t3 = 1.0 / 3.0;
+  {  // right face, K is the lower-x cell: trace a + (b + c) eta
+    const bool in = i + 1 < nx;
+    const double aR = in ? xa[p + 1] : 0.0, bR = in ? xb[p + 1] : 0.0, cR = in ? xc[p + 1] : 0.0;
+    const double J0 = cxp * a + cxm * aR;
+    const double J1 = cxp * (b + c) - cxm * (bR - cR);
+    ya += hy * J0;
+    yb += hy * J1 * t3;
+    yc += hy * J1 * t3;
+  }
+  {  // left face, K is the upper-x cell: trace -a + (b - c) eta
+    const bool in = i > 0;
+    const double aL = in ? xa[p - 1] : 0.0, bL = in ? xb[p - 1] : 0.0, cL = in ? xc[p - 1] : 0.0;
+    const double J0 = cxp * aL + cxm * a;
+    const double J1 = cxp * (bL + cL) - cxm * (b - c);
+    ya += hy * J0;
+    yb -= hy * J1 * t3;
+    yc += hy * J1 * t3;
+  }
+  {  // top face, K is the lower-y cell: trace b + (a + c) xi
+    const bool in = j + 1 < ny;
+    const double aT = in ? xa[p + nx] : 0.0, bT = in ? xb[p + nx] : 0.0, cT = in ? xc[p + nx] : 0.0;
+    const double J0 = cyp * b + cym * bT;
+    const double J1 = cyp * (a + c) - cym * (aT - cT);
+    yb += hx * J0;
+    ya += hx * J1 * t3;
+    yc += hx * J1 * t3;
+  }
+  {  // bottom face, K is the upper-y cell: trace -b + (a - c) xi
+    const bool in = j > 0;
+    const double aB = in ? xa[p - nx] : 0.0, bB = in ? xb[p - nx] : 0.0, cB = in ? xc[p - nx] : 0.0;
+    const double J0 = cyp * bB + cym * b;
+    const double J1 = cyp * (aB + cB) - cym * (a - c);
+    yb += hx * J0;
+    ya -= hx * J1 * t3;
+    yc += hx * J1 * t3;
+  }
+}
+
+struct QuadMoments {
+  double w[4], ax[4], ay[4];  // per quadrant: sum w, sum w |Omega_x|, sum w |Omega_y|
+};
+
+// G Sigma_0^T x_0: the second block row applied to the isotropic field x_0 copied to
+// every direction (FP64, needed by the defect form of the operator).  Per direction
+// the rows depend on Omega only through its quadrant and linearly through w,
+// w|Omega_x|, w|Omega_y|, so the direction sum collapses to four quadrant terms.
+// LMDG: G = Sigma L_10 (rows Ox h_y (u_up - u_K), Oy h_x (u_down - u_K), 0).
+// RLMDG: G = Sigma (L_10 + L_11 R) - Sigma M_1 P_1 R, the rows of the sweep's cell
+// formula evaluated with psi = x_0 everywhere (upwind slopes k (u - u_up), k = 1 in
+// the inflow cell of the quadrant, traces zero outside the mesh).
+template <bool RLM>
+__device__ __forceinline__ void iso_g(const double* x0, int nx, int ny, int i, int j, double hx, double hy,
+                                      double sigtA, double scatA, const QuadMoments& qm, double g[3]) {
+  auto val = [&](int ii, int jj) -> double {
+    return (ii >= 0 && ii < nx && jj >= 0 && jj < ny) ? x0[(long long)jj * nx + ii] : 0.0;
+  };
+  const double v = x0[(long long)j * nx + i];
+  const double t3 = 1.0 / 3.0;
+  g[0] = g[1] = g[2] = 0.0;
+  double prx = 0.0, pry = 0.0;  // P_1 R x_0
+  for (int q = 0; q < 4; ++q) {
+    const int sx = (q & 1) ? -1 : 1, sy = (q & 2) ? -1 : 1;
+    const double W = qm.w[q], AX = qm.ax[q], AY = qm.ay[q];
+    const bool upx = sx > 0 ? i > 0 : i < nx - 1;  // upwind x neighbour inside the mesh
+    const bool upy = sy > 0 ? j > 0 : j < ny - 1;
+    const double u1 = val(i - sx, j), d1 = val(i, j - sy);
+    if (!RLM) {
+      g[0] += sx * AX * hy * (u1 - v);
+      g[1] += sy * AY * hx * (d1 - v);
+      continue;
+    }
+    const double u2 = val(i - 2 * sx, j), d2 = val(i, j - 2 * sy), ud = val(i - sx, j - sy);
+    const double kx = upx ? 0.5 : 1.0, ky = upy ? 0.5 : 1.0;
+    // is the upwind neighbour itself the inflow cell of its line?
+    const double kxu = (sx > 0 ? i - 1 == 0 : i + 1 == nx - 1) ? 1.0 : 0.5;
+    const double kyd = (sy > 0 ? j - 1 == 0 : j + 1 == ny - 1) ? 1.0 : 0.5;
+    const double cxi = sx * kx * (v - u1);
+    const double ceta = sy * ky * (v - d1);
+    const double txu = upx ? u1 + kxu * (u1 - u2) : 0.0;
+    const double tyd = upy ? d1 + kyd * (d1 - d2) : 0.0;
+    const double cxi_d = upy ? sx * kx * (d1 - ud) : 0.0;    // xi slope of the cell below
+    const double ceta_u = upx ? sy * ky * (u1 - ud) : 0.0;   // eta slope of the cell on the left
+    g[0] += sx * AX * hy * (txu - v) + (sigtA * t3 * W + AX * hy + AY * hx * t3) * cxi - AY * hx * t3 * cxi_d;
+    g[1] += sy * AY * hx * (tyd - v) + (sigtA * t3 * W + AY * hx + AX * hy * t3) * ceta - AX * hy * t3 * ceta_u;
+    g[2] += t3 * (sx * AX * hy * (ceta_u - ceta) + sy * AY * hx * (cxi_d - cxi));
+    prx += W * cxi;
+    pry += W * ceta;
+  }
+  if (RLM) {
+    g[0] -= scatA * t3 * prx;
+    g[1] -= scatA * t3 * pry;
+  }
+}
+
+// Reduced operator / right-hand side / recovery for LMDG and RLMDG from the
+// per-quadrant sweep sums (eq-nonrec-block; Sec. 3.3.2 with the second block row
+// G = Sigma (L_10 + L_11 R) - Sigma M_1 P_1 R; Step 4 with c = 0 since the source
+// has no slope moments and the inflow is vacuum).  In kApplyDefect the sweep solved
+// L~_00 psi_D = defect source, and K x = [P_0 psi_D ; B_11 x_1 - G Sigma_0^T x_0 + G psi_D].
+template <typename R, bool RLM>
+__global__ void combine_lm_kernel(int mode, int nx, int ny, double hx, double hy, double cxp, double cxm,
+                                  double cyp, double cym, QuadMoments qm, const double* __restrict__ x,
+                                  const R* __restrict__ part, const double* __restrict__ sigtA,
+                                  const double* __restrict__ scatA, const double* __restrict__ absA,
+                                  double* __restrict__ out) {
+  constexpr int NOUT = RLM ? 6 : 3;
+  const long long nc = (long long)nx * ny;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nc;
+       p += (long long)gridDim.x * blockDim.x) {
+    double s[NOUT];
+#pragma unroll
+    for (int m = 0; m < NOUT; ++m) {
+      double acc = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc += (double)part[((long long)q * NOUT + m) * nc + p];
+      s[m] = acc;
+    }
+    const double sl = RLM ? scatA[p] * (1.0 / 3.0) : 0.0;  // Sigma M_1 on the xi, eta slopes
+    const double g1 = s[1] - (RLM ? sl * s[4] : 0.0);
+    const double g2 = s[2] - (RLM ? sl * s[5] : 0.0);
+    const double g3 = RLM ? s[3] : 0.0;
+    if (mode == kApply) {
+      const int i = (int)(p % nx), j = (int)(p / nx);
+      double ya, yb, yc;
+      b11_cell(x, nc, nx, ny, i, j, hx, hy, cxp, cxm, cyp, cym, absA[p], ya, yb, yc);
+      out[p] = x[p] - s[0];
+      out[nc + p] = ya - g1;
+      out[2 * nc + p] = yb - g2;
+      out[3 * nc + p] = yc - g3;
+    } else if (mode == kApplyDefect) {
+      const int i = (int)(p % nx), j = (int)(p / nx);
+      double ya, yb, yc, gi[3];
+      b11_cell(x, nc, nx, ny, i, j, hx, hy, cxp, cxm, cyp, cym, absA[p], ya, yb, yc);
+      iso_g<RLM>(x, nx, ny, i, j, hx, hy, sigtA[p], scatA[p], qm, gi);
+      out[p] = s[0];
+      out[nc + p] = ya - gi[0] + g1;
+      out[2 * nc + p] = yb - gi[1] + g2;
+      out[3 * nc + p] = yc - gi[2] + g3;
+    } else if (mode == kRhs) {
+      out[p] = s[0];
+      out[nc + p] = g1;
+      out[2 * nc + p] = g2;
+      out[3 * nc + p] = g3;
+    } else {  // recovery: Phi_1 = -X_1 + P_1 R Psi_0 (+ c, zero here)
+      out[p] = s[0];
+      out[nc + p] = -x[nc + p] + (RLM ? s[4] : 0.0);
+      out[2 * nc + p] = -x[2 * nc + p] + (RLM ? s[5] : 0.0);
+      out[3 * nc + p] = -x[3 * nc + p];
+    }
+  }
+}
+
+// Standard scheme: K Phi = Phi - P L^{-1} M Phi (eq-sndg-phi); right-hand side and
+// recovered scalar flux are the plain quadrant sums.
+template <typename R>
+__global__ void combine_std_kernel(int mode, long long nc, const double* __restrict__ x,
+                                   const R* __restrict__ part, double* __restrict__ out) {
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nc;
+       p += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      double acc = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc += (double)part[((long long)q * 4 + m) * nc + p];
+      // kApplyDefect: the sweep already produced P L^{-1}(defect source) = K Phi
+      out[m * nc + p] = (mode == kApply) ? x[m * nc + p] - acc : acc;
+    }
+  }
+}
+
+template <typename R>
+__global__ void sum_quadrants_kernel(int nout, int nout_abi, long long nc, const R* __restrict__ part,
+                                     double* __restrict__ out) {
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nc;
+       p += (long long)gridDim.x * blockDim.x) {
+    for (int m = 0; m < nout_abi; ++m) {
+      double acc = 0;
+      if (m < nout)
+        for (int q = 0; q < 4; ++q) acc += (double)part[((long long)q * nout + m) * nc + p];
+      out[m * nc + p] = acc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- GMRES vectors
+constexpr int kDotBlocks = 240;
+
+// partial[v * kDotBlocks + b] = block b's share of V_v . w
+__global__ void dots_partial_kernel(const double* __restrict__ V, long long ld, const double* __restrict__ w,
+                                    long long n, double* __restrict__ partial) {
+  const int v = blockIdx.y;
+  const double* vv = V + v * ld;
+  double acc = 0;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    acc += vv[e] * w[e];
+  __shared__ double sh[kBlock];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(long long)v * gridDim.x + blockIdx.x] = sh[0];
+}
+
+__global__ void dots_final_kernel(const double* __restrict__ partial, int nparts, double* __restrict__ out) {
+  const int v = blockIdx.x;
+  __shared__ double sh[kBlock];
+  double acc = 0;
+  for (int e = threadIdx.x; e < nparts; e += blockDim.x) acc += partial[(long long)v * nparts + e];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[v] = sh[0];
+}
+
+__global__ void axpy_multi_kernel(double* __restrict__ w, const double* __restrict__ V, long long ld, int nvec,
+                                  const double* __restrict__ coef, double sign, long long n) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    double acc = 0;
+    for (int v = 0; v < nvec; ++v) acc += coef[v] * V[v * ld + e];
+    w[e] += sign * acc;
+  }
+}
+
+__global__ void axpby_kernel(double* __restrict__ y, double a, const double* __restrict__ x, double b,
+                             long long n) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    y[e] = (b == 0.0) ? a * x[e] : a * x[e] + b * y[e];  // b = 0 never reads y
+}
+
+__global__ void fill_kernel(double* __restrict__ y, double v, long long n) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    y[e] = v;
+}
+
+}  // namespace
+
+int dots_partials() { return kDotBlocks; }
+
+void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double* x, double* out,
+                    hipStream_t st) {
+  const long long nc = h->ncell;
+  const int g = std::min(grid_for(nc), 4096);
+  const int nx = (int)h->n[0], ny = (int)h->n[1];
+  if (scheme == LMDG_SCHEME_STD) {
+    if (prec == LMDG_PREC_FP64)
+      hipLaunchKernelGGL(combine_std_kernel<double>, dim3(g), dim3(kBlock), 0, st, mode, nc, x,
+                         (const double*)h->ws.part, out);
+    else
+      hipLaunchKernelGGL(combine_std_kernel<float>, dim3(g), dim3(kBlock), 0, st, mode, nc, x,
+                         (const float*)h->ws.part, out);
+    return;
+  }
+  const double hx = h->h[0], hy = h->h[1];
+  QuadMoments qm;
+  for (int q = 0; q < 4; ++q) {
+    qm.w[q] = h->qw[q];
+    qm.ax[q] = h->qax[q];
+    qm.ay[q] = h->qay[q];
+  }
+#define LMDG_COMBINE(R, RLM)                                                                        \
+  hipLaunchKernelGGL((combine_lm_kernel<R, RLM>), dim3(g), dim3(kBlock), 0, st, mode, nx, ny, hx, hy, \
+                     h->cplus[0], h->cminus[0], h->cplus[1], h->cminus[1], qm, x,                    \
+                     (const R*)h->ws.part, h->d_sigtA, h->d_scatA, h->d_absA, out)
+  const bool rlm = scheme == LMDG_SCHEME_RLMDG;
+  if (prec == LMDG_PREC_FP64) {
+    if (rlm) LMDG_COMBINE(double, true); else LMDG_COMBINE(double, false);
+  } else {
+    if (rlm) LMDG_COMBINE(float, true); else LMDG_COMBINE(float, false);
+  }
+#undef LMDG_COMBINE
+}
+
+void launch_sum_quadrants(lmdg_handle* h, int scheme, int prec, double* out, hipStream_t st) {
+  const int nout = scheme == LMDG_SCHEME_STD ? 4 : (scheme == LMDG_SCHEME_LMDG ? 3 : 6);
+  const int nout_abi = scheme == LMDG_SCHEME_RLMDG ? 6 : 4;
+  const int g = std::min(grid_for(h->ncell), 4096);
+  if (prec == LMDG_PREC_FP64)
+    hipLaunchKernelGGL(sum_quadrants_kernel<double>, dim3(g), dim3(kBlock), 0, st, nout, nout_abi, h->ncell,
+                       (const double*)h->ws.part, out);
+  else
+    hipLaunchKernelGGL(sum_quadrants_kernel<float>, dim3(g), dim3(kBlock), 0, st, nout, nout_abi, h->ncell,
+                       (const float*)h->ws.part, out);
+}
+
+void vec_dots(const double* V, long long ld, int nvec, const double* w, long long n, double* partial,
+              double* out, hipStream_t st) {
+  hipLaunchKernelGGL(dots_partial_kernel, dim3(kDotBlocks, nvec), dim3(kBlock), 0, st, V, ld, w, n, partial);
+  hipLaunchKernelGGL(dots_final_kernel, dim3(nvec), dim3(kBlock), 0, st, partial, kDotBlocks, out);
+}
+
+void vec_axpy_multi(double* w, const double* V, long long ld, int nvec, const double* coef, double sign,
+                    long long n, hipStream_t st) {
+  hipLaunchKernelGGL(axpy_multi_kernel, dim3(std::min(grid_for(n), 4096)), dim3(kBlock), 0, st, w, V, ld, nvec,
+                     coef, sign, n);
+}
+
+void vec_axpby(double* y, double a, const double* x, double b, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(axpby_kernel, dim3(std::min(grid_for(n), 4096)), dim3(kBlock), 0, st, y, a, x, b, n);
+}
+
+void vec_copy(double* y, const double* x, long long n, hipStream_t st) {
+  hipMemcpyAsync(y, x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st);
+}
+
+void vec_fill(double* y, double v, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(fill_kernel, dim3(std::min(grid_for(n), 4096)), dim3(kBlock), 0, st, y, v, n);
+}
+
+}  // namespace lmdg

@@ -1,0 +1,71 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports every
+symbol the header declares, its quadrature generator agrees with the oracle's, and
+argument validation rejects bad input before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.quadrature import level_symmetric
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1907_01027_amd import lmdg
+    return lmdg
+
+
+def test_library_exports_header_symbols():
+    lmdg = _lib()
+    header = open(os.path.join(ROOT, "include", "lmdg.h")).read()
+    declared = sorted(set(re.findall(r"\b(lmdg_[a-z_0-9]+)\s*\(", header)))
+    assert declared, "no declarations found"
+    lib = lmdg.library()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(lmdg.EXPORTED) == declared
+
+
+@pytest.mark.parametrize("order", [4, 8, 12, 16])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_library_quadrature_matches_oracle(order, dim):
+    lmdg = _lib()
+    om, w = lmdg.lmdg_quadrature_level_symmetric(dim, order)
+    om_o, w_o = level_symmetric(order, dim)
+    assert om.shape == om_o.shape
+    # same construction rule, independent code: same set of points and weights
+    ko = np.lexsort(np.c_[om_o, w_o].T)
+    kl = np.lexsort(np.c_[om, w].T)
+    # the two root searches for mu_1 stop at slightly different points; the S16
+    # residual is flat near its root (min-norm weights), so agreement is ~1e-9
+    assert np.abs(om[kl] - om_o[ko]).max() < 1e-8
+    assert np.abs(w[kl] - w_o[ko]).max() < 1e-8
+    assert abs(w.sum() - 1) < 1e-14 and np.abs(w @ om).max() < 1e-14
+    assert np.abs(np.einsum("j,ja,jb->ab", w, om, om) - np.eye(dim) / 3).max() < 1e-14
+
+
+def test_create_rejects_bad_input():
+    lmdg = _lib()
+    om, w = level_symmetric(4, 2)
+    bad = [
+        ((0, 4), (1.0, 1.0), om, w),                          # empty mesh
+        ((4, 4), (1.0, -1.0), om, w),                         # negative length
+        ((4, 4), (1.0, 1.0), om, w * 1.01),                   # weights do not sum to 1
+        ((4, 4), (1.0, 1.0), om * 0.9, w),                    # second moment wrong
+        ((4, 4), (1.0, 1.0), np.where(om > 0, om, 0.0), w),   # zero components
+    ]
+    for n, length, o, ww in bad:
+        with pytest.raises(lmdg.LmdgError) as e:
+            lmdg.lmdg_create(n, length, o, ww)
+        assert e.value.status == lmdg.LMDG_INVALID_ARG
+
+
+def test_status_strings():
+    lmdg = _lib()
+    lib = lmdg.library()
+    for st in range(6):
+        assert lib.lmdg_status_string(st)
+    assert lib.lmdg_last_error(None) == b"no handle"

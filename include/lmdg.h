@@ -106,7 +106,7 @@ int lmdg_quadrature_level_symmetric(int dim, int order, int capacity, int* n_dir
  * of [0, length[0]] x [0, length[1]] and the quadrature (omega, w) (host arrays,
  * copied).  The quadrature must satisfy eq-polyquad (i)-(iii) to 1e-12, have
  * positive weights and no zero component (the upwind direction along every axis
- * must be defined), and at most 64 directions per quadrant.
+ * must be defined), and at most 36 directions per quadrant (S16 has 36).
  * Errors: INVALID_ARG (NULL pointers, sizes < 1, quadrature violations),
  *         UNSUPPORTED (dim != 2), HIP_ERROR (allocation).
  */

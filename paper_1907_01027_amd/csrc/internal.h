@@ -12,7 +12,8 @@
 namespace lmdg {
 
 constexpr int kRows = 16;         // rows of one strip (lanes of one DPP row)
-constexpr int kMaxSlots = 64;     // direction slots per quadrant (16 waves x 4)
+constexpr int kMaxSlots = 36;     // direction slots per quadrant (9 waves x 4; S16 has 36)
+constexpr int kMaxWaves = kMaxSlots / 4;
 constexpr int kDirStride = 8;     // doubles per direction-table entry
 
 // Raw outputs of a sweep per scheme: number of per-cell reductions and of
@@ -25,7 +26,7 @@ template <> struct SchemeTraits<LMDG_SCHEME_RLMDG> { static constexpr int NOUT =
 // Everything the 2D sweep kernel reads; passed by value.
 template <typename R>
 struct SweepParams {
-  int nx, ny, nstrips, cw, nchunks, dslots, n_items;
+  int nx, ny, nstrips, cw, lcw, nchunks, dslots, n_items;  // cw = 1 << lcw steps per chunk
   double hx, hy;
   long long ncell;
   const double* dirs;    // [4][dslots][kDirStride]: ox, oy, w, index

@@ -14,10 +14,16 @@
 //                and reaches lane r through one DPP row shift; the cell to the left is
 //                the lane's own previous result.  Row 0 reads the trace that the strip
 //                below wrote to an edge buffer.
+//   chunks     = CW steps.  Before a chunk, the strip-below traces it needs are staged
+//                in LDS, and every cell it visits has its source reduced (in FP64, once
+//                per workgroup) to five coefficients per source moment, so that the
+//                source of direction l is c0 + Ox c1 + Oy c2 + |Ox| c3 + |Oy| c4.  The
+//                coefficients of chunk k+1 are loaded while chunk k runs; the step loop
+//                touches only registers and LDS.
 //   reductions = per-cell sums over directions: over the 4 slots of a wave with two
 //                cross-lane swaps, over waves through LDS, written once per cell and
 //                quadrant; a combine kernel adds the quadrants.
-// Strips publish "columns finished in my top row" every CW steps with an agent-scope
+// Strips publish "columns finished in my top row" every chunk with an agent-scope
 // release; consumers acquire before reading.  Progress words carry the launch epoch
 // in the high half so they never need clearing.  Every wait is bounded: a stuck wait
 // sets an error flag and the kernel still finishes.
@@ -68,16 +74,29 @@ __device__ __forceinline__ void store_agent(T* p, T v) {
 }
 
 constexpr long long kSpinLimit = 1ll << 25;
+constexpr int kStepGroup = 4;  // steps per unrolled group; chunks hold a multiple of it
 
 // Per-lane direction constants.
 template <typename R>
 struct Dir {
   double ox, oy;        // Omega components
+  R rox, roy;           // the same in the sweep precision
+  R aox, aoy;           // |Omega_x|, |Omega_y|
   R w;                  // quadrature weight (0 for padding slots)
   R axhy, ayhx;         // |Omega_x| h_y, |Omega_y| h_x  (face measures times |Omega.nu|)
   R oxhy, oyhx;         // Omega_x h_y, Omega_y h_x
   R sx, sy;             // signs of Omega_x, Omega_y
   int idx;              // caller's direction index, -1 for padding
+};
+
+// Source layout per scheme: NS source moments, NC staged values per cell
+// (sigma_t|K| followed by 5 coefficients per moment), NRAW FP64 inputs per cell.
+template <int S>
+struct SrcTraits {
+  static constexpr int NS = (S == LMDG_SCHEME_STD) ? 4 : 1;
+  static constexpr int NC = 1 + 5 * NS;
+  static constexpr int NRAW = (S == LMDG_SCHEME_STD) ? 16 : 13;
+  static constexpr int MAXC = (S == LMDG_SCHEME_STD) ? 1 : 2;  // staged cells per thread
 };
 
 // ---------------------------------------------------------------- local solves
@@ -131,13 +150,7 @@ __device__ __forceinline__ void cell_rlmdg(const Dir<R>& d, R src, R sigtA, R kx
   psi_out = psi;
 }
 
-// Standard Q^1 sweep: the 4 x 4 local block (sigma_t M + streaming + outflow faces)
-// of eq-Ljk with basis 1, xi, eta, xi*eta, right-hand side src (4 moments) plus the
-// inflow traces A + B (along-face coordinate) from the left and lower neighbours.
-// The symmetric part of the block is positive definite, so elimination needs no
-// pivoting.  Hands downwind the outflow traces; reductions are w c_r (P Psi).
-// Local block (coef M + streaming + outflow faces) of the standard sweep; coef is
-// sigma_t|K| for the sweep and eps sigma_a |K| for the defect source below.
+// Local block (coef M + streaming + outflow faces) of the standard sweep.
 // ax = |Ox| h_y, ay = |Oy| h_x, oxhy = Ox h_y, oyhx = Oy h_x, sx/sy the signs.
 template <typename T>
 __device__ __forceinline__ void std_block(T coef, T ax, T ay, T oxhy, T oyhx, T sx, T sy, T m[4][4]) {
@@ -175,6 +188,11 @@ __device__ __forceinline__ void std_inflow(T ax, T ay, T sx, T sy, const T* xin,
   b[3] = -ax * sx * third * xin[1] - ay * sy * third * ydn[1];
 }
 
+// Standard Q^1 sweep: the 4 x 4 local block (sigma_t M + streaming + outflow faces)
+// of eq-Ljk with basis 1, xi, eta, xi*eta, right-hand side src (4 moments) plus the
+// inflow traces from the left and lower neighbours.  The symmetric part of the block
+// is positive definite, so elimination needs no pivoting.  Hands downwind the outflow
+// traces; reductions are w c_r (P Psi).
 template <typename R>
 __device__ __forceinline__ void cell_std(const Dir<R>& d, const R* src, R sigtA, const R* xin,
                                          const R* ydn, R* xo, R* yo, R* o, R* c) {
@@ -212,89 +230,180 @@ __device__ __forceinline__ void cell_std(const Dir<R>& d, const R* src, R sigtA,
   for (int r = 0; r < 4; ++r) o[r] = d.w * c[r];
 }
 
-// ---------------------------------------------------------------- FP64 sources
-// Right-hand side of the low-memory sweeps for a moment vector x (FP64), with the
-// upwind cells at cell - sxs (x) and cell - sys (y); c, jr are sweep-order indices.
-//   plain : M_0 x_0 + L_01 Sigma^T x_1
-//   defect: (L~_00 Sigma_0^T - M_0) x_0 - L_01 Sigma^T x_1
-// The defect form is the same operator rearranged (Sigma_0^T copies x_0 to every
-// direction, P_0 Sigma_0^T = I since the weights sum to one):
-//   x_0 - P_0 L~_00^{-1}(M_0 x_0 + L_01 Sigma^T x_1) = P_0 L~_00^{-1}(defect source);
-// the sigma_s/eps parts of sigma_t|K| and M_0 cancel exactly, leaving eps sigma_a |K|
-// and upwind face differences of x_0, so nothing large cancels after the sweep.
-// L~_00 applied to an isotropic field u: sigma_t|K| u_K + |Ox| h_y (T_x(K) - T_x(up))
-// + |Oy| h_x (T_y(K) - T_y(down)), T = outflow trace (u itself for LMDG; with the
-// upwind slope k (u - u_up), k = 1 in the inflow cell and 1/2 inside, for RLMDG;
-// zero for cells outside the mesh).
-template <bool REC>
-__device__ __forceinline__ double lm_source(const double* x, long long nc, long long cell, long long sxs,
-                                            long long sys, int c, int jr, double scatA, double absA, double ox,
-                                            double oy, double hx, double hy, bool defect) {
-  const double a = x[nc + cell], b = x[2 * nc + cell];
-  const double al = c > 0 ? x[nc + cell - sxs] : 0.0;
-  const double bd = jr > 0 ? x[2 * nc + cell - sys] : 0.0;
-  const double l01 = ox * hy * (a - al) + oy * hx * (b - bd);
-  const double x0 = x[cell];
-  if (!defect) return scatA * x0 + l01;
-  const double u1 = c > 0 ? x[cell - sxs] : 0.0;
-  const double d1 = jr > 0 ? x[cell - sys] : 0.0;
-  double tx = x0, txu = u1, ty = x0, tyd = d1;
-  if (REC) {
-    const double u2 = c > 1 ? x[cell - 2 * sxs] : 0.0;
-    const double d2 = jr > 1 ? x[cell - 2 * sys] : 0.0;
-    tx = x0 + (c == 0 ? 1.0 : 0.5) * (x0 - u1);
-    ty = x0 + (jr == 0 ? 1.0 : 0.5) * (x0 - d1);
-    txu = c > 0 ? u1 + (c == 1 ? 1.0 : 0.5) * (u1 - u2) : 0.0;
-    tyd = jr > 0 ? d1 + (jr == 1 ? 1.0 : 0.5) * (d1 - d2) : 0.0;
-  }
-  return absA * x0 + fabs(ox) * hy * (tx - txu) + fabs(oy) * hx * (ty - tyd) - l01;
-}
-
-// Right-hand side of the standard sweep for Phi = x (FP64, 4 moments):
-//   plain : M Phi_K = (sigma_s/eps)|K| diag(1, 1/3, 1/3, 1/9) Phi_K
-//   defect: (L_l Sigma^T - M) Phi = (eps sigma_a |K| mass + streaming + outflow) Phi_K
-//           minus the inflow terms built from the upwind cells' outflow traces of Phi,
-// so that Phi - P L^{-1} M Phi = P L^{-1}(defect source) without cancellation.
-__device__ __forceinline__ void std_source(const double* x, long long nc, long long cell, long long sxs,
-                                           long long sys, int c, int jr, double scatA, double absA, double ox,
-                                           double oy, double hx, double hy, bool defect, double out[4]) {
-  const double phi[4] = {x[cell], x[nc + cell], x[2 * nc + cell], x[3 * nc + cell]};
-  if (!defect) {
-    out[0] = scatA * phi[0];
-    out[1] = scatA * (1.0 / 3.0) * phi[1];
-    out[2] = scatA * (1.0 / 3.0) * phi[2];
-    out[3] = scatA * (1.0 / 9.0) * phi[3];
-    return;
-  }
-  const double sx = ox > 0 ? 1.0 : -1.0, sy = oy > 0 ? 1.0 : -1.0;
-  const double ax = fabs(ox) * hy, ay = fabs(oy) * hx;
-  double m[4][4];
-  std_block<double>(absA, ax, ay, ox * hy, oy * hx, sx, sy, m);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) out[r] = m[r][0] * phi[0] + m[r][1] * phi[1] + m[r][2] * phi[2] + m[r][3] * phi[3];
-  double xin[2] = {0.0, 0.0}, ydn[2] = {0.0, 0.0};
-  if (c > 0) {
-    const long long u = cell - sxs;
-    xin[0] = x[u] + sx * x[nc + u];
-    xin[1] = x[2 * nc + u] + sx * x[3 * nc + u];
-  }
-  if (jr > 0) {
-    const long long u = cell - sys;
-    ydn[0] = x[u] + sy * x[2 * nc + u];
-    ydn[1] = x[nc + u] + sy * x[3 * nc + u];
-  }
-  double b[4];
-  std_inflow<double>(ax, ay, sx, sy, xin, ydn, b);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) out[r] -= b[r];
-}
-
+// ---------------------------------------------------------------- staged sources
+// FP64 inputs of one cell (sweep-order column c, row jr) of quadrant (sxi, syi).
+//   LMDG/RLMDG: x_0 at the cell, 1 and 2 cells upwind in x and in y; the xi slope
+//               of x_1 at the cell and its x-upwind neighbour; the eta slope at the cell
+//               and its y-upwind neighbour; sigma_t|K|, eps sigma_a|K|, sigma_s/eps|K|, eps q|K|
+//   STD:        the 4 moments at the cell, at its x-upwind and y-upwind neighbours,
+//               and the same four material values
+// Values outside the mesh are zero (zero exterior traces, vacuum inflow).
 template <typename R, int S>
-__global__ void __launch_bounds__(1024) sweep2d_kernel(SweepParams<R> P) {
+__device__ __forceinline__ void raw_load(const SweepParams<R>& P, int sxi, int syi, int c, int jr, double* raw) {
+  constexpr int NRAW = SrcTraits<S>::NRAW;
+#pragma unroll
+  for (int k = 0; k < NRAW; ++k) raw[k] = 0.0;
+  if (c < 0 || c >= P.nx || jr >= P.ny) return;
+  const int nx = P.nx;
+  const long long nc = P.ncell;
+  const int i = sxi > 0 ? c : nx - 1 - c;
+  const int j = syi > 0 ? jr : P.ny - 1 - jr;
+  const long long cell = (long long)j * nx + i;
+  const long long sxs = sxi, sys = (long long)syi * nx;  // cell - sxs, cell - sys: upwind
+  const double* x = P.x;
+  if constexpr (S == LMDG_SCHEME_STD) {
+    if (x) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) raw[m] = x[m * nc + cell];
+      if (c > 0) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) raw[4 + m] = x[m * nc + cell - sxs];
+      }
+      if (jr > 0) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) raw[8 + m] = x[m * nc + cell - sys];
+      }
+    }
+    raw[12] = P.sigtA[cell];
+    raw[13] = P.absA[cell];
+    raw[14] = P.scatA[cell];
+    raw[15] = P.qA ? P.qA[cell] : 0.0;
+  } else {
+    if (x) {
+      raw[0] = x[cell];
+      if (c > 0) raw[1] = x[cell - sxs];
+      if (c > 1) raw[2] = x[cell - 2 * sxs];
+      if (jr > 0) raw[3] = x[cell - sys];
+      if (jr > 1) raw[4] = x[cell - 2 * sys];
+      raw[5] = x[nc + cell];
+      if (c > 0) raw[6] = x[nc + cell - sxs];
+      raw[7] = x[2 * nc + cell];
+      if (jr > 0) raw[8] = x[2 * nc + cell - sys];
+    }
+    raw[9] = P.sigtA[cell];
+    raw[10] = P.absA[cell];
+    raw[11] = P.scatA[cell];
+    raw[12] = P.qA ? P.qA[cell] : 0.0;
+  }
+}
+
+// Source coefficients of one cell (FP64 arithmetic, stored in the sweep precision).
+//
+// LMDG/RLMDG, plain form: M_0 x_0 + L_01 Sigma^T x_1 (+ Q~_0); the isotropic slopes
+//   of x_1 enter the constant row through the face traces:
+//   c0 = (sigma_s/eps)|K| x_0 + eps q|K|, c1 = h_y (a_K - a_left), c2 = h_x (b_K - b_down).
+// LMDG/RLMDG, defect form: (L~_00 Sigma_0^T - M_0) x_0 - L_01 Sigma^T x_1, the same
+//   operator rearranged (Sigma_0^T copies x_0 to every direction; P_0 Sigma_0^T = I):
+//     x_0 - P_0 L~_00^{-1}(M_0 x_0 + L_01 Sigma^T x_1) = P_0 L~_00^{-1}(defect source).
+//   The sigma_s/eps parts of sigma_t|K| and M_0 cancel exactly, leaving
+//   c0 = eps sigma_a|K| x_0, c1, c2 = minus the plain ones, c3 = h_y (T_x(K) - T_x(left)),
+//   c4 = h_x (T_y(K) - T_y(down)), with T the outflow trace of x_0 (x_0 itself for
+//   LMDG; with the upwind slope k (u - u_up), k = 1 in the inflow cell and 1/2
+//   inside, for RLMDG; zero outside the mesh).
+// STD, plain: M Phi_K = (sigma_s/eps)|K| diag(1, 1/3, 1/3, 1/9) Phi_K (+ Q).
+// STD, defect: (L_l Sigma^T - M) Phi = (eps sigma_a|K| mass + streaming + outflow) Phi_K
+//   minus the inflow terms of the upwind cells' outflow traces of Phi, split by the
+//   factor (1, Ox, Oy, |Ox|, |Oy|) each term carries.
+template <typename R, int S>
+__device__ __forceinline__ void raw_coef(const double* raw, int c, int jr, int sxi, int syi, double hx,
+                                         double hy, bool defect, R* coef, int cstride) {
+  if constexpr (S == LMDG_SCHEME_STD) {
+    const double* p = raw;       // moments at the cell
+    const double* u = raw + 4;   // x-upwind neighbour
+    const double* dn = raw + 8;  // y-upwind neighbour
+    const double sigtA = raw[12], absA = raw[13], scatA = raw[14], qA = raw[15];
+    const double t3 = 1.0 / 3.0, t9 = 1.0 / 9.0;
+    double cf[4][5];
+    for (int m = 0; m < 4; ++m)
+      for (int k = 0; k < 5; ++k) cf[m][k] = 0.0;
+    const double mass[4] = {1.0, t3, t3, t9};
+    if (!defect) {
+      for (int m = 0; m < 4; ++m) cf[m][0] = scatA * mass[m] * p[m];
+    } else {
+      const double sx = sxi, sy = syi;
+      for (int m = 0; m < 4; ++m) cf[m][0] = absA * mass[m] * p[m];
+      // streaming -int u Omega.grad v
+      cf[1][1] = -2.0 * hy * p[0];
+      cf[3][1] = -2.0 * t3 * hy * p[2];
+      cf[2][2] = -2.0 * hx * p[0];
+      cf[3][2] = -2.0 * t3 * hx * p[1];
+      // outflow faces minus inflow traces of the upwind cells
+      const double Ax = u[0] + sx * u[1], Bx = u[2] + sx * u[3];
+      const double Ay = dn[0] + sy * dn[2], By = dn[1] + sy * dn[3];
+      cf[0][3] = hy * (p[0] + sx * p[1] - Ax);
+      cf[1][3] = hy * (sx * p[0] + p[1] + sx * Ax);
+      cf[2][3] = hy * (t3 * p[2] + sx * t3 * p[3] - t3 * Bx);
+      cf[3][3] = hy * (sx * t3 * p[2] + t3 * p[3] + sx * t3 * Bx);
+      cf[0][4] = hx * (p[0] + sy * p[2] - Ay);
+      cf[1][4] = hx * (t3 * p[1] + sy * t3 * p[3] - t3 * By);
+      cf[2][4] = hx * (sy * p[0] + p[2] + sy * Ay);
+      cf[3][4] = hx * (sy * t3 * p[1] + t3 * p[3] + sy * t3 * By);
+    }
+    cf[0][0] += qA;
+    coef[0] = (R)sigtA;
+    for (int m = 0; m < 4; ++m)
+      for (int k = 0; k < 5; ++k) coef[(1 + 5 * m + k) * cstride] = (R)cf[m][k];
+  } else {
+    const double x0 = raw[0], u1 = raw[1], u2 = raw[2], d1 = raw[3], d2 = raw[4];
+    const double da = hy * (raw[5] - raw[6]);  // h_y (a_K - a_left)
+    const double db = hx * (raw[7] - raw[8]);  // h_x (b_K - b_down)
+    const double sigtA = raw[9], absA = raw[10], scatA = raw[11], qA = raw[12];
+    double c0, c1, c2, c3 = 0.0, c4 = 0.0;
+    if (!defect) {
+      c0 = scatA * x0 + qA;
+      c1 = da;
+      c2 = db;
+    } else {
+      double tx = x0, txu = u1, ty = x0, tyd = d1;
+      if (S == LMDG_SCHEME_RLMDG) {
+        tx = x0 + (c == 0 ? 1.0 : 0.5) * (x0 - u1);
+        ty = x0 + (jr == 0 ? 1.0 : 0.5) * (x0 - d1);
+        txu = c > 0 ? u1 + (c == 1 ? 1.0 : 0.5) * (u1 - u2) : 0.0;
+        tyd = jr > 0 ? d1 + (jr == 1 ? 1.0 : 0.5) * (d1 - d2) : 0.0;
+      }
+      c0 = absA * x0 + qA;
+      c1 = -da;
+      c2 = -db;
+      c3 = hy * (tx - txu);
+      c4 = hx * (ty - tyd);
+    }
+    coef[0] = (R)sigtA;
+    coef[1 * cstride] = (R)c0;
+    coef[2 * cstride] = (R)c1;
+    coef[3 * cstride] = (R)c2;
+    coef[4 * cstride] = (R)c3;
+    coef[5 * cstride] = (R)c4;
+  }
+}
+
+// Reciprocal from a hardware estimate refined by Newton steps r <- r + r (1 - d r);
+// the denominators of the low-memory sweeps do not depend on the upwind values, so
+// this runs off the step's dependency chain.  FP64: the single-precision estimate
+// (about 23 correct bits) doubles its correct bits with each of two FP64 steps.
+__device__ __forceinline__ double recip(double d) {
+  double r = (double)__builtin_amdgcn_rcpf((float)d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float d) {
+  float r = __builtin_amdgcn_rcpf(d);
+  const float e = fmaf(-d, r, 1.0f);
+  return fmaf(r, e, r);
+}
+
+// MAXW bounds the waves per workgroup so that small direction sets get more registers.
+template <typename R, int S, int MAXW>
+__global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
   constexpr int NOUT = SchemeTraits<S>::NOUT;
   constexpr int NF = SchemeTraits<S>::NF;
+  constexpr int NS = SrcTraits<S>::NS;
+  constexpr int NC = SrcTraits<S>::NC;
+  constexpr int NRAW = SrcTraits<S>::NRAW;
+  constexpr int MAXC = SrcTraits<S>::MAXC;
+  constexpr bool LM = S != LMDG_SCHEME_STD;
   extern __shared__ unsigned char smem_raw[];
-  R* red = reinterpret_cast<R*>(smem_raw);  // [cw][W][NOUT][16]
   __shared__ int s_item;
 
   const int tid = threadIdx.x;
@@ -305,6 +414,15 @@ __global__ void __launch_bounds__(1024) sweep2d_kernel(SweepParams<R> P) {
   const int slot = wv * 4 + (lane >> 4);
   const long long nc = P.ncell;
   const int nx = P.nx, ny = P.ny;
+  const int lcw = P.lcw;
+  const int cw = 1 << lcw;
+  const int ncells = kRows << lcw;  // cells staged per chunk
+  // LDS: red [cw][W][NOUT][16] | coef [2][NC][cw][16] | eds [cw][NF][dslots]
+  // (coefficients structure-of-arrays: the 16 rows of one value are contiguous, so
+  // 64-bit reads by the 16 rows of a wave hit distinct banks)
+  R* red = reinterpret_cast<R*>(smem_raw);
+  R* coef = red + (size_t)cw * W * NOUT * kRows;
+  R* eds = coef + (size_t)2 * ncells * NC;
 
   for (;;) {
     if (tid == 0) s_item = (int)(atomicAdd(P.ticket, 1u) - P.ticket_base);
@@ -321,6 +439,10 @@ __global__ void __launch_bounds__(1024) sweep2d_kernel(SweepParams<R> P) {
       const double* e = P.dirs + ((long long)q * P.dslots + slot) * kDirStride;
       d.ox = e[0];
       d.oy = e[1];
+      d.rox = (R)d.ox;
+      d.roy = (R)d.oy;
+      d.aox = (R)fabs(d.ox);
+      d.aoy = (R)fabs(d.oy);
       d.w = (R)e[2];
       d.idx = (int)e[3];
       d.axhy = (R)(fabs(d.ox) * P.hy);
@@ -335,14 +457,41 @@ __global__ void __launch_bounds__(1024) sweep2d_kernel(SweepParams<R> P) {
     const int j = syi > 0 ? jr : ny - 1 - jr;
     const R ky = (jr == 0) ? R(1) : R(0.5);
 
+    // staging of chunk k's cells: thread handles cells e = tid + m * blockDim,
+    // e -> (row e / cw, step e % cw) so consecutive threads read consecutive columns
+    double raw[MAXC][NRAW];
+    auto stage_load = [&](int k) {
+#pragma unroll
+      for (int m = 0; m < MAXC; ++m) {
+        const int e = tid + m * blockDim.x;
+        const int rr = e >> lcw, tt = e & (cw - 1);
+        const int c = (e < ncells) ? (k << lcw) + tt - rr : -1;
+        raw_load<R, S>(P, sxi, syi, c, s * kRows + rr, raw[m]);
+      }
+    };
+    auto stage_store = [&](int k, int buf) {
+#pragma unroll
+      for (int m = 0; m < MAXC; ++m) {
+        const int e = tid + m * blockDim.x;
+        if (e < ncells) {
+          const int rr = e >> lcw, tt = e & (cw - 1);
+          raw_coef<R, S>(raw[m], (k << lcw) + tt - rr, s * kRows + rr, sxi, syi, P.hx, P.hy, P.defect != 0,
+                         coef + (size_t)buf * NC * ncells + (tt << 4) + rr, ncells);
+        }
+      }
+    };
+
     R xin[NF], yprev[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) { xin[f] = 0; yprev[f] = 0; }
 
+    stage_load(0);
+    stage_store(0, 0);
     for (int k = 0; k < P.nchunks; ++k) {
-      const int t0 = k * P.cw;
+      const int t0 = k << lcw;
+      const int buf = k & 1;
       if (s > 0 && tid == 0) {
-        const int need = min(nx, t0 + P.cw);
+        const int need = min(nx, t0 + cw);
         const unsigned long long target = (P.epoch << 32) | (unsigned long long)need;
         const unsigned long long* flag = P.prog + (long long)q * P.nstrips + (s - 1);
         long long spins = 0;
@@ -353,88 +502,145 @@ __global__ void __launch_bounds__(1024) sweep2d_kernel(SweepParams<R> P) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       __syncthreads();
+      // traces of the strip below for the columns of this chunk (zero for the first strip)
+      {
+        const int ne = (cw * NF) * P.dslots;
+        const R* src = P.edge + (((long long)q * P.nstrips + (s - 1)) * nx + t0) * NF * P.dslots;
+        for (int e = tid; e < ne; e += blockDim.x) {
+          const int c = t0 + e / (NF * P.dslots);
+          eds[e] = (s > 0 && c < nx) ? load_agent(src + e) : R(0);
+        }
+      }
+      if (k + 1 < P.nchunks) stage_load(k + 1);  // overlaps the step loop below
+      __syncthreads();
 
-      for (int tt = 0; tt < P.cw; ++tt) {
-        const int c = t0 + tt - r;
-        const bool act = row_ok && c >= 0 && c < nx;
-        R ydn[NF];
+      const R* cbuf = coef + (size_t)buf * NC * ncells;
+      // Steps run in fully unrolled groups of U: the source, sigma_t, reciprocal of the
+      // denominator and strip-below trace of all U steps (none depends on upwind
+      // values) are formed first as independent chains, then the U dependent steps
+      // follow; the body has no branches except the stores after each group, so one
+      // wave can overlap the latencies itself.
+      constexpr int U = kStepGroup;
+      for (int tg = 0; tg < cw; tg += U) {
+        R src_g[U][NS], sig_g[U], inv_g[U], edn_g[U][NF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) ydn[f] = shr1(yprev[f]);
-        if (r == 0) {
-          if (act && s > 0) {
-            const R* e = P.edge + ((((long long)q * P.nstrips + (s - 1)) * nx + c) * NF) * P.dslots + slot;
+        for (int u = 0; u < U; ++u) {
+          const int tt = tg + u;
+          const R* cf = cbuf + (tt << 4) + r;
+          sig_g[u] = cf[0];
 #pragma unroll
-            for (int f = 0; f < NF; ++f) ydn[f] = load_agent(e + (long long)f * P.dslots);
-          } else {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) ydn[f] = 0;
+          for (int m = 0; m < NS; ++m) {
+            const R* a = cf + (size_t)(1 + 5 * m) * ncells;
+            src_g[u][m] = a[0] + d.rox * a[ncells] + d.roy * a[2 * ncells] + d.aox * a[3 * ncells] +
+                          d.aoy * a[4 * ncells];
           }
+          if constexpr (S == LMDG_SCHEME_LMDG) {
+            inv_g[u] = recip(sig_g[u] + d.axhy + d.ayhx);
+          } else if constexpr (S == LMDG_SCHEME_RLMDG) {
+            const R kx = (t0 + tt - r == 0) ? R(1) : R(0.5);
+            inv_g[u] = recip(sig_g[u] + d.axhy * (R(1) + kx) + d.ayhx * (R(1) + ky));
+          } else {
+            inv_g[u] = R(0);
+          }
+#pragma unroll
+          for (int f = 0; f < NF; ++f) edn_g[u][f] = eds[((tt * NF) + f) * P.dslots + slot];
         }
-        if (c == 0) {
+        R yo_g[U][NF], psi_g[U][4];
 #pragma unroll
-          for (int f = 0; f < NF; ++f) xin[f] = 0;
-        }
-        R o[NOUT], xo[NF], yo[NF];
+        for (int u = 0; u < U; ++u) {
+          const int tt = tg + u;
+          const int c = t0 + tt - r;
+          const bool act = row_ok && c >= 0 && c < nx;
+          const R inv = inv_g[u];
+          R ydn[NF];
 #pragma unroll
-        for (int m = 0; m < NOUT; ++m) o[m] = 0;
-#pragma unroll
-        for (int f = 0; f < NF; ++f) { xo[f] = xin[f]; yo[f] = 0; }
-        if (act) {
-          const int i = sxi > 0 ? c : nx - 1 - c;
-          const long long cell = (long long)j * nx + i;
-          const double sigtA = P.sigtA[cell];
-          const long long sxs = sxi, sys = (long long)syi * nx;  // cell - sxs / - sys = upwind
+          for (int f = 0; f < NF; ++f) {
+            const R v = shr1(yprev[f]);
+            ydn[f] = (r == 0) ? edn_g[u][f] : v;
+            xin[f] = (c == 0) ? R(0) : xin[f];
+          }
+          R o[NOUT], xo[NF], yo[NF];
           if constexpr (S == LMDG_SCHEME_STD) {
-            R src[4];
-            double sd[4] = {0, 0, 0, 0};
-            if (P.x)
-              std_source(P.x, nc, cell, sxs, sys, c, jr, P.scatA[cell], P.absA[cell], d.ox, d.oy, P.hx, P.hy,
-                         P.defect != 0, sd);
-            if (P.qA) sd[0] += P.qA[cell];
-            src[0] = (R)sd[0]; src[1] = (R)sd[1]; src[2] = (R)sd[2]; src[3] = (R)sd[3];
-            R cf[4];
-            cell_std<R>(d, src, (R)sigtA, xin, ydn, xo, yo, o, cf);
-            if (P.psi && d.idx >= 0) {
-#pragma unroll
-              for (int m = 0; m < 4; ++m) P.psi[((long long)d.idx * 4 + m) * nc + cell] = (double)cf[m];
-            }
+            cell_std<R>(d, src_g[u], sig_g[u], xin, ydn, xo, yo, o, psi_g[u]);
+          } else if constexpr (S == LMDG_SCHEME_LMDG) {
+            const R psi = (src_g[u][0] + d.axhy * xin[0] + d.ayhx * ydn[0]) * inv;
+            xo[0] = psi;
+            yo[0] = psi;
+            o[0] = d.w * psi;
+            o[1] = d.w * d.oxhy * (xin[0] - psi);
+            o[2] = d.w * d.oyhx * (ydn[0] - psi);
+            psi_g[u][0] = psi;
           } else {
-            double src = 0;
-            if (P.x)
-              src = lm_source<S == LMDG_SCHEME_RLMDG>(P.x, nc, cell, sxs, sys, c, jr, P.scatA[cell], P.absA[cell],
-                                                      d.ox, d.oy, P.hx, P.hy, P.defect != 0);
-            if (P.qA) src += P.qA[cell];
-            R psi;
-            if constexpr (S == LMDG_SCHEME_LMDG) {
-              cell_lmdg<R>(d, (R)src, (R)sigtA, xin, ydn, xo, yo, o, psi);
-            } else {
-              const R kx = (c == 0) ? R(1) : R(0.5);
-              cell_rlmdg<R>(d, (R)src, (R)sigtA, kx, ky, xin, ydn, xo, yo, o, psi);
-            }
-            if (P.psi && d.idx >= 0) P.psi[(long long)d.idx * nc + cell] = (double)psi;
+            const R kx = (c == 0) ? R(1) : R(0.5);
+            const R third = R(1) / R(3);
+            const R psi =
+                (src_g[u][0] + d.axhy * (xin[0] + kx * xin[2]) + d.ayhx * (ydn[0] + ky * ydn[2])) * inv;
+            const R cxi = d.sx * kx * (psi - xin[2]);
+            const R ceta = d.sy * ky * (psi - ydn[2]);
+            xo[0] = psi + kx * (psi - xin[2]);
+            xo[1] = ceta;
+            xo[2] = psi;
+            yo[0] = psi + ky * (psi - ydn[2]);
+            yo[1] = cxi;
+            yo[2] = psi;
+            const R sA3 = sig_g[u] * third;
+            o[0] = d.w * psi;
+            o[1] = d.w * (d.oxhy * (xin[0] - psi) + (sA3 + d.axhy + d.ayhx * third) * cxi - d.ayhx * third * ydn[1]);
+            o[2] = d.w * (d.oyhx * (ydn[0] - psi) + (sA3 + d.ayhx + d.axhy * third) * ceta - d.axhy * third * xin[1]);
+            o[3] = d.w * third * (d.oxhy * (xin[1] - ceta) + d.oyhx * (ydn[1] - cxi));
+            o[4] = d.w * cxi;
+            o[5] = d.w * ceta;
+            psi_g[u][0] = psi;
+          }
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            xin[f] = xo[f];
+            yprev[f] = yo[f];
+            yo_g[u][f] = yo[f];
+          }
+#pragma unroll
+          for (int m = 0; m < NOUT; ++m) o[m] = quad_sum(act ? o[m] : R(0));
+          if (lane < kRows) {  // the four lanes of a row hold the same sum
+#pragma unroll
+            for (int m = 0; m < NOUT; ++m) red[((tt * W + wv) * NOUT + m) * kRows + r] = o[m];
           }
         }
+        if (r == kRows - 1 && s + 1 < P.nstrips) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) { xin[f] = xo[f]; yprev[f] = yo[f]; }
+          for (int u = 0; u < U; ++u) {
+            const int c = t0 + tg + u - r;
+            if (row_ok && c >= 0 && c < nx) {
+              R* e = P.edge + ((((long long)q * P.nstrips + s) * nx + c) * NF) * P.dslots + slot;
 #pragma unroll
-        for (int m = 0; m < NOUT; ++m) o[m] = quad_sum(o[m]);
-        if (lane < 16) {
-#pragma unroll
-          for (int m = 0; m < NOUT; ++m) red[((tt * W + wv) * NOUT + m) * kRows + r] = o[m];
+              for (int f = 0; f < NF; ++f) store_agent(e + (long long)f * P.dslots, yo_g[u][f]);
+            }
+          }
         }
-        if (r == kRows - 1 && act && s + 1 < P.nstrips) {
-          R* e = P.edge + ((((long long)q * P.nstrips + s) * nx + c) * NF) * P.dslots + slot;
+        if (P.psi && d.idx >= 0) {
 #pragma unroll
-          for (int f = 0; f < NF; ++f) store_agent(e + (long long)f * P.dslots, yo[f]);
+          for (int u = 0; u < U; ++u) {
+            const int c = t0 + tg + u - r;
+            if (row_ok && c >= 0 && c < nx) {
+              const int i = sxi > 0 ? c : nx - 1 - c;
+              const long long cell = (long long)j * nx + i;
+              if constexpr (LM) {
+                P.psi[(long long)d.idx * nc + cell] = (double)psi_g[u][0];
+              } else {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) P.psi[((long long)d.idx * 4 + m) * nc + cell] = (double)psi_g[u][m];
+              }
+            }
+          }
         }
       }
       __syncthreads();
+      if (k + 1 < P.nchunks) stage_store(k + 1, buf ^ 1);
       // sums over waves, written with consecutive threads on consecutive columns
-      const int nred = P.cw * NOUT * kRows;
+      const int nred = (NOUT * kRows) << lcw;
       for (int e = tid; e < nred; e += blockDim.x) {
-        const int tt = e % P.cw;
-        const int m = (e / P.cw) % NOUT;
-        const int rr = e / (P.cw * NOUT);
+        const int tt = e & (cw - 1);
+        const int m = (e >> lcw) % NOUT;
+        const int rr = (e >> lcw) / NOUT;
         const int c = t0 + tt - rr;
         const int jr2 = s * kRows + rr;
         if (jr2 < ny && c >= 0 && c < nx) {
@@ -446,29 +652,40 @@ __global__ void __launch_bounds__(1024) sweep2d_kernel(SweepParams<R> P) {
         }
       }
       if (s + 1 < P.nstrips && tid == 0) {
-        const int done = min(nx, t0 + P.cw - (kRows - 1));
+        const int done = min(nx, t0 + cw - (kRows - 1));
         if (done > 0) {
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
           store_agent(P.prog + (long long)q * P.nstrips + s, (P.epoch << 32) | (unsigned long long)done);
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
 }
 
 template <typename R, int S>
-int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipStream_t st, bool defect) {
+size_t lds_bytes(int cw, int W, int dslots) {
   constexpr int NOUT = SchemeTraits<S>::NOUT;
+  constexpr int NF = SchemeTraits<S>::NF;
+  constexpr int NC = SrcTraits<S>::NC;
+  return ((size_t)cw * W * NOUT * kRows + (size_t)2 * cw * kRows * NC + (size_t)cw * NF * dslots) * sizeof(R);
+}
+
+template <typename R, int S>
+int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipStream_t st, bool defect) {
   SweepParams<R> P;
   P.nx = (int)h->n[0];
   P.ny = (int)h->n[1];
   P.nstrips = h->nstrips;
   P.dslots = h->dslots;
   const int W = h->waves;
+  // chunk length: at most MAXC staged cells per thread and 64 KB of LDS
   int cw = 16;
-  while (cw > 4 && (size_t)cw * W * NOUT * kRows * sizeof(R) > 64 * 1024) cw >>= 1;
+  while (cw > kStepGroup && (kRows * cw > SrcTraits<S>::MAXC * 64 * W || lds_bytes<R, S>(cw, W, h->dslots) > 64 * 1024))
+    cw >>= 1;
   P.cw = cw;
+  P.lcw = 0;
+  while ((1 << P.lcw) < cw) ++P.lcw;
   P.nchunks = (P.nx + kRows - 1 + cw - 1) / cw;
   P.n_items = 4 * h->nstrips;
   P.hx = h->h[0];
@@ -490,7 +707,7 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   P.epoch = h->epoch;
   P.ticket_base = h->ticket_base;
   const int grid = std::min(P.n_items, 4 * h->n_cu);
-  const size_t lds = (size_t)cw * W * NOUT * kRows * sizeof(R);
+  const size_t lds = lds_bytes<R, S>(cw, W, h->dslots);
   hipEvent_t ev_end = nullptr;
   if (h->profiling) {
     if (h->ev_used + 2 > h->ev_pool.size()) {
@@ -504,7 +721,10 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
     ev_end = h->ev_pool[h->ev_used + 1];
     h->ev_used += 2;
   }
-  hipLaunchKernelGGL((sweep2d_kernel<R, S>), dim3(grid), dim3(64 * W), lds, st, P);
+  if (W <= 4)
+    hipLaunchKernelGGL((sweep2d_kernel<R, S, 4>), dim3(grid), dim3(64 * W), lds, st, P);
+  else
+    hipLaunchKernelGGL((sweep2d_kernel<R, S, kMaxWaves>), dim3(grid), dim3(64 * W), lds, st, P);
   if (ev_end) hipEventRecord(ev_end, st);
   h->epoch += 1;
   h->ticket_base += (unsigned)(P.n_items + grid);

@@ -118,9 +118,10 @@ void lmdg_destroy(lmdg_t* h);
 /*
  * Cross sections and source (device arrays, n_cells each, copied into the handle):
  * sigma_s >= 0, sigma_a >= 0, eps > 0 per cell (eq-main; a per-cell eps describes a
- * multiscale medium), q = per-cell constant source.  sigma_a may be 0 only if
- * sigma_s > 0 in the same cell is not required by the algebra but the paper's
- * analysis assumes sigma_a >= delta_a > 0.  alpha must be NULL (vacuum inflow).
+ * multiscale medium), q = per-cell constant source.  sigma_a = 0 is accepted;
+ * the paper's analysis assumes sigma_a >= delta_a > 0, and without absorption the
+ * reduced systems can be arbitrarily ill-conditioned.  alpha must be NULL (vacuum
+ * inflow).
  * Errors: INVALID_ARG (NULL, negative or non-finite values, eps <= 0),
  *         UNSUPPORTED (alpha != NULL).
  */
@@ -174,6 +175,36 @@ int lmdg_recover(lmdg_t* h, int scheme, int prec, const double* x, double* phi,
 int lmdg_solve(lmdg_t* h, int scheme, int mode, double tol, int restart, int max_iter,
                const double* x0, double* x_out, double* phi_out, lmdg_info* info,
                void* stream);
+
+/*
+ * Detector response and its gradients (Galerkin schemes STD and LMDG).
+ * J = int_D phi_h d dx for detector moments det (device moment vector,
+ * det[r*n_cells + p] = int_{K_p} d b_r dx; for the indicator of a box, the exact
+ * integral of each basis function over the part of the cell inside the box).
+ * The scheme's discrete system A y = b (eq-sndg-scheme; eq-lmdg-block with the
+ * trial map of eq-gene-scheme) is solved forward, then A^T lambda = dJ/dy, and the
+ * derivatives of the bilinear form of eq-Ljk with respect to the per-cell data give
+ *   g_sigma_a = -eps sum_l w_l int_K psi_l lambda_l,
+ *   g_sigma_s = -(1/eps) (sum_l w_l int_K psi_l lambda_l - int_K phi Lambda),
+ *   g_q       =  eps int_K Lambda           (Lambda = sum_l w_l lambda_l),
+ * i.e. dJ/d(sigma_s, sigma_a, q) of cell K for the discrete J.  Both solves use
+ * mode, tol, restart and max_iter as lmdg_solve does.  The quadrature must be
+ * centrally symmetric (-Omega with the same weight for every Omega): the adjoint
+ * sweep of direction Omega is then the forward sweep of -Omega.
+ *   det                device, 4 * n_cells doubles (moment-major)
+ *   g_sigma_s, g_sigma_a, g_q   device outputs, n_cells doubles each
+ *   J_out              host output
+ *   info               host; iterations, restarts and passes summed over both solves
+ * The handle keeps both angular fluxes (2 n_dir n_cells doubles for LMDG, 8 n_dir
+ * n_cells for STD) after the first call.
+ * Errors: UNSUPPORTED (RLMDG: its adjoint is Petrov-Galerkin), INVALID_ARG (NULL
+ * pointers, bad solver arguments, quadrature without central symmetry),
+ * NOT_CONVERGED (either solve, or the conjugate gradients of B_11 that give the
+ * slope part of the LMDG adjoint source), HIP_ERROR.
+ */
+int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, double tol,
+                       int restart, int max_iter, double* g_sigma_s, double* g_sigma_a,
+                       double* g_q, double* J_out, lmdg_info* info, void* stream);
 
 /*
  * Kernel timing for measurement: while enabled, every sweep-kernel launch of this

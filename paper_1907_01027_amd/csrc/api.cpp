@@ -300,6 +300,15 @@ int lmdg_create(int dim, const int64_t* n, const double* length, int n_dir, cons
     h->qax[q] += w[l] * std::fabs(omega[2 * l]);
     h->qay[q] += w[l] * std::fabs(omega[2 * l + 1]);
   }
+  // -Omega_l for every l (central symmetry), used by the adjoint; -1 when absent
+  h->neg_dir.assign(n_dir, -1);
+  for (int l = 0; l < n_dir; ++l)
+    for (int k = 0; k < n_dir; ++k)
+      if (std::fabs(omega[2 * k] + omega[2 * l]) <= 1e-12 && std::fabs(omega[2 * k + 1] + omega[2 * l + 1]) <= 1e-12 &&
+          std::fabs(w[k] - w[l]) <= 1e-12 * w[l]) {
+        h->neg_dir[l] = k;
+        break;
+      }
   int dev = 0;
   hipGetDevice(&dev);
   h->device = dev;
@@ -320,6 +329,14 @@ int lmdg_create(int dim, const int64_t* n, const double* length, int n_dir, cons
   alloc((void**)&h->ws.ticket, sizeof(unsigned int));
   alloc((void**)&h->ws.err, sizeof(int));
   alloc((void**)&h->ws.vec, (size_t)kScratchVecs * 4 * nc * sizeof(double));
+  alloc((void**)&h->d_adjtab, (size_t)2 * n_dir * sizeof(double));
+  std::vector<double> adjtab(2 * n_dir);
+  for (int l = 0; l < n_dir; ++l) {
+    adjtab[2 * l] = w[l];
+    adjtab[2 * l + 1] = h->neg_dir[l] >= 0 ? h->neg_dir[l] : l;
+  }
+  if (st == LMDG_OK) st = check_hip(h, hipMemcpy(h->d_adjtab, adjtab.data(), adjtab.size() * sizeof(double),
+                                                 hipMemcpyHostToDevice), "copy direction map");
   if (st == LMDG_OK) st = check_hip(h, hipMemcpy(h->d_dirs, tab.data(), tab.size() * sizeof(double),
                                                  hipMemcpyHostToDevice), "copy directions");
   if (st == LMDG_OK) st = check_hip(h, hipMemset(h->ws.prog, 0, (size_t)4 * h->nstrips * 8), "clear flags");
@@ -338,7 +355,8 @@ void lmdg_destroy(lmdg_t* h) {
   if (!h) return;
   hipDeviceSynchronize();
   void* ptrs[] = {h->d_dirs, h->d_sigtA, h->d_scatA, h->d_absA, h->d_qA, h->ws.part, h->ws.edge,
-                  h->ws.prog, h->ws.ticket, h->ws.err, h->ws.vec, h->d_krylov, h->d_small};
+                  h->ws.prog, h->ws.ticket, h->ws.err, h->ws.vec, h->d_krylov, h->d_small,
+                  h->d_epsA, h->d_adjtab, h->d_psi_f, h->d_psi_a, h->d_cvec};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (h->h_small) hipHostFree(h->h_small);
@@ -362,7 +380,7 @@ int lmdg_set_materials(lmdg_t* h, const double* sigma_s, const double* sigma_a, 
                    "read materials");
   if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "read materials");
   if (rc != LMDG_OK) return rc;
-  std::vector<double> sigtA(nc), scatA(nc), absA(nc), qA(nc);
+  std::vector<double> sigtA(nc), scatA(nc), absA(nc), qA(nc), epsA(nc);
   for (long long p = 0; p < nc; ++p) {
     if (!std::isfinite(ss[p]) || !std::isfinite(sa[p]) || !std::isfinite(ep[p]) || !std::isfinite(qq[p]))
       return set_error(h, LMDG_NONFINITE, "non-finite material value at cell " + std::to_string(p));
@@ -373,10 +391,11 @@ int lmdg_set_materials(lmdg_t* h, const double* sigma_s, const double* sigma_a, 
     scatA[p] = ss[p] / ep[p] * h->area;
     absA[p] = ep[p] * sa[p] * h->area;
     qA[p] = ep[p] * qq[p] * h->area;
+    epsA[p] = ep[p] * h->area;
   }
-  double** tgt[4] = {&h->d_sigtA, &h->d_scatA, &h->d_absA, &h->d_qA};
-  std::vector<double>* vals[4] = {&sigtA, &scatA, &absA, &qA};
-  for (int k = 0; k < 4 && rc == LMDG_OK; ++k) {
+  double** tgt[5] = {&h->d_sigtA, &h->d_scatA, &h->d_absA, &h->d_qA, &h->d_epsA};
+  std::vector<double>* vals[5] = {&sigtA, &scatA, &absA, &qA, &epsA};
+  for (int k = 0; k < 5 && rc == LMDG_OK; ++k) {
     if (!*tgt[k]) rc = check_hip(h, hipMalloc((void**)tgt[k], nc * sizeof(double)), "hipMalloc materials");
     if (rc == LMDG_OK)
       rc = check_hip(h, hipMemcpyAsync(*tgt[k], vals[k]->data(), nc * sizeof(double), hipMemcpyHostToDevice, st),
@@ -459,6 +478,18 @@ int norm2(lmdg_t* h, const double* v, long long n, double* out, hipStream_t st) 
   int rc = check_hip(h, hipMemcpyAsync(hres, dres, sizeof(double), hipMemcpyDeviceToHost, st), "norm");
   if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "norm");
   *out = std::sqrt(std::max(0.0, *hres));
+  return rc;
+}
+
+// a . b via the dot kernels, synchronising the stream.
+int dot(lmdg_t* h, const double* a, const double* b, long long n, double* out, hipStream_t st) {
+  double* part = h->d_small + 256;
+  double* dres = h->d_small + h->small_doubles - 1;
+  double* hres = h->h_small + h->small_doubles - 1;
+  lmdg::vec_dots(a, n, 1, b, n, part, dres, st);
+  int rc = check_hip(h, hipMemcpyAsync(hres, dres, sizeof(double), hipMemcpyDeviceToHost, st), "dot");
+  if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "dot");
+  *out = *hres;
   return rc;
 }
 
@@ -643,22 +674,26 @@ int lmdg_recover(lmdg_t* h, int scheme, int prec, const double* x, double* phi, 
   return check_hip(h, hipGetLastError(), "recover");
 }
 
-int lmdg_solve(lmdg_t* h, int scheme, int mode, double tol, int restart, int max_iter, const double* x0,
-               double* x_out, double* phi_out, lmdg_info* info, void* stream) {
-  int rc = check_call(h, scheme, LMDG_PREC_FP64);
-  if (rc != LMDG_OK) return rc;
-  if (!x_out || !(tol > 0) || restart < 1 || restart > 250 || max_iter < 1 ||
-      (mode != LMDG_MODE_FP64 && mode != LMDG_MODE_MIXED))
-    return set_error(h, LMDG_INVALID_ARG, "bad solve arguments");
-  hipStream_t st = (hipStream_t)stream;
-  rc = ensure_small(h, small_size(restart));
+// The solve behind lmdg_solve and lmdg_adjoint_solve.  rhs_x (nullable) is the
+// moment vector the right-hand-side sweep takes (Step 1's -Sigma^T c term when the
+// source has slope moments); cshift (nullable) is c, removed from x before recovery
+// (Psi_0 = L_00^{-1}(M_0 X_0 + L_01 Sigma^T (X_1 - c) + Q_0), Phi_1 = c - X_1).
+static int solve_impl(lmdg_t* h, int scheme, int mode, double tol, int restart, int max_iter, const double* x0,
+                      double* x_out, double* phi_out, double* psi_out, lmdg_info* info, hipStream_t st,
+                      const double* rhs_x, const double* cshift) {
+  int rc = ensure_small(h, small_size(restart));
   if (rc != LMDG_OK) return rc;
   const auto t_start = std::chrono::steady_clock::now();
   const long long N = 4 * h->ncell;
   double* b = h->ws.vec;
   double* r = h->ws.vec + N;
   double* d = h->ws.vec + 2 * N;
-  rc = lmdg_rhs(h, scheme, LMDG_PREC_FP64, b, st);
+  if (!rhs_x) {
+    rc = lmdg_rhs(h, scheme, LMDG_PREC_FP64, b, st);
+  } else {
+    rc = lmdg::launch_sweep(h, scheme, LMDG_PREC_FP64, rhs_x, true, nullptr, st);
+    if (rc == LMDG_OK) lmdg::launch_combine(h, scheme, LMDG_PREC_FP64, lmdg::kRhs, nullptr, b, st);
+  }
   if (rc != LMDG_OK) return rc;
   if (x0) lmdg::vec_copy(x_out, x0, N, st); else lmdg::vec_fill(x_out, 0.0, N, st);
   GmresStats stats;
@@ -698,7 +733,16 @@ int lmdg_solve(lmdg_t* h, int scheme, int mode, double tol, int restart, int max
       lmdg::vec_axpby(x_out, 1.0, d, 1.0, N, st);
     }
   }
-  if (rc == LMDG_OK && phi_out) rc = lmdg_recover(h, scheme, LMDG_PREC_FP64, x_out, phi_out, nullptr, st);
+  if (rc == LMDG_OK && phi_out) {
+    const double* xr = x_out;
+    if (cshift) {
+      double* t = h->ws.vec + 3 * N;
+      lmdg::vec_copy(t, x_out, N, st);
+      lmdg::vec_axpby(t, -1.0, cshift, 1.0, N, st);
+      xr = t;
+    }
+    rc = lmdg_recover(h, scheme, LMDG_PREC_FP64, xr, phi_out, psi_out, st);
+  }
   if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "solve");
   const double total =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
@@ -713,6 +757,136 @@ int lmdg_solve(lmdg_t* h, int scheme, int mode, double tol, int restart, int max
   }
   if (rc != LMDG_OK) return rc;
   return conv ? LMDG_OK : set_error(h, LMDG_NOT_CONVERGED, "tolerance not reached");
+}
+
+int lmdg_solve(lmdg_t* h, int scheme, int mode, double tol, int restart, int max_iter, const double* x0,
+               double* x_out, double* phi_out, lmdg_info* info, void* stream) {
+  int rc = check_call(h, scheme, LMDG_PREC_FP64);
+  if (rc != LMDG_OK) return rc;
+  if (!x_out || !(tol > 0) || restart < 1 || restart > 250 || max_iter < 1 ||
+      (mode != LMDG_MODE_FP64 && mode != LMDG_MODE_MIXED))
+    return set_error(h, LMDG_INVALID_ARG, "bad solve arguments");
+  return solve_impl(h, scheme, mode, tol, restart, max_iter, x0, x_out, phi_out, nullptr, info, (hipStream_t)stream,
+                    nullptr, nullptr);
+}
+
+// Conjugate gradients on B_11 c = f_1 (B_11 symmetric positive definite, Sec. 3.2);
+// vectors in the moment-major layout with slot 0 held at zero.  Uses ws.vec[0..3).
+static int cg_b11(lmdg_t* h, const double* f, double* c, double rtol, hipStream_t st) {
+  const long long nc = h->ncell, N = 4 * nc;
+  double* r = h->ws.vec;
+  double* p = h->ws.vec + N;
+  double* Ap = h->ws.vec + 2 * N;
+  lmdg::vec_copy(r, f, N, st);
+  lmdg::vec_fill(r, 0.0, nc, st);
+  lmdg::vec_fill(c, 0.0, N, st);
+  double rr;
+  int rc = dot(h, r, r, N, &rr, st);
+  if (rc != LMDG_OK) return rc;
+  const double bn = std::sqrt(rr);
+  if (bn == 0.0) return LMDG_OK;
+  lmdg::vec_copy(p, r, N, st);
+  for (int it = 0; it < 100000; ++it) {
+    lmdg::launch_b11(h, p, Ap, st);
+    double pAp;
+    rc = dot(h, p, Ap, N, &pAp, st);
+    if (rc != LMDG_OK) return rc;
+    if (!(pAp > 0)) return set_error(h, LMDG_NONFINITE, "B_11 conjugate gradients broke down");
+    const double alpha = rr / pAp;
+    lmdg::vec_axpby(c, alpha, p, 1.0, N, st);
+    lmdg::vec_axpby(r, -alpha, Ap, 1.0, N, st);
+    double rr_new;
+    rc = dot(h, r, r, N, &rr_new, st);
+    if (rc != LMDG_OK) return rc;
+    if (std::sqrt(rr_new) <= rtol * bn) return LMDG_OK;
+    lmdg::vec_axpby(p, 1.0, r, rr_new / rr, N, st);
+    rr = rr_new;
+  }
+  return set_error(h, LMDG_NOT_CONVERGED, "B_11 conjugate gradients did not converge");
+}
+
+int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, double tol, int restart, int max_iter,
+                       double* g_sigma_s, double* g_sigma_a, double* g_q, double* J_out, lmdg_info* info,
+                       void* stream) {
+  int rc = check_call(h, scheme, LMDG_PREC_FP64);
+  if (rc != LMDG_OK) return rc;
+  if (scheme == LMDG_SCHEME_RLMDG)
+    return set_error(h, LMDG_UNSUPPORTED, "the adjoint covers the Galerkin schemes (standard, LMDG)");
+  if (!det || !g_sigma_s || !g_sigma_a || !g_q || !J_out || !(tol > 0) || restart < 1 || restart > 250 ||
+      max_iter < 1 || (mode != LMDG_MODE_FP64 && mode != LMDG_MODE_MIXED))
+    return set_error(h, LMDG_INVALID_ARG, "bad adjoint arguments");
+  for (int l = 0; l < h->ndir; ++l)
+    if (h->neg_dir[l] < 0) return set_error(h, LMDG_INVALID_ARG, "quadrature is not centrally symmetric");
+  hipStream_t st = (hipStream_t)stream;
+  const long long nc = h->ncell, N = 4 * nc;
+  const int npsi = scheme == LMDG_SCHEME_STD ? 4 : 1;
+  const size_t psi_doubles = (size_t)h->ndir * npsi * nc;
+  if (h->psi_doubles < psi_doubles) {
+    if (h->d_psi_f) hipFree(h->d_psi_f);
+    if (h->d_psi_a) hipFree(h->d_psi_a);
+    h->d_psi_f = h->d_psi_a = nullptr;
+    h->psi_doubles = 0;
+    rc = check_hip(h, hipMalloc((void**)&h->d_psi_f, psi_doubles * sizeof(double)), "hipMalloc psi");
+    if (rc == LMDG_OK) rc = check_hip(h, hipMalloc((void**)&h->d_psi_a, psi_doubles * sizeof(double)), "hipMalloc psi");
+    if (rc != LMDG_OK) return rc;
+    h->psi_doubles = psi_doubles;
+  }
+  if (!h->d_cvec) {
+    rc = check_hip(h, hipMalloc((void**)&h->d_cvec, (size_t)4 * N * sizeof(double)), "hipMalloc adjoint vectors");
+    if (rc != LMDG_OK) return rc;
+  }
+  rc = ensure_small(h, small_size(restart));
+  if (rc != LMDG_OK) return rc;
+  double* c = h->d_cvec;
+  double* x = h->d_cvec + N;
+  double* phi = h->d_cvec + 2 * N;
+  double* Lam = h->d_cvec + 3 * N;
+  const auto t_start = std::chrono::steady_clock::now();
+  // forward solve, keeping every direction's angular flux
+  lmdg_info inf_f{}, inf_a{};
+  rc = solve_impl(h, scheme, mode, tol, restart, max_iter, nullptr, x, phi, h->d_psi_f, &inf_f, st, nullptr, nullptr);
+  double J = 0.0;
+  if (rc == LMDG_OK) rc = dot(h, det, phi, N, &J, st);
+  // adjoint: on a centrally symmetric quadrature L_l^T is the upwind operator of
+  // -Omega_l, so A^T lambda = j is the forward system with source moments d and the
+  // direction blocks exchanged l <-> -l; the same sweeps solve it
+  if (rc == LMDG_OK) {
+    h->src0 = det;
+    h->src1 = scheme == LMDG_SCHEME_STD ? det + nc : nullptr;
+    const double* rhs_x = nullptr;
+    const double* cshift = nullptr;
+    if (scheme == LMDG_SCHEME_LMDG) {
+      // Step 1: c = B_11^{-1} Sigma Q_1 (Sigma Q_1 = d_1 since sum_l w_l = 1)
+      rc = cg_b11(h, det, c, std::min(1e-13, 1e-3 * tol), st);
+      if (rc == LMDG_OK) {
+        double* t = h->ws.vec + 3 * N;
+        lmdg::vec_axpby(t, -1.0, c, 0.0, N, st);
+        rhs_x = t;
+        cshift = c;
+      }
+    }
+    if (rc == LMDG_OK)
+      rc = solve_impl(h, scheme, mode, tol, restart, max_iter, nullptr, x, Lam, h->d_psi_a, &inf_a, st, rhs_x,
+                      cshift);
+    h->src0 = nullptr;
+    h->src1 = nullptr;
+  }
+  if (rc == LMDG_OK) {
+    lmdg::launch_gradients(h, npsi, phi, Lam, g_sigma_s, g_sigma_a, g_q, st);
+    rc = check_hip(h, hipGetLastError(), "gradients");
+  }
+  if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "adjoint");
+  *J_out = J;
+  if (info) {
+    info->iterations = inf_f.iterations + inf_a.iterations;
+    info->restarts = inf_f.restarts + inf_a.restarts;
+    info->ir_passes = inf_f.ir_passes + inf_a.ir_passes;
+    info->converged = (inf_f.converged && inf_a.converged) ? 1 : 0;
+    info->rel_residual = std::max(inf_f.rel_residual, inf_a.rel_residual);
+    info->time_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    info->time_apply_ms = inf_f.time_apply_ms + inf_a.time_apply_ms;
+  }
+  return rc;
 }
 
 int lmdg_profile(lmdg_t* h, int enable) {

@@ -34,6 +34,7 @@ struct SweepParams {
   const double* sigtA;   // (sigma_s/eps + eps sigma_a) |K|
   const double* scatA;   // (sigma_s/eps) |K|
   const double* qA;      // eps q |K| or null
+  const double* qS;      // source slope moments (3 * ncell, standard scheme) or null
   const double* absA;    // eps sigma_a |K|
   int defect;            // 1: x enters through the defect source (see lm_source)
   R* part;               // [4][NOUT][ncell] per-quadrant sums
@@ -77,6 +78,18 @@ struct lmdg_handle {
   double* d_scatA = nullptr;
   double* d_absA = nullptr;        // eps sigma_a |K|
   double* d_qA = nullptr;
+  double* d_epsA = nullptr;        // eps |K| (gradients)
+  // source used by sweeps with use_q: src0 replaces eps q |K| when set, src1 adds
+  // slope moments (standard scheme); both null outside the adjoint solve
+  const double* src0 = nullptr;
+  const double* src1 = nullptr;
+  // directions: index of -Omega_l and the weights on the device (adjoint gradients)
+  std::vector<int> neg_dir;
+  double* d_adjtab = nullptr;      // [n_dir][2]: w_l, index of -Omega_l
+  double* d_psi_f = nullptr;       // angular fluxes kept by the adjoint solve
+  double* d_psi_a = nullptr;
+  size_t psi_doubles = 0;
+  double* d_cvec = nullptr;        // B_11^{-1} of the source slopes (4 * ncell, slot 0 zero)
   lmdg::Workspace ws;
   unsigned long long epoch = 1;
   unsigned int ticket_base = 0;
@@ -106,6 +119,9 @@ void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double
                     double* out, hipStream_t st);
 void launch_sum_quadrants(lmdg_handle* h, int scheme, int prec, double* out, hipStream_t st);
 void launch_check_error(lmdg_handle* h, hipStream_t st);
+void launch_b11(lmdg_handle* h, const double* x, double* y, hipStream_t st);
+void launch_gradients(lmdg_handle* h, int npsi, const double* phi, const double* Lam, double* gs, double* ga,
+                      double* gq, hipStream_t st);
 
 // kApplyDefect: K x from a sweep run with the defect source (same operator).
 enum CombineMode { kApply = 0, kRhs = 1, kRecover = 2, kApplyDefect = 3 };

@@ -214,6 +214,65 @@ __global__ void sum_quadrants_kernel(int nout, int nout_abi, long long nc, const
   }
 }
 
+// y = [0 ; B_11 x_1] on the moment-major layout (slot 0 of x is not read).
+__global__ void b11_apply_kernel(int nx, int ny, double hx, double hy, double cxp, double cxm, double cyp,
+                                 double cym, const double* __restrict__ x, const double* __restrict__ absA,
+                                 double* __restrict__ y) {
+  const long long nc = (long long)nx * ny;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nc;
+       p += (long long)gridDim.x * blockDim.x) {
+    double ya, yb, yc;
+    b11_cell(x, nc, nx, ny, (int)(p % nx), (int)(p / nx), hx, hy, cxp, cxm, cyp, cym, absA[p], ya, yb, yc);
+    y[p] = 0.0;
+    y[nc + p] = ya;
+    y[2 * nc + p] = yb;
+    y[3 * nc + p] = yc;
+  }
+}
+
+// Gradients of J = int phi d with respect to per-cell sigma_s, sigma_a, q from the
+// forward angular flux psi and the adjoint angular flux lambda (bilinear form of
+// eq-Ljk differentiated cell by cell):
+//   dJ/dsigma_a = -eps sum_l w_l int_K psi_l lambda_l
+//   dJ/dsigma_s = -(1/eps) (sum_l w_l int_K psi_l lambda_l - int_K phi Lambda)
+//   dJ/dq       =  eps int_K Lambda
+// with phi, Lambda the scalar fluxes.  The adjoint field of direction l is the
+// forward-type solution of direction -Omega_l (tab: w_l, index of -Omega_l).
+// npsi = 4 (standard: all moments per direction) or 1 (low-memory: Psi_0 per
+// direction; the slope part is the isotropic Phi_1 of phi / Lambda).  Legendre mass
+// on K is |K| diag(1, 1/3, 1/3, 1/9).
+__global__ void gradient_kernel(long long nc, int ndir, int npsi, const double* __restrict__ tab,
+                                const double* __restrict__ psi, const double* __restrict__ lam,
+                                const double* __restrict__ phi, const double* __restrict__ Lam,
+                                const double* __restrict__ epsA, double area, double* __restrict__ gs,
+                                double* __restrict__ ga, double* __restrict__ gq) {
+  const double mass[4] = {1.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 9.0};
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nc;
+       p += (long long)gridDim.x * blockDim.x) {
+    double bil = 0.0;
+    for (int l = 0; l < ndir; ++l) {
+      const double w = tab[2 * l];
+      const long long ln = (long long)tab[2 * l + 1];
+      double acc = 0.0;
+      for (int m = 0; m < npsi; ++m)
+        acc += mass[m] * psi[((long long)l * npsi + m) * nc + p] * lam[(ln * npsi + m) * nc + p];
+      bil += w * acc;
+    }
+    double bar = 0.0, slopes = 0.0;
+    for (int m = 0; m < 4; ++m) {
+      const double t = mass[m] * phi[m * nc + p] * Lam[m * nc + p];
+      bar += t;
+      if (m > 0) slopes += t;
+    }
+    if (npsi == 1) bil += slopes;  // isotropic slope part, sum_l w_l = 1
+    const double eA = epsA[p];
+    const double eps = eA / area;
+    ga[p] = -eA * bil;
+    gs[p] = -(area / eps) * (bil - bar);
+    gq[p] = eA * Lam[p];
+  }
+}
+
 // ---------------------------------------------------------------- GMRES vectors
 constexpr int kDotBlocks = 240;
 
@@ -321,6 +380,19 @@ void launch_sum_quadrants(lmdg_handle* h, int scheme, int prec, double* out, hip
   else
     hipLaunchKernelGGL(sum_quadrants_kernel<float>, dim3(g), dim3(kBlock), 0, st, nout, nout_abi, h->ncell,
                        (const float*)h->ws.part, out);
+}
+
+void launch_b11(lmdg_handle* h, const double* x, double* y, hipStream_t st) {
+  const int g = std::min(grid_for(h->ncell), 4096);
+  hipLaunchKernelGGL(b11_apply_kernel, dim3(g), dim3(kBlock), 0, st, (int)h->n[0], (int)h->n[1], h->h[0], h->h[1],
+                     h->cplus[0], h->cminus[0], h->cplus[1], h->cminus[1], x, h->d_absA, y);
+}
+
+void launch_gradients(lmdg_handle* h, int npsi, const double* phi, const double* Lam, double* gs, double* ga,
+                      double* gq, hipStream_t st) {
+  const int g = std::min(grid_for(h->ncell), 4096);
+  hipLaunchKernelGGL(gradient_kernel, dim3(g), dim3(kBlock), 0, st, h->ncell, h->ndir, npsi, h->d_adjtab,
+                     h->d_psi_f, h->d_psi_a, phi, Lam, h->d_epsA, h->area, gs, ga, gq);
 }
 
 void vec_dots(const double* V, long long ld, int nvec, const double* w, long long n, double* partial,

@@ -95,7 +95,7 @@ template <int S>
 struct SrcTraits {
   static constexpr int NS = (S == LMDG_SCHEME_STD) ? 4 : 1;
   static constexpr int NC = 1 + 5 * NS;
-  static constexpr int NRAW = (S == LMDG_SCHEME_STD) ? 16 : 13;
+  static constexpr int NRAW = (S == LMDG_SCHEME_STD) ? 19 : 13;
   static constexpr int MAXC = (S == LMDG_SCHEME_STD) ? 1 : 2;  // staged cells per thread
 };
 
@@ -268,6 +268,10 @@ __device__ __forceinline__ void raw_load(const SweepParams<R>& P, int sxi, int s
     raw[13] = P.absA[cell];
     raw[14] = P.scatA[cell];
     raw[15] = P.qA ? P.qA[cell] : 0.0;
+    if (P.qS) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m) raw[16 + m] = P.qS[m * nc + cell];
+    }
   } else {
     if (x) {
       raw[0] = x[cell];
@@ -340,6 +344,7 @@ __device__ __forceinline__ void raw_coef(const double* raw, int c, int jr, int s
       cf[3][4] = hx * (sy * t3 * p[1] + t3 * p[3] + sy * t3 * By);
     }
     cf[0][0] += qA;
+    for (int m = 1; m < 4; ++m) cf[m][0] += raw[15 + m];  // source slope moments
     coef[0] = (R)sigtA;
     for (int m = 0; m < 4; ++m)
       for (int k = 0; k < 5; ++k) coef[(1 + 5 * m + k) * cstride] = (R)cf[m][k];
@@ -695,7 +700,8 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   P.x = x;
   P.sigtA = h->d_sigtA;
   P.scatA = h->d_scatA;
-  P.qA = use_q ? h->d_qA : nullptr;
+  P.qA = use_q ? (h->src0 ? h->src0 : h->d_qA) : nullptr;
+  P.qS = (use_q && S == LMDG_SCHEME_STD) ? h->src1 : nullptr;
   P.absA = h->d_absA;
   P.defect = defect ? 1 : 0;
   P.part = reinterpret_cast<R*>(h->ws.part);

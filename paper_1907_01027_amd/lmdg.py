@@ -28,7 +28,7 @@ MODES = {"fp64": 0, "mixed": 1}
 
 EXPORTED = ["lmdg_status_string", "lmdg_last_error", "lmdg_quadrature_level_symmetric", "lmdg_create",
             "lmdg_destroy", "lmdg_set_materials", "lmdg_sweep", "lmdg_apply", "lmdg_rhs",
-            "lmdg_recover", "lmdg_solve", "lmdg_profile", "lmdg_sweep_kernel_time"]
+            "lmdg_recover", "lmdg_solve", "lmdg_adjoint_solve", "lmdg_profile", "lmdg_sweep_kernel_time"]
 
 
 class LmdgInfo(ctypes.Structure):
@@ -63,6 +63,7 @@ def _load():
         "lmdg_rhs": (I, [P, I, I, P, P]),
         "lmdg_recover": (I, [P, I, I, P, P, P, P]),
         "lmdg_solve": (I, [P, I, I, D, I, I, P, P, P, ctypes.POINTER(LmdgInfo), P]),
+        "lmdg_adjoint_solve": (I, [P, I, I, P, D, I, I, P, P, P, ctypes.POINTER(D), ctypes.POINTER(LmdgInfo), P]),
         "lmdg_profile": (I, [P, I]),
         "lmdg_sweep_kernel_time": (I, [P, ctypes.POINTER(D), ctypes.POINTER(I)]),
     }
@@ -177,6 +178,16 @@ def lmdg_solve(h, scheme, mode, tol, restart, max_iter, x_out, phi_out=None, x0=
         return info.as_dict()
     _check(st, h)
     return info.as_dict()
+
+
+def lmdg_adjoint_solve(h, scheme, mode, det, tol, restart, max_iter, g_sigma_s, g_sigma_a, g_q, stream=None):
+    """J and the gradients (written into g_*) for detector moments det; returns (J, info)."""
+    info = LmdgInfo()
+    J = ctypes.c_double(0)
+    _check(_lib.lmdg_adjoint_solve(h, SCHEMES[scheme], MODES[mode], _ptr(det), float(tol), int(restart),
+                                   int(max_iter), _ptr(g_sigma_s), _ptr(g_sigma_a), _ptr(g_q), ctypes.byref(J),
+                                   ctypes.byref(info), _stream(stream)), h)
+    return J.value, info.as_dict()
 
 
 def lmdg_profile(h, enable):

@@ -80,7 +80,6 @@ constexpr int kStepGroup = 4;  // steps per unrolled group; chunks hold a multip
 template <typename R>
 struct Dir {
   double ox, oy;        // Omega components
-  R rox, roy;           // the same in the sweep precision
   R aox, aoy;           // |Omega_x|, |Omega_y|
   R w;                  // quadrature weight (0 for padding slots)
   R axhy, ayhx;         // |Omega_x| h_y, |Omega_y| h_x  (face measures times |Omega.nu|)
@@ -94,7 +93,7 @@ struct Dir {
 template <int S>
 struct SrcTraits {
   static constexpr int NS = (S == LMDG_SCHEME_STD) ? 4 : 1;
-  static constexpr int NC = 1 + 5 * NS;
+  static constexpr int NC = 1 + 3 * NS;  // sigma_t|K| and 3 source coefficients per moment
   static constexpr int NRAW = (S == LMDG_SCHEME_STD) ? 19 : 13;
   static constexpr int MAXC = (S == LMDG_SCHEME_STD) ? 1 : 2;  // staged cells per thread
 };
@@ -308,6 +307,8 @@ __device__ __forceinline__ void raw_load(const SweepParams<R>& P, int sxi, int s
 // STD, defect: (L_l Sigma^T - M) Phi = (eps sigma_a|K| mass + streaming + outflow) Phi_K
 //   minus the inflow terms of the upwind cells' outflow traces of Phi, split by the
 //   factor (1, Ox, Oy, |Ox|, |Oy|) each term carries.
+// Within a quadrant Ox = sx |Ox| and Oy = sy |Oy|, so the five factors fold into
+// three stored coefficients per moment: src = a + |Ox| b + |Oy| c.
 template <typename R, int S>
 __device__ __forceinline__ void raw_coef(const double* raw, int c, int jr, int sxi, int syi, double hx,
                                          double hy, bool defect, R* coef, int cstride) {
@@ -321,10 +322,10 @@ __device__ __forceinline__ void raw_coef(const double* raw, int c, int jr, int s
     for (int m = 0; m < 4; ++m)
       for (int k = 0; k < 5; ++k) cf[m][k] = 0.0;
     const double mass[4] = {1.0, t3, t3, t9};
+    const double sx = sxi, sy = syi;
     if (!defect) {
       for (int m = 0; m < 4; ++m) cf[m][0] = scatA * mass[m] * p[m];
     } else {
-      const double sx = sxi, sy = syi;
       for (int m = 0; m < 4; ++m) cf[m][0] = absA * mass[m] * p[m];
       // streaming -int u Omega.grad v
       cf[1][1] = -2.0 * hy * p[0];
@@ -347,7 +348,12 @@ __device__ __forceinline__ void raw_coef(const double* raw, int c, int jr, int s
     for (int m = 1; m < 4; ++m) cf[m][0] += raw[15 + m];  // source slope moments
     coef[0] = (R)sigtA;
     for (int m = 0; m < 4; ++m)
-      for (int k = 0; k < 5; ++k) coef[(1 + 5 * m + k) * cstride] = (R)cf[m][k];
+    for (int m = 0; m < 4; ++m) {
+      // within a quadrant Ox = sx |Ox| and Oy = sy |Oy|
+      coef[(1 + 3 * m) * cstride] = (R)cf[m][0];
+      coef[(2 + 3 * m) * cstride] = (R)(sx * cf[m][1] + cf[m][3]);
+      coef[(3 + 3 * m) * cstride] = (R)(sy * cf[m][2] + cf[m][4]);
+    }
   } else {
     const double x0 = raw[0], u1 = raw[1], u2 = raw[2], d1 = raw[3], d2 = raw[4];
     const double da = hy * (raw[5] - raw[6]);  // h_y (a_K - a_left)
@@ -374,10 +380,8 @@ __device__ __forceinline__ void raw_coef(const double* raw, int c, int jr, int s
     }
     coef[0] = (R)sigtA;
     coef[1 * cstride] = (R)c0;
-    coef[2 * cstride] = (R)c1;
-    coef[3 * cstride] = (R)c2;
-    coef[4 * cstride] = (R)c3;
-    coef[5 * cstride] = (R)c4;
+    coef[2 * cstride] = (R)(sxi * c1 + c3);  // |Ox| factor (Ox = sx |Ox| in the quadrant)
+    coef[3 * cstride] = (R)(syi * c2 + c4);  // |Oy| factor
   }
 }
 
@@ -444,8 +448,6 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
       const double* e = P.dirs + ((long long)q * P.dslots + slot) * kDirStride;
       d.ox = e[0];
       d.oy = e[1];
-      d.rox = (R)d.ox;
-      d.roy = (R)d.oy;
       d.aox = (R)fabs(d.ox);
       d.aoy = (R)fabs(d.oy);
       d.w = (R)e[2];
@@ -535,9 +537,8 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
           sig_g[u] = cf[0];
 #pragma unroll
           for (int m = 0; m < NS; ++m) {
-            const R* a = cf + (size_t)(1 + 5 * m) * ncells;
-            src_g[u][m] = a[0] + d.rox * a[ncells] + d.roy * a[2 * ncells] + d.aox * a[3 * ncells] +
-                          d.aoy * a[4 * ncells];
+            const R* a = cf + (size_t)(1 + 3 * m) * ncells;
+            src_g[u][m] = a[0] + d.aox * a[ncells] + d.aoy * a[2 * ncells];
           }
           if constexpr (S == LMDG_SCHEME_LMDG) {
             inv_g[u] = recip(sig_g[u] + d.axhy + d.ayhx);
@@ -684,9 +685,11 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   P.nstrips = h->nstrips;
   P.dslots = h->dslots;
   const int W = h->waves;
-  // chunk length: at most MAXC staged cells per thread and 64 KB of LDS
+  // chunk length: at most MAXC staged cells per thread and kLdsBudget bytes of LDS
+  // (one workgroup per compute unit; gfx950 gives a workgroup up to 160 KB)
+  constexpr size_t kLdsBudget = 144 * 1024;
   int cw = 16;
-  while (cw > kStepGroup && (kRows * cw > SrcTraits<S>::MAXC * 64 * W || lds_bytes<R, S>(cw, W, h->dslots) > 64 * 1024))
+  while (cw > kStepGroup && (kRows * cw > SrcTraits<S>::MAXC * 64 * W || lds_bytes<R, S>(cw, W, h->dslots) > kLdsBudget))
     cw >>= 1;
   P.cw = cw;
   P.lcw = 0;

@@ -33,6 +33,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--solve-max-iter", type=int, default=4000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 64 MiB five times (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -43,6 +46,36 @@ def sweep_bytes_per_launch(ncell, scheme):
     n_in = 5 if scheme != "std" else 6
     n_out = {"rlmdg": 6, "lmdg": 3, "std": 4}[scheme]
     return 4 * ncell * (n_in + n_out) * 8
+
+
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "sweep_rlmdg_256_s8_traffic.json")
+SWEEP_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1907_01027_amd", "csrc", "sweep2d.hip")
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed FETCH_SIZE / WRITE_SIZE counter runs,
+    scaled by the same counters' reading for a plain copy of known size; None when the
+    counters were taken on a different sweep source."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        src = hashlib.sha256(open(SWEEP_SOURCE, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("sweep_source_sha256") != src:
+        return None
+    return rec["fetch_bytes_per_launch"] / rec["copy_fetch_factor"] + rec["write_bytes_per_launch"] / rec["copy_write_factor"]
+
+
+def calibrate_copy():
+    import torch
+    n = 1 << 23
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 5}), flush=True)
 
 
 def cpu_baseline(seconds):
@@ -81,6 +114,9 @@ def main():
         print(f"bench.py measures one GPU only (asked for {args.gpus}); this build has no multi-GPU path. "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     import torch
     from paper_1907_01027_amd import lmdg
     from paper_1907_01027_amd.workloads import WORKLOADS, materials
@@ -134,7 +170,7 @@ def main():
                                "low-memory DG with upwind reconstruction (RLMDG), FP64",
                    "cells": ncell, "directions": len(w), "step": "one reduced-operator application K x"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "sweep2d_kernel<double, RLMDG>", "kernel_ms": sweep_ms,
                      "bytes_per_launch": nbytes},
     }
@@ -146,11 +182,12 @@ def main():
             xs.zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            info = lmdg.lmdg_solve(h, scheme, mode, 1e-8, 60, 20000, xs, phi, raise_on_nonconvergence=False)
+            info = lmdg.lmdg_solve(h, scheme, mode, 1e-8, 60, args.solve_max_iter, xs, phi,
+                                   raise_on_nonconvergence=False)
             torch.cuda.synchronize()
             info["wall_s"] = time.perf_counter() - t0
             res[mode] = info
-        out["solve"] = {"tol": 1e-8, "restart": 60, **res}
+        out["solve"] = {"tol": 1e-8, "restart": 60, "max_iter": args.solve_max_iter, **res}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     solver.close()

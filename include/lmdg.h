@@ -26,6 +26,12 @@
  *   right-hand sides and scalar fluxes all use this layout (n_P * n_cells doubles).
  *   For LMDG/RLMDG moment 0 is X_0 (per-cell scalar-flux average) and moments 1..3
  *   are X_1 of Sec. 3.2 Step 3.
+ * - Right-hand sides: a handle carries n_rhs sources (1 after lmdg_set_materials,
+ *   n after lmdg_set_sources).  Every vector argument of lmdg_sweep, lmdg_apply,
+ *   lmdg_rhs, lmdg_recover and lmdg_solve then holds the n_rhs fields stacked:
+ *   v[(k * n_P + r) * n_cells + p] for right-hand side k (sweep outputs and angular
+ *   fluxes likewise, with their own per-right-hand-side sizes).  All right-hand sides
+ *   share each sweep launch; the solver runs one GMRES instance per right-hand side.
  * - Pointers documented as "device" must point to memory of the handle's GPU
  *   (e.g. torch CUDA tensors); "host" pointers are ordinary CPU memory.  The caller
  *   owns every array it passes; the handle owns its internal workspaces.
@@ -130,6 +136,16 @@ int lmdg_set_materials(lmdg_t* h, const double* sigma_s, const double* sigma_a,
                        void* stream);
 
 /*
+ * n_rhs per-cell constant sources q (device, n_rhs * n_cells doubles, right-hand
+ * side k at q[k * n_cells + p]) replacing the single source of lmdg_set_materials;
+ * the cross sections and eps stay.  The source term of right-hand side k is
+ * eps q_k (eq-main).  All right-hand sides are swept together (one schedule, one
+ * set of per-cell coefficients per launch); solves run one GMRES instance each.
+ * Errors: INVALID_ARG (materials not set, NULL, n_rhs < 1 or > 64), NONFINITE.
+ */
+int lmdg_set_sources(lmdg_t* h, int n_rhs, const double* q, void* stream);
+
+/*
  * One sweep of all directions followed by the angular reductions (Sec. 2.1.1 for
  * STD, eq-nonrec-block for LMDG, Sec. 3.3.2 for RLMDG), without the identity/B_11
  * part of the reduced operator.  Solves, per direction, L_l Psi_l = S_l with
@@ -169,7 +185,9 @@ int lmdg_recover(lmdg_t* h, int scheme, int prec, const double* x, double* phi,
  * GMRES solves that use FP32 sweeps; the FP64 operator defines the residual.
  *   x_out    device moment vector (solution of the reduced system)
  *   phi_out  device moment vector (scalar flux), NULL to skip
- *   info     host, filled also when NOT_CONVERGED is returned
+ *   info     host, filled also when NOT_CONVERGED is returned; with several
+ *            right-hand sides rel_residual is the largest over them, converged
+ *            means all converged, and iterations counts shared operator applications
  * Errors: INVALID_ARG (tol <= 0, restart < 1, max_iter < 1), NOT_CONVERGED.
  */
 int lmdg_solve(lmdg_t* h, int scheme, int mode, double tol, int restart, int max_iter,
@@ -198,7 +216,8 @@ int lmdg_solve(lmdg_t* h, int scheme, int mode, double tol, int restart, int max
  * The handle keeps both angular fluxes (2 n_dir n_cells doubles for LMDG, 8 n_dir
  * n_cells for STD) after the first call.
  * Errors: UNSUPPORTED (RLMDG: its adjoint is Petrov-Galerkin), INVALID_ARG (NULL
- * pointers, bad solver arguments, quadrature without central symmetry),
+ * pointers, bad solver arguments, quadrature without central symmetry, more than
+ * one right-hand side on the handle),
  * NOT_CONVERGED (either solve, or the conjugate gradients of B_11 that give the
  * slope part of the LMDG adjoint source), HIP_ERROR.
  */

@@ -364,6 +364,39 @@ void lmdg_destroy(lmdg_t* h) {
   delete h;
 }
 
+// Grow the per-right-hand-side workspaces (partials, strip edges, progress words,
+// scratch vectors, sources) to n_rhs right-hand sides.
+static int ensure_rhs_capacity(lmdg_t* h, int n_rhs) {
+  using namespace lmdg;
+  if (n_rhs <= h->rhs_cap) return LMDG_OK;
+  hipDeviceSynchronize();
+  const long long nc = h->ncell;
+  void* olds[] = {h->ws.part, h->ws.edge, h->ws.prog, h->ws.vec, h->d_qA};
+  for (void* p : olds)
+    if (p) hipFree(p);
+  h->ws.part = nullptr;
+  h->ws.edge = nullptr;
+  h->ws.prog = nullptr;
+  h->ws.vec = nullptr;
+  h->d_qA = nullptr;
+  h->rhs_cap = 0;
+  int rc = check_hip(h, hipMalloc((void**)&h->ws.part, (size_t)4 * 6 * nc * n_rhs * sizeof(double)), "hipMalloc");
+  if (rc == LMDG_OK) rc = check_hip(h, hipMalloc(&h->ws.edge, h->ws.edge_bytes * n_rhs), "hipMalloc");
+  if (rc == LMDG_OK)
+    rc = check_hip(h, hipMalloc((void**)&h->ws.prog, (size_t)4 * h->nstrips * n_rhs * sizeof(unsigned long long)),
+                   "hipMalloc");
+  if (rc == LMDG_OK)
+    rc = check_hip(h, hipMalloc((void**)&h->ws.vec, (size_t)kScratchVecs * 4 * nc * n_rhs * sizeof(double)),
+                   "hipMalloc");
+  if (rc == LMDG_OK) rc = check_hip(h, hipMalloc((void**)&h->d_qA, (size_t)nc * n_rhs * sizeof(double)), "hipMalloc");
+  if (rc == LMDG_OK)
+    rc = check_hip(h, hipMemset(h->ws.prog, 0, (size_t)4 * h->nstrips * n_rhs * sizeof(unsigned long long)),
+                   "clear flags");
+  if (rc == LMDG_OK) rc = check_hip(h, hipDeviceSynchronize(), "workspaces");
+  if (rc == LMDG_OK) h->rhs_cap = n_rhs;
+  return rc;
+}
+
 int lmdg_set_materials(lmdg_t* h, const double* sigma_s, const double* sigma_a, const double* eps,
                        const double* q, const double* alpha, void* stream) {
   if (!h) return LMDG_INVALID_ARG;
@@ -402,7 +435,35 @@ int lmdg_set_materials(lmdg_t* h, const double* sigma_s, const double* sigma_a, 
                      "write materials");
   }
   if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "write materials");
-  if (rc == LMDG_OK) h->have_mat = true;
+  if (rc == LMDG_OK) {
+    h->have_mat = true;
+    h->n_rhs = 1;
+    h->h_eps = ep;
+  }
+  return rc;
+}
+
+int lmdg_set_sources(lmdg_t* h, int n_rhs, const double* q, void* stream) {
+  if (!h) return LMDG_INVALID_ARG;
+  if (!h->have_mat) return set_error(h, LMDG_INVALID_ARG, "materials not set");
+  if (!q || n_rhs < 1 || n_rhs > lmdg::kMaxRhs) return set_error(h, LMDG_INVALID_ARG, "bad source arguments");
+  hipStream_t st = (hipStream_t)stream;
+  const long long nc = h->ncell;
+  std::vector<double> qq((size_t)n_rhs * nc);
+  int rc = check_hip(h, hipMemcpyAsync(qq.data(), q, qq.size() * sizeof(double), hipMemcpyDeviceToHost, st),
+                     "read sources");
+  if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "read sources");
+  if (rc != LMDG_OK) return rc;
+  for (size_t e = 0; e < qq.size(); ++e) {
+    if (!std::isfinite(qq[e])) return set_error(h, LMDG_NONFINITE, "non-finite source value");
+    qq[e] = h->h_eps[e % nc] * qq[e] * h->area;  // eps q |K|, as lmdg_set_materials forms it
+  }
+  rc = ensure_rhs_capacity(h, n_rhs);
+  if (rc != LMDG_OK) return rc;
+  rc = check_hip(h, hipMemcpyAsync(h->d_qA, qq.data(), qq.size() * sizeof(double), hipMemcpyHostToDevice, st),
+                 "write sources");
+  if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "write sources");
+  if (rc == LMDG_OK) h->n_rhs = n_rhs;
   return rc;
 }
 
@@ -463,34 +524,48 @@ int ensure_krylov(lmdg_t* h, size_t doubles) {
   return rc;
 }
 
-// Scratch layout of d_small / h_small (small_doubles entries each):
-//   [0, 256)                  GMRES coefficients (device) / both CGS passes (host)
-//   [256, 256 + nvec*parts)   partial sums of the dot kernels (device)
-//   [small_doubles - 1]       result slot of norm2 (device and host)
-size_t small_size(int restart) { return 256 + (size_t)(restart + 2) * (lmdg::dots_partials() + 4); }
+// Scratch layout of d_small / h_small for nr right-hand sides (offsets in doubles):
+//   coef   2 (kMaxRestart + 2) nr   GMRES coefficients (device) / both CGS passes (host)
+//   part   kDotBlocks (kMaxRestart + 2) nr   partial sums of the dot kernels (device)
+//   scal   nr                       per-segment scale factors
+//   res    nr                       dot / norm results
+constexpr int kMaxRestart = 250;
+struct SmallLayout {
+  size_t coef, part, scal, res, total;
+};
+SmallLayout small_layout(int nr) {
+  SmallLayout L;
+  L.coef = 0;
+  L.part = (size_t)2 * (kMaxRestart + 2) * nr;
+  L.scal = L.part + (size_t)lmdg::dots_partials() * (kMaxRestart + 2) * nr;
+  L.res = L.scal + nr;
+  L.total = L.res + nr + 8;
+  return L;
+}
 
-// ||v||_2 via the dot kernels, synchronising the stream.
-int norm2(lmdg_t* h, const double* v, long long n, double* out, hipStream_t st) {
-  double* part = h->d_small + 256;
-  double* dres = h->d_small + h->small_doubles - 1;
-  double* hres = h->h_small + h->small_doubles - 1;
-  lmdg::vec_dots(v, n, 1, v, n, part, dres, st);
-  int rc = check_hip(h, hipMemcpyAsync(hres, dres, sizeof(double), hipMemcpyDeviceToHost, st), "norm");
-  if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "norm");
-  *out = std::sqrt(std::max(0.0, *hres));
+// Per-segment dot products a[rz] . b[rz] (nr segments of length n) into out[0..nr),
+// synchronising the stream.
+int seg_dots(lmdg_t* h, const double* a, const double* b, long long n, int nr, double* out, hipStream_t st) {
+  const SmallLayout L = small_layout(nr);
+  int rc = ensure_small(h, L.total);
+  if (rc != LMDG_OK) return rc;
+  lmdg::vec_dots(a, n * nr, 1, b, n, h->d_small + L.part, h->d_small + L.res, st, nr);
+  rc = check_hip(h, hipMemcpyAsync(h->h_small + L.res, h->d_small + L.res, nr * sizeof(double),
+                                   hipMemcpyDeviceToHost, st), "dots");
+  if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "dots");
+  if (rc == LMDG_OK) std::copy(h->h_small + L.res, h->h_small + L.res + nr, out);
   return rc;
 }
 
-// a . b via the dot kernels, synchronising the stream.
-int dot(lmdg_t* h, const double* a, const double* b, long long n, double* out, hipStream_t st) {
-  double* part = h->d_small + 256;
-  double* dres = h->d_small + h->small_doubles - 1;
-  double* hres = h->h_small + h->small_doubles - 1;
-  lmdg::vec_dots(a, n, 1, b, n, part, dres, st);
-  int rc = check_hip(h, hipMemcpyAsync(hres, dres, sizeof(double), hipMemcpyDeviceToHost, st), "dot");
-  if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "dot");
-  *out = *hres;
+// ||v[rz]||_2 for every segment.
+int seg_norms(lmdg_t* h, const double* v, long long n, int nr, double* out, hipStream_t st) {
+  int rc = seg_dots(h, v, v, n, nr, out, st);
+  for (int k = 0; k < nr; ++k) out[k] = std::sqrt(std::max(0.0, out[k]));
   return rc;
+}
+
+int dot(lmdg_t* h, const double* a, const double* b, long long n, double* out, hipStream_t st) {
+  return seg_dots(h, a, b, n, 1, out, st);
 }
 
 // LMDG_VERBOSE=1 in the environment prints solver progress to stderr.
@@ -507,32 +582,39 @@ struct GmresStats {
   double apply_ms = 0;
 };
 
-// Restarted GMRES(m) with classical Gram-Schmidt applied twice, FP64 vectors.
-// Solves K_prec x = b starting from x (in/out); stops when the true FP64-operator
-// residual ||b - K x|| <= rtol * ||b|| (true_prec) or after max_iter applications.
+// Restarted GMRES(m) with classical Gram-Schmidt applied twice, FP64 vectors, for the
+// handle's nr right-hand sides at once: nr independent GMRES instances (own Hessenberg
+// matrices, rotations and stopping tests) share every operator application.  Solves
+// K_prec x = b from x (in/out); stops when every true FP64-operator residual
+// ||b - K x|| <= rtol ||b|| (true_prec) or after max_iter applications.  relres is
+// the largest relative residual over the right-hand sides.
 int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, double* x, double rtol, int m,
           int max_iter, hipStream_t st, GmresStats& stats, double& relres, bool& converged) {
-  const long long N = 4 * h->ncell;
-  int rc = ensure_krylov(h, (size_t)(m + 2) * N);
-  if (rc == LMDG_OK) rc = ensure_small(h, small_size(m));
+  const int nr = h->n_rhs;
+  const long long N = 4 * h->ncell;  // one right-hand side
+  const long long NT = N * nr;
+  const SmallLayout L = small_layout(nr);
+  int rc = ensure_krylov(h, (size_t)(m + 2) * NT);
+  if (rc == LMDG_OK) rc = ensure_small(h, L.total);
   if (rc != LMDG_OK) return rc;
-  double* V = h->d_krylov;              // m + 1 basis vectors
-  double* r = V + (size_t)(m + 1) * N;  // residual work vector
-  double* dcoef = h->d_small;           // device coefficients (m + 2)
-  double* part = h->d_small + 256;
-  double* hc = h->h_small;
-  double bnorm;
-  rc = norm2(h, b, N, &bnorm, st);
+  double* V = h->d_krylov;               // m + 1 basis vectors of length NT
+  double* r = V + (size_t)(m + 1) * NT;  // residual work vector
+  double* dcoef = h->d_small + L.coef;
+  double* dscal = h->d_small + L.scal;
+  double* part = h->d_small + L.part;
+  double* hc = h->h_small + L.coef;      // first pass at 0, second at (m + 1) nr
+  double* hscal = h->h_small + L.scal;
+  std::vector<double> bnorm(nr), beta(nr), hn(nr);
+  rc = seg_norms(h, b, N, nr, bnorm.data(), st);
   if (rc != LMDG_OK) return rc;
   converged = false;
   relres = 1.0;
-  if (bnorm == 0.0) {
-    lmdg::vec_fill(x, 0.0, N, st);
-    converged = true;
-    relres = 0.0;
-    return check_hip(h, hipStreamSynchronize(st), "gmres");
-  }
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  std::vector<std::vector<double>> H(nr, std::vector<double>((size_t)(m + 1) * m)), cs(nr, std::vector<double>(m)),
+      sn(nr, std::vector<double>(m)), g(nr, std::vector<double>(m + 1));
+  std::vector<int> kr(nr);
+  std::vector<char> done(nr);
+  std::vector<double> y(m);
+  double prev_relres = -1.0;
   hipEvent_t e0, e1;
   hipEventCreate(&e0);
   hipEventCreate(&e1);
@@ -548,78 +630,116 @@ int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, doubl
     hipEventElapsedTime(&ms, e0, e1);
     stats.apply_ms += ms;
   };
+  auto upload_scales = [&]() {
+    return check_hip(h, hipMemcpyAsync(dscal, hscal, nr * sizeof(double), hipMemcpyHostToDevice, st), "scales");
+  };
   while (rc == LMDG_OK) {
-    // true residual with the FP64 (or requested) operator
+    // true residuals with the FP64 (or requested) operator
     rc = timed_apply(true_prec, x, r);
     if (rc != LMDG_OK) break;
-    lmdg::vec_axpby(r, 1.0, b, -1.0, N, st);  // r = b - K x
-    double beta;
-    rc = norm2(h, r, N, &beta, st);
+    lmdg::vec_axpby(r, 1.0, b, -1.0, NT, st);  // r = b - K x
+    rc = seg_norms(h, r, N, nr, beta.data(), st);
     add_time();
     if (rc != LMDG_OK) break;
-    relres = beta / bnorm;
+    relres = 0.0;
+    bool finite = true;
+    for (int k = 0; k < nr; ++k) {
+      finite = finite && std::isfinite(beta[k]);
+      relres = std::max(relres, bnorm[k] > 0 ? beta[k] / bnorm[k] : 0.0);
+    }
     if (verbose())
-      std::fprintf(stderr, "lmdg GMRES(%d) %s: restart %d, %d its, true rel residual %.3e\n", m,
-                   prec == LMDG_PREC_FP64 ? "fp64" : "fp32", stats.restarts, stats.iterations, relres);
-    if (!std::isfinite(beta)) { rc = set_error(h, LMDG_NONFINITE, "non-finite residual"); break; }
+      std::fprintf(stderr, "lmdg GMRES(%d) %s: restart %d, %d its, true rel residual %.3e (max over %d rhs)\n", m,
+                   prec == LMDG_PREC_FP64 ? "fp64" : "fp32", stats.restarts, stats.iterations, relres, nr);
+    if (!finite) { rc = set_error(h, LMDG_NONFINITE, "non-finite residual"); break; }
     if (relres <= rtol) { converged = true; break; }
     if (stats.iterations >= max_iter) break;
+    // an FP32 inner solve of the refinement loop returns once a restart cycle no
+    // longer reduces its own true residual (the FP32 operator's accuracy floor)
+    if (prec == LMDG_PREC_FP32 && prev_relres > 0 && relres >= prev_relres) break;
+    prev_relres = relres;
     stats.restarts += 1;
-    lmdg::vec_axpby(V, 1.0 / beta, r, 0.0, N, st);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int k = 0;
+    for (int k = 0; k < nr; ++k) {
+      std::fill(g[k].begin(), g[k].end(), 0.0);
+      g[k][0] = beta[k];
+      kr[k] = 0;
+      done[k] = beta[k] == 0.0 || beta[k] <= 0.5 * rtol * bnorm[k];
+      hscal[k] = done[k] ? 0.0 : 1.0 / beta[k];
+    }
+    rc = upload_scales();
+    if (rc != LMDG_OK) break;
+    lmdg::vec_scale_seg(V, r, dscal, N, nr, st);
     for (int j = 0; j < m && stats.iterations < max_iter; ++j) {
-      double* w = V + (size_t)(j + 1) * N;
-      rc = timed_apply(prec, V + (size_t)j * N, w);
+      double* w = V + (size_t)(j + 1) * NT;
+      rc = timed_apply(prec, V + (size_t)j * NT, w);
       if (rc != LMDG_OK) break;
       stats.iterations += 1;
       // two passes of classical Gram-Schmidt, coefficients kept on the device
-      lmdg::vec_dots(V, N, j + 1, w, N, part, dcoef, st);
-      lmdg::vec_axpy_multi(w, V, N, j + 1, dcoef, -1.0, N, st);
-      rc = check_hip(h, hipMemcpyAsync(hc, dcoef, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, st), "h");
+      lmdg::vec_dots(V, NT, j + 1, w, N, part, dcoef, st, nr);
+      lmdg::vec_axpy_multi(w, V, NT, j + 1, dcoef, -1.0, N, st, nr);
+      rc = check_hip(h, hipMemcpyAsync(hc, dcoef, (j + 1) * nr * sizeof(double), hipMemcpyDeviceToHost, st), "h");
       if (rc != LMDG_OK) break;
-      lmdg::vec_dots(V, N, j + 1, w, N, part, dcoef, st);
-      lmdg::vec_axpy_multi(w, V, N, j + 1, dcoef, -1.0, N, st);
-      rc = check_hip(h, hipMemcpyAsync(hc + (m + 1), dcoef, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, st),
-                     "h2");
+      lmdg::vec_dots(V, NT, j + 1, w, N, part, dcoef, st, nr);
+      lmdg::vec_axpy_multi(w, V, NT, j + 1, dcoef, -1.0, N, st, nr);
+      rc = check_hip(h, hipMemcpyAsync(hc + (size_t)(m + 1) * nr, dcoef, (j + 1) * nr * sizeof(double),
+                                       hipMemcpyDeviceToHost, st), "h2");
       if (rc != LMDG_OK) break;
-      double hn;
-      rc = norm2(h, w, N, &hn, st);  // synchronises: hc is valid afterwards
+      rc = seg_norms(h, w, N, nr, hn.data(), st);  // synchronises: hc is valid afterwards
       add_time();
       if (rc != LMDG_OK) break;
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hc[i] + hc[m + 1 + i];
-      H[(size_t)(j + 1) * m + j] = hn;
-      for (int i = 0; i < j; ++i) {  // previous rotations
-        const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
-        H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
-        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+      bool all_done = true;
+      for (int k = 0; k < nr; ++k) {
+        if (done[k]) {
+          hscal[k] = 0.0;
+          continue;
+        }
+        if (!std::isfinite(hn[k])) { rc = set_error(h, LMDG_NONFINITE, "non-finite Krylov vector"); break; }
+        std::vector<double>& Hk = H[k];
+        for (int i = 0; i <= j; ++i)
+          Hk[(size_t)i * m + j] = hc[(size_t)i * nr + k] + hc[(size_t)(m + 1) * nr + (size_t)i * nr + k];
+        Hk[(size_t)(j + 1) * m + j] = hn[k];
+        for (int i = 0; i < j; ++i) {  // previous rotations
+          const double a = Hk[(size_t)i * m + j], c = Hk[(size_t)(i + 1) * m + j];
+          Hk[(size_t)i * m + j] = cs[k][i] * a + sn[k][i] * c;
+          Hk[(size_t)(i + 1) * m + j] = -sn[k][i] * a + cs[k][i] * c;
+        }
+        const double a = Hk[(size_t)j * m + j], c = Hk[(size_t)(j + 1) * m + j];
+        const double rr = std::hypot(a, c);
+        cs[k][j] = rr == 0 ? 1.0 : a / rr;
+        sn[k][j] = rr == 0 ? 0.0 : c / rr;
+        Hk[(size_t)j * m + j] = rr;
+        Hk[(size_t)(j + 1) * m + j] = 0.0;
+        g[k][j + 1] = -sn[k][j] * g[k][j];
+        g[k][j] = cs[k][j] * g[k][j];
+        kr[k] = j + 1;
+        if (std::fabs(g[k][j + 1]) <= 0.5 * rtol * bnorm[k] || hn[k] == 0.0) done[k] = 1;
+        hscal[k] = done[k] ? 0.0 : 1.0 / hn[k];
+        all_done = all_done && done[k];
       }
-      const double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
-      const double rr = std::hypot(a, c);
-      cs[j] = rr == 0 ? 1.0 : a / rr;
-      sn[j] = rr == 0 ? 0.0 : c / rr;
-      H[(size_t)j * m + j] = rr;
-      H[(size_t)(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      k = j + 1;
-      if (!std::isfinite(hn)) { rc = set_error(h, LMDG_NONFINITE, "non-finite Krylov vector"); break; }
-      if (std::fabs(g[j + 1]) <= 0.5 * rtol * bnorm || hn == 0.0) break;
-      lmdg::vec_axpby(w, 1.0 / hn, w, 0.0, N, st);
+      if (rc != LMDG_OK || all_done) break;
+      rc = upload_scales();
+      if (rc != LMDG_OK) break;
+      lmdg::vec_scale_seg(w, w, dscal, N, nr, st);  // finished segments become zero
     }
     if (rc != LMDG_OK) break;
-    // x += V y with H y = g (upper triangular)
-    for (int i = k - 1; i >= 0; --i) {
-      double acc = g[i];
-      for (int jj = i + 1; jj < k; ++jj) acc -= H[(size_t)i * m + jj] * y[jj];
-      y[i] = acc / H[(size_t)i * m + i];
-    }
-    if (k > 0) {
-      std::copy(y.begin(), y.begin() + k, hc);
-      rc = check_hip(h, hipMemcpyAsync(dcoef, hc, k * sizeof(double), hipMemcpyHostToDevice, st), "y");
+    // x[k] += V y_k with H_k y_k = g_k (upper triangular, k_r columns)
+    int kmax = 0;
+    for (int k = 0; k < nr; ++k) kmax = std::max(kmax, kr[k]);
+    if (kmax > 0) {
+      std::fill(hc, hc + (size_t)kmax * nr, 0.0);
+      for (int k = 0; k < nr; ++k) {
+        const int kk = kr[k];
+        const std::vector<double>& Hk = H[k];
+        for (int i = kk - 1; i >= 0; --i) {
+          double acc = g[k][i];
+          for (int jj = i + 1; jj < kk; ++jj) acc -= Hk[(size_t)i * m + jj] * y[jj];
+          y[i] = acc / Hk[(size_t)i * m + i];
+        }
+        for (int i = 0; i < kk; ++i) hc[(size_t)i * nr + k] = y[i];
+      }
+      rc = check_hip(h, hipMemcpyAsync(dcoef, hc, (size_t)kmax * nr * sizeof(double), hipMemcpyHostToDevice, st),
+                     "y");
       if (rc != LMDG_OK) break;
-      lmdg::vec_axpy_multi(x, V, N, k, dcoef, 1.0, N, st);
+      lmdg::vec_axpy_multi(x, V, NT, kmax, dcoef, 1.0, N, st, nr);
       rc = check_hip(h, hipStreamSynchronize(st), "update");  // hc is reused next cycle
     }
   }
@@ -681,10 +801,12 @@ int lmdg_recover(lmdg_t* h, int scheme, int prec, const double* x, double* phi, 
 static int solve_impl(lmdg_t* h, int scheme, int mode, double tol, int restart, int max_iter, const double* x0,
                       double* x_out, double* phi_out, double* psi_out, lmdg_info* info, hipStream_t st,
                       const double* rhs_x, const double* cshift) {
-  int rc = ensure_small(h, small_size(restart));
+  const int nr = h->n_rhs;
+  int rc = ensure_small(h, small_layout(nr).total);
   if (rc != LMDG_OK) return rc;
   const auto t_start = std::chrono::steady_clock::now();
-  const long long N = 4 * h->ncell;
+  const long long N = 4 * h->ncell * nr;  // all right-hand sides
+  const long long N1 = 4 * h->ncell;
   double* b = h->ws.vec;
   double* r = h->ws.vec + N;
   double* d = h->ws.vec + 2 * N;
@@ -705,21 +827,27 @@ static int solve_impl(lmdg_t* h, int scheme, int mode, double tol, int restart, 
     rc = gmres(h, scheme, LMDG_PREC_FP64, LMDG_PREC_FP64, b, x_out, tol, restart, max_iter, st, stats, relres, conv);
   } else {
     // FP64 iterative refinement: r = b - K64 x; inner GMRES with FP32 sweeps on K d = r
-    double bnorm;
-    rc = norm2(h, b, N, &bnorm, st);
+    std::vector<double> bnorm(nr), rn(nr);
+    rc = seg_norms(h, b, N1, nr, bnorm.data(), st);
     while (rc == LMDG_OK && stats.iterations < max_iter && passes < 100) {
       rc = apply_op(h, scheme, LMDG_PREC_FP64, x_out, r, st);
       if (rc != LMDG_OK) break;
       lmdg::vec_axpby(r, 1.0, b, -1.0, N, st);
-      double rn;
-      rc = norm2(h, r, N, &rn, st);
+      rc = seg_norms(h, r, N1, nr, rn.data(), st);
       if (rc != LMDG_OK) break;
-      relres = bnorm > 0 ? rn / bnorm : 0.0;
-      if (!std::isfinite(rn)) { rc = set_error(h, LMDG_NONFINITE, "non-finite residual"); break; }
+      relres = 0.0;
+      bool finite = true;
+      for (int k = 0; k < nr; ++k) {
+        finite = finite && std::isfinite(rn[k]);
+        relres = std::max(relres, bnorm[k] > 0 ? rn[k] / bnorm[k] : 0.0);
+      }
+      if (!finite) { rc = set_error(h, LMDG_NONFINITE, "non-finite residual"); break; }
       if (relres <= tol) { conv = true; break; }
       passes += 1;
       lmdg::vec_fill(d, 0.0, N, st);
-      const double inner = std::max(1e-5, 0.5 * tol / relres);
+      // FP32 sweeps carry about 1e-6 relative error, so each pass asks for three
+      // digits at most and the FP64 residual of the next pass corrects the rest
+      const double inner = std::max(1e-3, 0.5 * tol / relres);
       bool iconv = false;
       double irel = 1;
       const int before = stats.iterations;
@@ -817,6 +945,7 @@ int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, doubl
     return set_error(h, LMDG_INVALID_ARG, "bad adjoint arguments");
   for (int l = 0; l < h->ndir; ++l)
     if (h->neg_dir[l] < 0) return set_error(h, LMDG_INVALID_ARG, "quadrature is not centrally symmetric");
+  if (h->n_rhs != 1) return set_error(h, LMDG_INVALID_ARG, "the adjoint solve takes one right-hand side");
   hipStream_t st = (hipStream_t)stream;
   const long long nc = h->ncell, N = 4 * nc;
   const int npsi = scheme == LMDG_SCHEME_STD ? 4 : 1;
@@ -835,8 +964,6 @@ int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, doubl
     rc = check_hip(h, hipMalloc((void**)&h->d_cvec, (size_t)4 * N * sizeof(double)), "hipMalloc adjoint vectors");
     if (rc != LMDG_OK) return rc;
   }
-  rc = ensure_small(h, small_size(restart));
-  if (rc != LMDG_OK) return rc;
   double* c = h->d_cvec;
   double* x = h->d_cvec + N;
   double* phi = h->d_cvec + 2 * N;

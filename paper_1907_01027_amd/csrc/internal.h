@@ -15,6 +15,7 @@ constexpr int kRows = 16;         // rows of one strip (lanes of one DPP row)
 constexpr int kMaxSlots = 36;     // direction slots per quadrant (9 waves x 4; S16 has 36)
 constexpr int kMaxWaves = kMaxSlots / 4;
 constexpr int kDirStride = 8;     // doubles per direction-table entry
+constexpr int kMaxRhs = 64;       // right-hand sides per handle
 
 // Raw outputs of a sweep per scheme: number of per-cell reductions and of
 // face-trace values handed from a cell to its downwind neighbours.
@@ -27,20 +28,22 @@ template <> struct SchemeTraits<LMDG_SCHEME_RLMDG> { static constexpr int NOUT =
 template <typename R>
 struct SweepParams {
   int nx, ny, nstrips, cw, lcw, nchunks, dslots, n_items;  // cw = 1 << lcw steps per chunk
+  int n_rhs;             // right-hand sides swept together (vectors stacked rhs-major)
+  long long psi_rstride, edge_rstride;
   double hx, hy;
   long long ncell;
   const double* dirs;    // [4][dslots][kDirStride]: ox, oy, w, index
-  const double* x;       // moment vector (4 * ncell) or null
+  const double* x;       // moment vectors (n_rhs * 4 * ncell) or null
   const double* sigtA;   // (sigma_s/eps + eps sigma_a) |K|
   const double* scatA;   // (sigma_s/eps) |K|
-  const double* qA;      // eps q |K| or null
+  const double* qA;      // eps q |K| (n_rhs * ncell) or null
   const double* qS;      // source slope moments (3 * ncell, standard scheme) or null
   const double* absA;    // eps sigma_a |K|
   int defect;            // 1: x enters through the defect source (see lm_source)
-  R* part;               // [4][NOUT][ncell] per-quadrant sums
-  R* edge;               // [4][nstrips][nx][NF][dslots] top-row traces
-  double* psi;           // optional angular flux
-  unsigned long long* prog;   // [4][nstrips] progress words
+  R* part;               // [n_rhs][4][NOUT][ncell] per-quadrant sums
+  R* edge;               // [n_rhs][4][nstrips][nx][NF][dslots] top-row traces
+  double* psi;           // optional angular flux ([n_rhs][n_dir][...])
+  unsigned long long* prog;   // [n_rhs][4][nstrips] progress words
   unsigned int* ticket;
   int* err;
   unsigned long long epoch;
@@ -64,6 +67,8 @@ struct lmdg_handle {
   int64_t n[2] = {0, 0};
   double len[2] = {1, 1}, h[2] = {1, 1}, area = 1;
   long long ncell = 0;
+  int n_rhs = 1;                   // right-hand sides (sources) of the handle
+  int rhs_cap = 1;                 // right-hand sides the workspaces are sized for
   int np = 4;
   int ndir = 0;
   std::vector<double> omega, w;
@@ -79,6 +84,7 @@ struct lmdg_handle {
   double* d_absA = nullptr;        // eps sigma_a |K|
   double* d_qA = nullptr;
   double* d_epsA = nullptr;        // eps |K| (gradients)
+  std::vector<double> h_eps;       // host copy of eps (source scaling)
   // source used by sweeps with use_q: src0 replaces eps q |K| when set, src1 adds
   // slope moments (standard scheme); both null outside the adjoint solve
   const double* src0 = nullptr;
@@ -126,11 +132,13 @@ void launch_gradients(lmdg_handle* h, int npsi, const double* phi, const double*
 // kApplyDefect: K x from a sweep run with the defect source (same operator).
 enum CombineMode { kApply = 0, kRhs = 1, kRecover = 2, kApplyDefect = 3 };
 
-// GMRES vector kernels (ops.hip)
+// GMRES vector kernels (ops.hip).  Vectors of nr right-hand sides are stacked in
+// segments of length n; dot products and coefficients are indexed [v * nr + segment].
 void vec_dots(const double* V, long long ld, int nvec, const double* w, long long n,
-              double* partial, double* out, hipStream_t st);
+              double* partial, double* out, hipStream_t st, int nr = 1);
 void vec_axpy_multi(double* w, const double* V, long long ld, int nvec, const double* coef,
-                    double sign, long long n, hipStream_t st);
+                    double sign, long long n, hipStream_t st, int nr = 1);
+void vec_scale_seg(double* y, const double* x, const double* scale, long long n, int nr, hipStream_t st);
 void vec_axpby(double* y, double a, const double* x, double b, long long n, hipStream_t st);
 void vec_copy(double* y, const double* x, long long n, hipStream_t st);
 void vec_fill(double* y, double v, long long n, hipStream_t st);

@@ -130,15 +130,20 @@ __device__ __forceinline__ void iso_g(const double* x0, int nx, int ny, int i, i
 // has no slope moments and the inflow is vacuum).  In kApplyDefect the sweep solved
 // L~_00 psi_D = defect source, and K x = [P_0 psi_D ; B_11 x_1 - G Sigma_0^T x_0 + G psi_D].
 template <typename R, bool RLM>
-__global__ void combine_lm_kernel(int mode, int nx, int ny, double hx, double hy, double cxp, double cxm,
-                                  double cyp, double cym, QuadMoments qm, const double* __restrict__ x,
-                                  const R* __restrict__ part, const double* __restrict__ sigtA,
+__global__ void combine_lm_kernel(int mode, int nr, int nx, int ny, double hx, double hy, double cxp, double cxm,
+                                  double cyp, double cym, QuadMoments qm, const double* __restrict__ x_all,
+                                  const R* __restrict__ part_all, const double* __restrict__ sigtA,
                                   const double* __restrict__ scatA, const double* __restrict__ absA,
-                                  double* __restrict__ out) {
+                                  double* __restrict__ out_all) {
   constexpr int NOUT = RLM ? 6 : 3;
   const long long nc = (long long)nx * ny;
-  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nc;
-       p += (long long)gridDim.x * blockDim.x) {
+  for (long long pr = blockIdx.x * (long long)blockDim.x + threadIdx.x; pr < nr * nc;
+       pr += (long long)gridDim.x * blockDim.x) {
+    // right-hand side rh, cell p; vectors are stacked rhs-major
+    const long long rh = pr / nc, p = pr - rh * nc;
+    const double* x = x_all ? x_all + rh * 4 * nc : nullptr;
+    const R* part = part_all + rh * 4 * NOUT * nc;
+    double* out = out_all + rh * 4 * nc;
     double s[NOUT];
 #pragma unroll
     for (int m = 0; m < NOUT; ++m) {
@@ -185,10 +190,14 @@ __global__ void combine_lm_kernel(int mode, int nx, int ny, double hx, double hy
 // Standard scheme: K Phi = Phi - P L^{-1} M Phi (eq-sndg-phi); right-hand side and
 // recovered scalar flux are the plain quadrant sums.
 template <typename R>
-__global__ void combine_std_kernel(int mode, long long nc, const double* __restrict__ x,
-                                   const R* __restrict__ part, double* __restrict__ out) {
-  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nc;
-       p += (long long)gridDim.x * blockDim.x) {
+__global__ void combine_std_kernel(int mode, int nr, long long nc, const double* __restrict__ x_all,
+                                   const R* __restrict__ part_all, double* __restrict__ out_all) {
+  for (long long pr = blockIdx.x * (long long)blockDim.x + threadIdx.x; pr < nr * nc;
+       pr += (long long)gridDim.x * blockDim.x) {
+    const long long rh = pr / nc, p = pr - rh * nc;
+    const double* x = x_all ? x_all + rh * 4 * nc : nullptr;
+    const R* part = part_all + rh * 16 * nc;
+    double* out = out_all + rh * 4 * nc;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       double acc = 0;
@@ -201,10 +210,13 @@ __global__ void combine_std_kernel(int mode, long long nc, const double* __restr
 }
 
 template <typename R>
-__global__ void sum_quadrants_kernel(int nout, int nout_abi, long long nc, const R* __restrict__ part,
-                                     double* __restrict__ out) {
-  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nc;
-       p += (long long)gridDim.x * blockDim.x) {
+__global__ void sum_quadrants_kernel(int nout, int nout_abi, int nr, long long nc, const R* __restrict__ part_all,
+                                     double* __restrict__ out_all) {
+  for (long long pr = blockIdx.x * (long long)blockDim.x + threadIdx.x; pr < nr * nc;
+       pr += (long long)gridDim.x * blockDim.x) {
+    const long long rh = pr / nc, p = pr - rh * nc;
+    const R* part = part_all + rh * 4 * nout * nc;
+    double* out = out_all + rh * nout_abi * nc;
     for (int m = 0; m < nout_abi; ++m) {
       double acc = 0;
       if (m < nout)
@@ -276,11 +288,15 @@ __global__ void gradient_kernel(long long nc, int ndir, int npsi, const double* 
 // ---------------------------------------------------------------- GMRES vectors
 constexpr int kDotBlocks = 240;
 
-// partial[v * kDotBlocks + b] = block b's share of V_v . w
-__global__ void dots_partial_kernel(const double* __restrict__ V, long long ld, const double* __restrict__ w,
+// Vectors of nr right-hand sides are stacked (segments of length n).  For basis
+// vector v (blockIdx.y) and segment rz (blockIdx.z):
+// partial[(v * nr + rz) * kDotBlocks + b] = block b's share of V_v[rz] . w[rz]
+__global__ void dots_partial_kernel(const double* __restrict__ V, long long ld, const double* __restrict__ w_all,
                                     long long n, double* __restrict__ partial) {
   const int v = blockIdx.y;
-  const double* vv = V + v * ld;
+  const int rz = blockIdx.z;
+  const double* vv = V + v * ld + rz * n;
+  const double* w = w_all + rz * n;
   double acc = 0;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x)
@@ -292,7 +308,7 @@ __global__ void dots_partial_kernel(const double* __restrict__ V, long long ld, 
     if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[(long long)v * gridDim.x + blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) partial[((long long)v * gridDim.z + rz) * gridDim.x + blockIdx.x] = sh[0];
 }
 
 __global__ void dots_final_kernel(const double* __restrict__ partial, int nparts, double* __restrict__ out) {
@@ -309,14 +325,24 @@ __global__ void dots_final_kernel(const double* __restrict__ partial, int nparts
   if (threadIdx.x == 0) out[v] = sh[0];
 }
 
+// w[rz] += sign * sum_v coef[v * nr + rz] V_v[rz] over stacked segments of length n
 __global__ void axpy_multi_kernel(double* __restrict__ w, const double* __restrict__ V, long long ld, int nvec,
-                                  const double* __restrict__ coef, double sign, long long n) {
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+                                  const double* __restrict__ coef, double sign, long long n, int nr) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n * nr;
        e += (long long)gridDim.x * blockDim.x) {
+    const long long rz = e / n;
     double acc = 0;
-    for (int v = 0; v < nvec; ++v) acc += coef[v] * V[v * ld + e];
+    for (int v = 0; v < nvec; ++v) acc += coef[(long long)v * nr + rz] * V[v * ld + e];
     w[e] += sign * acc;
   }
+}
+
+// y[rz] = scale[rz] * x[rz] over stacked segments of length n (scale on the device)
+__global__ void scale_seg_kernel(double* __restrict__ y, const double* __restrict__ x,
+                                 const double* __restrict__ scale, long long n, int nr) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n * nr;
+       e += (long long)gridDim.x * blockDim.x)
+    y[e] = scale[e / n] * x[e];
 }
 
 __global__ void axpby_kernel(double* __restrict__ y, double a, const double* __restrict__ x, double b,
@@ -339,14 +365,15 @@ int dots_partials() { return kDotBlocks; }
 void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double* x, double* out,
                     hipStream_t st) {
   const long long nc = h->ncell;
-  const int g = std::min(grid_for(nc), 4096);
+  const int nr = h->n_rhs;
+  const int g = std::min(grid_for(nc * nr), 4096);
   const int nx = (int)h->n[0], ny = (int)h->n[1];
   if (scheme == LMDG_SCHEME_STD) {
     if (prec == LMDG_PREC_FP64)
-      hipLaunchKernelGGL(combine_std_kernel<double>, dim3(g), dim3(kBlock), 0, st, mode, nc, x,
+      hipLaunchKernelGGL(combine_std_kernel<double>, dim3(g), dim3(kBlock), 0, st, mode, nr, nc, x,
                          (const double*)h->ws.part, out);
     else
-      hipLaunchKernelGGL(combine_std_kernel<float>, dim3(g), dim3(kBlock), 0, st, mode, nc, x,
+      hipLaunchKernelGGL(combine_std_kernel<float>, dim3(g), dim3(kBlock), 0, st, mode, nr, nc, x,
                          (const float*)h->ws.part, out);
     return;
   }
@@ -358,7 +385,7 @@ void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double
     qm.ay[q] = h->qay[q];
   }
 #define LMDG_COMBINE(R, RLM)                                                                        \
-  hipLaunchKernelGGL((combine_lm_kernel<R, RLM>), dim3(g), dim3(kBlock), 0, st, mode, nx, ny, hx, hy, \
+  hipLaunchKernelGGL((combine_lm_kernel<R, RLM>), dim3(g), dim3(kBlock), 0, st, mode, nr, nx, ny, hx, hy, \
                      h->cplus[0], h->cminus[0], h->cplus[1], h->cminus[1], qm, x,                    \
                      (const R*)h->ws.part, h->d_sigtA, h->d_scatA, h->d_absA, out)
   const bool rlm = scheme == LMDG_SCHEME_RLMDG;
@@ -373,13 +400,13 @@ void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double
 void launch_sum_quadrants(lmdg_handle* h, int scheme, int prec, double* out, hipStream_t st) {
   const int nout = scheme == LMDG_SCHEME_STD ? 4 : (scheme == LMDG_SCHEME_LMDG ? 3 : 6);
   const int nout_abi = scheme == LMDG_SCHEME_RLMDG ? 6 : 4;
-  const int g = std::min(grid_for(h->ncell), 4096);
+  const int g = std::min(grid_for(h->ncell * h->n_rhs), 4096);
   if (prec == LMDG_PREC_FP64)
-    hipLaunchKernelGGL(sum_quadrants_kernel<double>, dim3(g), dim3(kBlock), 0, st, nout, nout_abi, h->ncell,
-                       (const double*)h->ws.part, out);
+    hipLaunchKernelGGL(sum_quadrants_kernel<double>, dim3(g), dim3(kBlock), 0, st, nout, nout_abi, h->n_rhs,
+                       h->ncell, (const double*)h->ws.part, out);
   else
-    hipLaunchKernelGGL(sum_quadrants_kernel<float>, dim3(g), dim3(kBlock), 0, st, nout, nout_abi, h->ncell,
-                       (const float*)h->ws.part, out);
+    hipLaunchKernelGGL(sum_quadrants_kernel<float>, dim3(g), dim3(kBlock), 0, st, nout, nout_abi, h->n_rhs,
+                       h->ncell, (const float*)h->ws.part, out);
 }
 
 void launch_b11(lmdg_handle* h, const double* x, double* y, hipStream_t st) {
@@ -396,15 +423,20 @@ void launch_gradients(lmdg_handle* h, int npsi, const double* phi, const double*
 }
 
 void vec_dots(const double* V, long long ld, int nvec, const double* w, long long n, double* partial,
-              double* out, hipStream_t st) {
-  hipLaunchKernelGGL(dots_partial_kernel, dim3(kDotBlocks, nvec), dim3(kBlock), 0, st, V, ld, w, n, partial);
-  hipLaunchKernelGGL(dots_final_kernel, dim3(nvec), dim3(kBlock), 0, st, partial, kDotBlocks, out);
+              double* out, hipStream_t st, int nr) {
+  hipLaunchKernelGGL(dots_partial_kernel, dim3(kDotBlocks, nvec, nr), dim3(kBlock), 0, st, V, ld, w, n, partial);
+  hipLaunchKernelGGL(dots_final_kernel, dim3(nvec * nr), dim3(kBlock), 0, st, partial, kDotBlocks, out);
+}
+
+void vec_scale_seg(double* y, const double* x, const double* scale, long long n, int nr, hipStream_t st) {
+  hipLaunchKernelGGL(scale_seg_kernel, dim3(std::min(grid_for(n * nr), 4096)), dim3(kBlock), 0, st, y, x, scale, n,
+                     nr);
 }
 
 void vec_axpy_multi(double* w, const double* V, long long ld, int nvec, const double* coef, double sign,
-                    long long n, hipStream_t st) {
-  hipLaunchKernelGGL(axpy_multi_kernel, dim3(std::min(grid_for(n), 4096)), dim3(kBlock), 0, st, w, V, ld, nvec,
-                     coef, sign, n);
+                    long long n, hipStream_t st, int nr) {
+  hipLaunchKernelGGL(axpy_multi_kernel, dim3(std::min(grid_for(n * nr), 4096)), dim3(kBlock), 0, st, w, V, ld, nvec,
+                     coef, sign, n, nr);
 }
 
 void vec_axpby(double* y, double a, const double* x, double b, long long n, hipStream_t st) {

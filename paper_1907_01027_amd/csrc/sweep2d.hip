@@ -238,7 +238,8 @@ __device__ __forceinline__ void cell_std(const Dir<R>& d, const R* src, R sigtA,
 //               and the same four material values
 // Values outside the mesh are zero (zero exterior traces, vacuum inflow).
 template <typename R, int S>
-__device__ __forceinline__ void raw_load(const SweepParams<R>& P, int sxi, int syi, int c, int jr, double* raw) {
+__device__ __forceinline__ void raw_load(const SweepParams<R>& P, const double* x, const double* qA, int sxi, int syi,
+                                         int c, int jr, double* raw) {
   constexpr int NRAW = SrcTraits<S>::NRAW;
 #pragma unroll
   for (int k = 0; k < NRAW; ++k) raw[k] = 0.0;
@@ -249,7 +250,6 @@ __device__ __forceinline__ void raw_load(const SweepParams<R>& P, int sxi, int s
   const int j = syi > 0 ? jr : P.ny - 1 - jr;
   const long long cell = (long long)j * nx + i;
   const long long sxs = sxi, sys = (long long)syi * nx;  // cell - sxs, cell - sys: upwind
-  const double* x = P.x;
   if constexpr (S == LMDG_SCHEME_STD) {
     if (x) {
 #pragma unroll
@@ -266,7 +266,7 @@ __device__ __forceinline__ void raw_load(const SweepParams<R>& P, int sxi, int s
     raw[12] = P.sigtA[cell];
     raw[13] = P.absA[cell];
     raw[14] = P.scatA[cell];
-    raw[15] = P.qA ? P.qA[cell] : 0.0;
+    raw[15] = qA ? qA[cell] : 0.0;
     if (P.qS) {
 #pragma unroll
       for (int m = 0; m < 3; ++m) raw[16 + m] = P.qS[m * nc + cell];
@@ -286,7 +286,7 @@ __device__ __forceinline__ void raw_load(const SweepParams<R>& P, int sxi, int s
     raw[9] = P.sigtA[cell];
     raw[10] = P.absA[cell];
     raw[11] = P.scatA[cell];
-    raw[12] = P.qA ? P.qA[cell] : 0.0;
+    raw[12] = qA ? qA[cell] : 0.0;
   }
 }
 
@@ -438,8 +438,17 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
     __syncthreads();
     const int item = s_item;
     if (item >= P.n_items) break;
+    // item = (strip * n_rhs + rhs) * 4 + quadrant: every item comes after the one
+    // it waits for (same quadrant and right-hand side, strip below)
     const int q = item & 3;
-    const int s = item >> 2;
+    const int s = (item >> 2) / P.n_rhs;
+    const int rh = (item >> 2) - s * P.n_rhs;
+    const double* xr = P.x ? P.x + (long long)rh * 4 * nc : nullptr;
+    const double* qAr = P.qA ? P.qA + (long long)rh * nc : nullptr;
+    R* const partr = P.part + (long long)rh * 4 * NOUT * nc;
+    R* const edger = P.edge + rh * P.edge_rstride;
+    unsigned long long* const progr = P.prog + (long long)rh * 4 * P.nstrips;
+    double* const psir = P.psi ? P.psi + rh * P.psi_rstride : nullptr;
     const int sxi = (q & 1) ? -1 : 1;
     const int syi = (q & 2) ? -1 : 1;
 
@@ -473,7 +482,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
         const int e = tid + m * blockDim.x;
         const int rr = e >> lcw, tt = e & (cw - 1);
         const int c = (e < ncells) ? (k << lcw) + tt - rr : -1;
-        raw_load<R, S>(P, sxi, syi, c, s * kRows + rr, raw[m]);
+        raw_load<R, S>(P, xr, qAr, sxi, syi, c, s * kRows + rr, raw[m]);
       }
     };
     auto stage_store = [&](int k, int buf) {
@@ -500,7 +509,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
       if (s > 0 && tid == 0) {
         const int need = min(nx, t0 + cw);
         const unsigned long long target = (P.epoch << 32) | (unsigned long long)need;
-        const unsigned long long* flag = P.prog + (long long)q * P.nstrips + (s - 1);
+        const unsigned long long* flag = progr + (long long)q * P.nstrips + (s - 1);
         long long spins = 0;
         while (load_agent(flag) < target) {
           __builtin_amdgcn_s_sleep(2);
@@ -512,7 +521,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
       // traces of the strip below for the columns of this chunk (zero for the first strip)
       {
         const int ne = (cw * NF) * P.dslots;
-        const R* src = P.edge + (((long long)q * P.nstrips + (s - 1)) * nx + t0) * NF * P.dslots;
+        const R* src = edger + (((long long)q * P.nstrips + (s - 1)) * nx + t0) * NF * P.dslots;
         for (int e = tid; e < ne; e += blockDim.x) {
           const int c = t0 + e / (NF * P.dslots);
           eds[e] = (s > 0 && c < nx) ? load_agent(src + e) : R(0);
@@ -616,13 +625,13 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
           for (int u = 0; u < U; ++u) {
             const int c = t0 + tg + u - r;
             if (row_ok && c >= 0 && c < nx) {
-              R* e = P.edge + ((((long long)q * P.nstrips + s) * nx + c) * NF) * P.dslots + slot;
+              R* e = edger + ((((long long)q * P.nstrips + s) * nx + c) * NF) * P.dslots + slot;
 #pragma unroll
               for (int f = 0; f < NF; ++f) store_agent(e + (long long)f * P.dslots, yo_g[u][f]);
             }
           }
         }
-        if (P.psi && d.idx >= 0) {
+        if (psir && d.idx >= 0) {
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const int c = t0 + tg + u - r;
@@ -630,10 +639,10 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
               const int i = sxi > 0 ? c : nx - 1 - c;
               const long long cell = (long long)j * nx + i;
               if constexpr (LM) {
-                P.psi[(long long)d.idx * nc + cell] = (double)psi_g[u][0];
+                psir[(long long)d.idx * nc + cell] = (double)psi_g[u][0];
               } else {
 #pragma unroll
-                for (int m = 0; m < 4; ++m) P.psi[((long long)d.idx * 4 + m) * nc + cell] = (double)psi_g[u][m];
+                for (int m = 0; m < 4; ++m) psir[((long long)d.idx * 4 + m) * nc + cell] = (double)psi_g[u][m];
               }
             }
           }
@@ -654,14 +663,14 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
           for (int w2 = 0; w2 < W; ++w2) acc += red[((tt * W + w2) * NOUT + m) * kRows + rr];
           const int i = sxi > 0 ? c : nx - 1 - c;
           const int jj = syi > 0 ? jr2 : ny - 1 - jr2;
-          P.part[((long long)q * NOUT + m) * nc + (long long)jj * nx + i] = acc;
+          partr[((long long)q * NOUT + m) * nc + (long long)jj * nx + i] = acc;
         }
       }
       if (s + 1 < P.nstrips && tid == 0) {
         const int done = min(nx, t0 + cw - (kRows - 1));
         if (done > 0) {
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          store_agent(P.prog + (long long)q * P.nstrips + s, (P.epoch << 32) | (unsigned long long)done);
+          store_agent(progr + (long long)q * P.nstrips + s, (P.epoch << 32) | (unsigned long long)done);
         }
       }
     }
@@ -695,7 +704,8 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   P.lcw = 0;
   while ((1 << P.lcw) < cw) ++P.lcw;
   P.nchunks = (P.nx + kRows - 1 + cw - 1) / cw;
-  P.n_items = 4 * h->nstrips;
+  P.n_rhs = h->n_rhs;
+  P.n_items = 4 * h->nstrips * h->n_rhs;
   P.hx = h->h[0];
   P.hy = h->h[1];
   P.ncell = h->ncell;
@@ -710,6 +720,8 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   P.part = reinterpret_cast<R*>(h->ws.part);
   P.edge = reinterpret_cast<R*>(h->ws.edge);
   P.psi = psi;
+  P.psi_rstride = (long long)h->ndir * (S == LMDG_SCHEME_STD ? 4 : 1) * h->ncell;
+  P.edge_rstride = (long long)4 * h->nstrips * P.nx * SchemeTraits<S>::NF * h->dslots;
   P.prog = h->ws.prog;
   P.ticket = h->ws.ticket;
   P.err = h->ws.err;

@@ -27,7 +27,7 @@ PRECS = {"fp64": 0, "fp32": 1}
 MODES = {"fp64": 0, "mixed": 1}
 
 EXPORTED = ["lmdg_status_string", "lmdg_last_error", "lmdg_quadrature_level_symmetric", "lmdg_create",
-            "lmdg_destroy", "lmdg_set_materials", "lmdg_sweep", "lmdg_apply", "lmdg_rhs",
+            "lmdg_destroy", "lmdg_set_materials", "lmdg_set_sources", "lmdg_sweep", "lmdg_apply", "lmdg_rhs",
             "lmdg_recover", "lmdg_solve", "lmdg_adjoint_solve", "lmdg_profile", "lmdg_sweep_kernel_time"]
 
 
@@ -58,6 +58,7 @@ def _load():
         "lmdg_create": (I, [I, P, P, I, P, P, ctypes.POINTER(P)]),
         "lmdg_destroy": (None, [P]),
         "lmdg_set_materials": (I, [P, P, P, P, P, P, P]),
+        "lmdg_set_sources": (I, [P, I, P, P]),
         "lmdg_sweep": (I, [P, I, I, P, I, P, P, P]),
         "lmdg_apply": (I, [P, I, I, P, P, P]),
         "lmdg_rhs": (I, [P, I, I, P, P]),
@@ -150,6 +151,12 @@ def lmdg_destroy(h):
 def lmdg_set_materials(h, sigma_s, sigma_a, eps, q, alpha=None, stream=None):
     _check(_lib.lmdg_set_materials(h, _ptr(sigma_s), _ptr(sigma_a), _ptr(eps), _ptr(q), _ptr(alpha),
                                    _stream(stream)), h)
+
+
+def lmdg_set_sources(h, q, stream=None):
+    """q: CUDA float64 tensor (n_rhs, n_cells) or (n_cells,); sets the handle's right-hand sides."""
+    n_rhs = 1 if q.dim() == 1 else int(q.shape[0])
+    _check(_lib.lmdg_set_sources(h, n_rhs, _ptr(q), _stream(stream)), h)
 
 
 def lmdg_sweep(h, scheme, prec, x, use_q, out, psi=None, stream=None):

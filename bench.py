@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--solve-max-iter", type=int, default=4000)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the secondary measurements (other workloads, several sources, small solves)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 64 MiB five times (HBM counter calibration)")
     return ap.parse_args()
@@ -106,6 +108,78 @@ def cpu_baseline(seconds):
                       f"FP64) on the 128x128 S8 mesh of the same seeded recipe; {k} applications in "
                       f"{el:.1f} s after {setup:.1f} s of assembly and factorisation; single-threaded "
                       f"SciPy/NumPy (host has {os.cpu_count()} logical CPUs)"}
+
+
+def _apply_rate(torch, lmdg, h, scheme, prec, x, y, ncell, ndir, n_rhs=1, reps=5):
+    for _ in range(2):
+        lmdg.lmdg_apply(h, scheme, prec, x, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lmdg.lmdg_apply(h, scheme, prec, x, y)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    return {"ms_per_apply": 1e3 * el, "updates_per_s": ncell * ndir * n_rhs / el}
+
+
+def extra_measurements(torch, lmdg, WORKLOADS, materials):
+    """Secondary figures: operator throughput on the other 2D workloads (FP64 and FP32
+    sweeps), eight sources swept together, and FP64 vs mixed solves of the 20x20 S4
+    workload to 1e-8 and 1e-10 (the case that converges without preconditioning)."""
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    res = {}
+    for key in (3, 4):
+        wl = WORKLOADS[key]
+        ss, sa, ep, q = materials(key)
+        om, w = lmdg.lmdg_quadrature_level_symmetric(2, wl.order)
+        s = lmdg.Solver(wl.n, (1.0, 1.0), om, w)
+        lmdg.lmdg_set_materials(s.h, T(ss), T(sa), T(ep), T(q[0]))
+        nc = wl.n[0] * wl.n[1]
+        x = T(np.random.default_rng(1).normal(size=4 * nc))
+        y = torch.empty_like(x)
+        res[f"{wl.n[0]}x{wl.n[1]}_S{wl.order}_{wl.scheme}"] = {
+            p: _apply_rate(torch, lmdg, s.h, wl.scheme, p, x, y, nc, len(w)) for p in ("fp64", "fp32")}
+        s.close()
+    # eight sources on the benchmark mesh, swept together
+    wl = WORKLOADS[2]
+    ss, sa, ep, q = materials(2)
+    om, w = lmdg.lmdg_quadrature_level_symmetric(2, wl.order)
+    s = lmdg.Solver(wl.n, (1.0, 1.0), om, w)
+    lmdg.lmdg_set_materials(s.h, T(ss), T(sa), T(ep), T(q[0]))
+    nc = wl.n[0] * wl.n[1]
+    qs = np.random.default_rng(20190708).uniform(0.0, 1.0, size=(8, nc))
+    lmdg.lmdg_set_sources(s.h, T(qs))
+    x = T(np.random.default_rng(2).normal(size=8 * 4 * nc))
+    y = torch.empty_like(x)
+    res["256x256_S8_rlmdg_8_sources"] = {
+        p: _apply_rate(torch, lmdg, s.h, "rlmdg", p, x, y, nc, len(w), n_rhs=8) for p in ("fp64", "fp32")}
+    s.close()
+    # 20x20, S4, eps = 1: solve times to 1e-8 and 1e-10, FP64 vs mixed
+    wl = WORKLOADS[1]
+    ss, sa, ep, q = materials(1)
+    om, w = lmdg.lmdg_quadrature_level_symmetric(2, wl.order)
+    s = lmdg.Solver(wl.n, (1.0, 1.0), om, w)
+    lmdg.lmdg_set_materials(s.h, T(ss), T(sa), T(ep), T(q[0]))
+    nc = wl.n[0] * wl.n[1]
+    xs = torch.zeros(4 * nc, dtype=torch.float64, device=dev)
+    phi = torch.zeros_like(xs)
+    solves = {}
+    for scheme in ("std", "lmdg"):
+        for tol in (1e-8, 1e-10):
+            for mode in ("fp64", "mixed"):
+                lmdg.lmdg_solve(s.h, scheme, mode, tol, 30, 2000, xs, phi)  # warm
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = lmdg.lmdg_solve(s.h, scheme, mode, tol, 30, 2000, xs, phi)
+                torch.cuda.synchronize()
+                solves[f"{scheme}_{mode}_tol{tol:g}"] = {"wall_ms": 1e3 * (time.perf_counter() - t0),
+                                                         "iterations": info["iterations"],
+                                                         "ir_passes": info["ir_passes"],
+                                                         "rel_residual": info["rel_residual"]}
+    res["20x20_S4_eps1_solves"] = solves
+    s.close()
+    return res
 
 
 def main():
@@ -188,9 +262,11 @@ def main():
             info["wall_s"] = time.perf_counter() - t0
             res[mode] = info
         out["solve"] = {"tol": 1e-8, "restart": 60, "max_iter": args.solve_max_iter, **res}
+    solver.close()
+    if not args.no_extra:
+        out["extra"] = extra_measurements(torch, lmdg, WORKLOADS, materials)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
-    solver.close()
     print(json.dumps(out), flush=True)
 
 

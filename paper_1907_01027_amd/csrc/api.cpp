@@ -207,54 +207,98 @@ int lmdg_quadrature_level_symmetric(int dim, int order, int capacity, int* n_dir
   return LMDG_OK;
 }
 
+// Grow the per-right-hand-side workspaces (partials, strip edges, z-trace ring,
+// progress words, scratch vectors, sources) to n_rhs right-hand sides.
+static int ensure_rhs_capacity(lmdg_t* h, int n_rhs) {
+  using namespace lmdg;
+  if (n_rhs <= h->rhs_cap) return LMDG_OK;
+  hipDeviceSynchronize();
+  const long long nc = h->ncell;
+  void* olds[] = {h->ws.part, h->ws.edge, h->ws.zbuf, h->ws.prog, h->ws.vec, h->d_qA};
+  for (void* p : olds)
+    if (p) hipFree(p);
+  h->ws.part = nullptr;
+  h->ws.edge = nullptr;
+  h->ws.zbuf = nullptr;
+  h->ws.prog = nullptr;
+  h->ws.vec = nullptr;
+  h->d_qA = nullptr;
+  h->rhs_cap = 0;
+  const size_t nr = (size_t)n_rhs;
+  int rc = check_hip(h, hipMalloc((void**)&h->ws.part, h->ws.part_bytes * nr), "hipMalloc");
+  if (rc == LMDG_OK) rc = check_hip(h, hipMalloc(&h->ws.edge, std::max<size_t>(h->ws.edge_bytes * nr, 8)), "hipMalloc");
+  if (rc == LMDG_OK && h->ws.zbuf_bytes)
+    rc = check_hip(h, hipMalloc(&h->ws.zbuf, h->ws.zbuf_bytes * nr), "hipMalloc");
+  if (rc == LMDG_OK)
+    rc = check_hip(h, hipMalloc((void**)&h->ws.prog, h->ws.prog_words * nr * sizeof(unsigned long long)), "hipMalloc");
+  if (rc == LMDG_OK)
+    rc = check_hip(h, hipMalloc((void**)&h->ws.vec, (size_t)kScratchVecs * h->np * nc * nr * sizeof(double)),
+                   "hipMalloc");
+  if (rc == LMDG_OK) rc = check_hip(h, hipMalloc((void**)&h->d_qA, (size_t)nc * nr * sizeof(double)), "hipMalloc");
+  if (rc == LMDG_OK)
+    rc = check_hip(h, hipMemset(h->ws.prog, 0, h->ws.prog_words * nr * sizeof(unsigned long long)), "clear flags");
+  if (rc == LMDG_OK) rc = check_hip(h, hipDeviceSynchronize(), "workspaces");
+  if (rc == LMDG_OK) h->rhs_cap = n_rhs;
+  return rc;
+}
+
 int lmdg_create(int dim, const int64_t* n, const double* length, int n_dir, const double* omega,
                 const double* w, lmdg_t** out) {
   using namespace lmdg;
   if (!out || !n || !length || !omega || !w) return LMDG_INVALID_ARG;
   *out = nullptr;
-  if (dim != 2) return LMDG_UNSUPPORTED;
-  if (n[0] < 1 || n[1] < 1 || !(length[0] > 0) || !(length[1] > 0) || n_dir < 1) return LMDG_INVALID_ARG;
-  if (n[0] > (1 << 20) || n[1] > (1 << 20) || n[0] * n[1] > (1ll << 31)) return LMDG_INVALID_ARG;
+  if (dim != 2 && dim != 3) return LMDG_UNSUPPORTED;
+  long long ncell = 1;
+  for (int a = 0; a < dim; ++a) {
+    if (n[a] < 1 || n[a] > (1 << 20) || !(length[a] > 0) || !std::isfinite(length[a])) return LMDG_INVALID_ARG;
+    ncell *= n[a];
+  }
+  if (n_dir < 1 || ncell > (1ll << 31)) return LMDG_INVALID_ARG;
   // eq-polyquad (i)-(iii), positive weights, no zero component
-  double s0 = 0, s1[2] = {0, 0}, s2[2][2] = {{0, 0}, {0, 0}};
+  double s0 = 0, s1[3] = {0, 0, 0}, s2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   for (int l = 0; l < n_dir; ++l) {
     if (!(w[l] > 0) || !std::isfinite(w[l])) return LMDG_INVALID_ARG;
-    for (int a = 0; a < 2; ++a)
-      if (!std::isfinite(omega[2 * l + a]) || omega[2 * l + a] == 0.0) return LMDG_INVALID_ARG;
+    for (int a = 0; a < dim; ++a)
+      if (!std::isfinite(omega[dim * l + a]) || omega[dim * l + a] == 0.0) return LMDG_INVALID_ARG;
     s0 += w[l];
-    for (int a = 0; a < 2; ++a) {
-      s1[a] += w[l] * omega[2 * l + a];
-      for (int b = 0; b < 2; ++b) s2[a][b] += w[l] * omega[2 * l + a] * omega[2 * l + b];
+    for (int a = 0; a < dim; ++a) {
+      s1[a] += w[l] * omega[dim * l + a];
+      for (int b = 0; b < dim; ++b) s2[a][b] += w[l] * omega[dim * l + a] * omega[dim * l + b];
     }
   }
   const double tq = 1e-12;
   if (std::fabs(s0 - 1) > tq) return LMDG_INVALID_ARG;
-  for (int a = 0; a < 2; ++a) {
+  for (int a = 0; a < dim; ++a) {
     if (std::fabs(s1[a]) > tq) return LMDG_INVALID_ARG;
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < dim; ++b)
       if (std::fabs(s2[a][b] - (a == b ? 1.0 / 3.0 : 0.0)) > tq) return LMDG_INVALID_ARG;
   }
   lmdg_handle* h = new (std::nothrow) lmdg_handle();
   if (!h) return LMDG_HIP_ERROR;
-  h->dim = 2;
-  for (int a = 0; a < 2; ++a) {
+  h->dim = dim;
+  h->np = dim == 2 ? 4 : 8;
+  h->noct = 1 << dim;
+  h->area = 1.0;
+  for (int a = 0; a < dim; ++a) {
     h->n[a] = n[a];
     h->len[a] = length[a];
     h->h[a] = length[a] / (double)n[a];
+    h->area *= h->h[a];
   }
-  h->area = h->h[0] * h->h[1];
-  h->ncell = n[0] * n[1];
+  h->ncell = ncell;
   h->ndir = n_dir;
-  h->omega.assign(omega, omega + 2 * n_dir);
+  h->omega.assign(omega, omega + dim * n_dir);
   h->w.assign(w, w + n_dir);
-  // quadrant q: bit 0 set when Omega_x < 0, bit 1 when Omega_y < 0
-  std::vector<int> byq[4];
-  for (int l = 0; l < n_dir; ++l) {
-    const int q = (omega[2 * l] < 0 ? 1 : 0) | (omega[2 * l + 1] < 0 ? 2 : 0);
-    byq[q].push_back(l);
-  }
+  // quadrant / octant q: bit a set when Omega_a < 0
+  auto octant = [&](int l) {
+    int q = 0;
+    for (int a = 0; a < dim; ++a) q |= (omega[dim * l + a] < 0 ? 1 : 0) << a;
+    return q;
+  };
+  std::vector<int> byq[8];
+  for (int l = 0; l < n_dir; ++l) byq[octant(l)].push_back(l);
   size_t dmax = 1;
-  for (auto& v : byq) dmax = std::max(dmax, v.size());
+  for (int q = 0; q < h->noct; ++q) dmax = std::max(dmax, byq[q].size());
   if (dmax > (size_t)kMaxSlots) {
     delete h;
     return LMDG_INVALID_ARG;
@@ -262,84 +306,81 @@ int lmdg_create(int dim, const int64_t* n, const double* length, int n_dir, cons
   h->dslots = (int)((dmax + 3) / 4 * 4);
   h->waves = h->dslots / 4;
   h->nstrips = (int)((n[1] + kRows - 1) / kRows);
-  std::vector<double> tab(4 * h->dslots * kDirStride, 0.0);
-  h->slot_dir.assign(4 * h->dslots, -1);
-  for (int q = 0; q < 4; ++q) {
+  // direction table: 2D entries (Ox, Oy, w, index), 3D entries (Ox, Oy, Oz, w, index)
+  std::vector<double> tab((size_t)h->noct * h->dslots * kDirStride, 0.0);
+  h->slot_dir.assign((size_t)h->noct * h->dslots, -1);
+  for (int q = 0; q < h->noct; ++q) {
     // padding slots copy a real direction of the quadrant (or the quadrant's sign
     // pattern) with zero weight, so they compute finite values and contribute nothing
-    double ox = (q & 1) ? -0.5 : 0.5, oy = (q & 2) ? -0.5 : 0.5;
-    if (!byq[q].empty()) {
-      ox = omega[2 * byq[q][0]];
-      oy = omega[2 * byq[q][0] + 1];
-    }
+    double pad[3];
+    for (int a = 0; a < dim; ++a) pad[a] = ((q >> a) & 1) ? -0.5 : 0.5;
+    if (!byq[q].empty())
+      for (int a = 0; a < dim; ++a) pad[a] = omega[dim * byq[q][0] + a];
     for (int sl = 0; sl < h->dslots; ++sl) {
-      double* e = &tab[(q * h->dslots + sl) * kDirStride];
-      if (sl < (int)byq[q].size()) {
-        const int l = byq[q][sl];
-        e[0] = omega[2 * l];
-        e[1] = omega[2 * l + 1];
-        e[2] = w[l];
-        e[3] = l;
-        h->slot_dir[q * h->dslots + sl] = l;
-      } else {
-        e[0] = ox;
-        e[1] = oy;
-        e[2] = 0.0;
-        e[3] = -1;
-      }
+      double* e = &tab[((size_t)q * h->dslots + sl) * kDirStride];
+      const bool real = sl < (int)byq[q].size();
+      const int l = real ? byq[q][sl] : -1;
+      for (int a = 0; a < dim; ++a) e[a] = real ? omega[dim * l + a] : pad[a];
+      e[dim] = real ? w[l] : 0.0;
+      e[dim + 1] = l;
+      h->slot_dir[(size_t)q * h->dslots + sl] = l;
     }
   }
-  for (int l = 0; l < n_dir; ++l)
-    for (int a = 0; a < 2; ++a) {
-      const double o = omega[2 * l + a];
-      if (o > 0) h->cplus[a] += w[l] * o; else h->cminus[a] += w[l] * (-o);
-    }
   for (int l = 0; l < n_dir; ++l) {
-    const int q = (omega[2 * l] < 0 ? 1 : 0) | (omega[2 * l + 1] < 0 ? 2 : 0);
+    const int q = octant(l);
     h->qw[q] += w[l];
-    h->qax[q] += w[l] * std::fabs(omega[2 * l]);
-    h->qay[q] += w[l] * std::fabs(omega[2 * l + 1]);
+    double* qa[3] = {h->qax, h->qay, h->qaz};
+    for (int a = 0; a < dim; ++a) {
+      const double o = omega[dim * l + a];
+      if (o > 0) h->cplus[a] += w[l] * o; else h->cminus[a] += w[l] * (-o);
+      qa[a][q] += w[l] * std::fabs(o);
+    }
   }
   // -Omega_l for every l (central symmetry), used by the adjoint; -1 when absent
   h->neg_dir.assign(n_dir, -1);
   for (int l = 0; l < n_dir; ++l)
-    for (int k = 0; k < n_dir; ++k)
-      if (std::fabs(omega[2 * k] + omega[2 * l]) <= 1e-12 && std::fabs(omega[2 * k + 1] + omega[2 * l + 1]) <= 1e-12 &&
-          std::fabs(w[k] - w[l]) <= 1e-12 * w[l]) {
+    for (int k = 0; k < n_dir; ++k) {
+      bool match = std::fabs(w[k] - w[l]) <= 1e-12 * w[l];
+      for (int a = 0; a < dim; ++a) match = match && std::fabs(omega[dim * k + a] + omega[dim * l + a]) <= 1e-12;
+      if (match) {
         h->neg_dir[l] = k;
         break;
       }
+    }
+  // per-right-hand-side workspace sizes
+  const long long nc = h->ncell;
+  if (dim == 2) {
+    h->ws.part_bytes = (size_t)4 * 6 * nc * sizeof(double);
+    h->ws.edge_bytes = (size_t)4 * h->nstrips * n[0] * 3 * h->dslots * sizeof(double);
+    h->ws.zbuf_bytes = 0;
+    h->ws.prog_words = (size_t)4 * h->nstrips;
+  } else {
+    h->ws.part_bytes = (size_t)8 * 10 * nc * sizeof(double);
+    h->ws.edge_bytes = (size_t)8 * n[2] * h->nstrips * n[0] * 4 * h->dslots * sizeof(double);
+    h->ws.zbuf_bytes = (size_t)8 * 2 * n[1] * n[0] * 4 * h->dslots * sizeof(double);
+    h->ws.prog_words = (size_t)8 * n[2] * h->nstrips;
+  }
   int dev = 0;
   hipGetDevice(&dev);
   h->device = dev;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
     h->n_cu = prop.multiProcessorCount;
-  const long long nc = h->ncell;
-  int st = LMDG_OK;
-  auto alloc = [&](void** p, size_t bytes) {
-    if (st != LMDG_OK) return;
-    st = check_hip(h, hipMalloc(p, std::max<size_t>(bytes, 8)), "hipMalloc");
-  };
-  alloc((void**)&h->d_dirs, tab.size() * sizeof(double));
-  alloc((void**)&h->ws.part, (size_t)4 * 6 * nc * sizeof(double));
-  h->ws.edge_bytes = (size_t)4 * h->nstrips * n[0] * 3 * h->dslots * sizeof(double);
-  alloc(&h->ws.edge, h->ws.edge_bytes);
-  alloc((void**)&h->ws.prog, (size_t)4 * h->nstrips * sizeof(unsigned long long));
-  alloc((void**)&h->ws.ticket, sizeof(unsigned int));
-  alloc((void**)&h->ws.err, sizeof(int));
-  alloc((void**)&h->ws.vec, (size_t)kScratchVecs * 4 * nc * sizeof(double));
-  alloc((void**)&h->d_adjtab, (size_t)2 * n_dir * sizeof(double));
+  h->rhs_cap = 0;
+  int st = check_hip(h, hipMalloc((void**)&h->d_dirs, tab.size() * sizeof(double)), "hipMalloc");
+  if (st == LMDG_OK) st = check_hip(h, hipMalloc((void**)&h->ws.ticket, sizeof(unsigned int)), "hipMalloc");
+  if (st == LMDG_OK) st = check_hip(h, hipMalloc((void**)&h->ws.err, sizeof(int)), "hipMalloc");
+  if (st == LMDG_OK) st = check_hip(h, hipMalloc((void**)&h->d_adjtab, (size_t)2 * n_dir * sizeof(double)), "hipMalloc");
+  if (st == LMDG_OK) st = ensure_rhs_capacity(h, 1);
   std::vector<double> adjtab(2 * n_dir);
   for (int l = 0; l < n_dir; ++l) {
     adjtab[2 * l] = w[l];
     adjtab[2 * l + 1] = h->neg_dir[l] >= 0 ? h->neg_dir[l] : l;
   }
-  if (st == LMDG_OK) st = check_hip(h, hipMemcpy(h->d_adjtab, adjtab.data(), adjtab.size() * sizeof(double),
-                                                 hipMemcpyHostToDevice), "copy direction map");
   if (st == LMDG_OK) st = check_hip(h, hipMemcpy(h->d_dirs, tab.data(), tab.size() * sizeof(double),
                                                  hipMemcpyHostToDevice), "copy directions");
-  if (st == LMDG_OK) st = check_hip(h, hipMemset(h->ws.prog, 0, (size_t)4 * h->nstrips * 8), "clear flags");
+  if (st == LMDG_OK) st = check_hip(h, hipMemcpy(h->d_adjtab, adjtab.data(), adjtab.size() * sizeof(double),
+                                                 hipMemcpyHostToDevice), "copy direction map");
   if (st == LMDG_OK) st = check_hip(h, hipMemset(h->ws.ticket, 0, sizeof(unsigned int)), "clear ticket");
   if (st == LMDG_OK) st = check_hip(h, hipMemset(h->ws.err, 0, sizeof(int)), "clear error flag");
   if (st == LMDG_OK) st = check_hip(h, hipDeviceSynchronize(), "create");
@@ -354,7 +395,7 @@ int lmdg_create(int dim, const int64_t* n, const double* length, int n_dir, cons
 void lmdg_destroy(lmdg_t* h) {
   if (!h) return;
   hipDeviceSynchronize();
-  void* ptrs[] = {h->d_dirs, h->d_sigtA, h->d_scatA, h->d_absA, h->d_qA, h->ws.part, h->ws.edge,
+  void* ptrs[] = {h->d_dirs, h->d_sigtA, h->d_scatA, h->d_absA, h->d_qA, h->ws.part, h->ws.edge, h->ws.zbuf,
                   h->ws.prog, h->ws.ticket, h->ws.err, h->ws.vec, h->d_krylov, h->d_small,
                   h->d_epsA, h->d_adjtab, h->d_psi_f, h->d_psi_a, h->d_cvec};
   for (void* p : ptrs)
@@ -362,39 +403,6 @@ void lmdg_destroy(lmdg_t* h) {
   if (h->h_small) hipHostFree(h->h_small);
   for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
   delete h;
-}
-
-// Grow the per-right-hand-side workspaces (partials, strip edges, progress words,
-// scratch vectors, sources) to n_rhs right-hand sides.
-static int ensure_rhs_capacity(lmdg_t* h, int n_rhs) {
-  using namespace lmdg;
-  if (n_rhs <= h->rhs_cap) return LMDG_OK;
-  hipDeviceSynchronize();
-  const long long nc = h->ncell;
-  void* olds[] = {h->ws.part, h->ws.edge, h->ws.prog, h->ws.vec, h->d_qA};
-  for (void* p : olds)
-    if (p) hipFree(p);
-  h->ws.part = nullptr;
-  h->ws.edge = nullptr;
-  h->ws.prog = nullptr;
-  h->ws.vec = nullptr;
-  h->d_qA = nullptr;
-  h->rhs_cap = 0;
-  int rc = check_hip(h, hipMalloc((void**)&h->ws.part, (size_t)4 * 6 * nc * n_rhs * sizeof(double)), "hipMalloc");
-  if (rc == LMDG_OK) rc = check_hip(h, hipMalloc(&h->ws.edge, h->ws.edge_bytes * n_rhs), "hipMalloc");
-  if (rc == LMDG_OK)
-    rc = check_hip(h, hipMalloc((void**)&h->ws.prog, (size_t)4 * h->nstrips * n_rhs * sizeof(unsigned long long)),
-                   "hipMalloc");
-  if (rc == LMDG_OK)
-    rc = check_hip(h, hipMalloc((void**)&h->ws.vec, (size_t)kScratchVecs * 4 * nc * n_rhs * sizeof(double)),
-                   "hipMalloc");
-  if (rc == LMDG_OK) rc = check_hip(h, hipMalloc((void**)&h->d_qA, (size_t)nc * n_rhs * sizeof(double)), "hipMalloc");
-  if (rc == LMDG_OK)
-    rc = check_hip(h, hipMemset(h->ws.prog, 0, (size_t)4 * h->nstrips * n_rhs * sizeof(unsigned long long)),
-                   "clear flags");
-  if (rc == LMDG_OK) rc = check_hip(h, hipDeviceSynchronize(), "workspaces");
-  if (rc == LMDG_OK) h->rhs_cap = n_rhs;
-  return rc;
 }
 
 int lmdg_set_materials(lmdg_t* h, const double* sigma_s, const double* sigma_a, const double* eps,
@@ -591,7 +599,7 @@ struct GmresStats {
 int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, double* x, double rtol, int m,
           int max_iter, hipStream_t st, GmresStats& stats, double& relres, bool& converged) {
   const int nr = h->n_rhs;
-  const long long N = 4 * h->ncell;  // one right-hand side
+  const long long N = (long long)h->np * h->ncell;  // one right-hand side
   const long long NT = N * nr;
   const SmallLayout L = small_layout(nr);
   int rc = ensure_krylov(h, (size_t)(m + 2) * NT);
@@ -805,8 +813,8 @@ static int solve_impl(lmdg_t* h, int scheme, int mode, double tol, int restart, 
   int rc = ensure_small(h, small_layout(nr).total);
   if (rc != LMDG_OK) return rc;
   const auto t_start = std::chrono::steady_clock::now();
-  const long long N = 4 * h->ncell * nr;  // all right-hand sides
-  const long long N1 = 4 * h->ncell;
+  const long long N = (long long)h->np * h->ncell * nr;  // all right-hand sides
+  const long long N1 = (long long)h->np * h->ncell;
   double* b = h->ws.vec;
   double* r = h->ws.vec + N;
   double* d = h->ws.vec + 2 * N;
@@ -901,7 +909,7 @@ int lmdg_solve(lmdg_t* h, int scheme, int mode, double tol, int restart, int max
 // Conjugate gradients on B_11 c = f_1 (B_11 symmetric positive definite, Sec. 3.2);
 // vectors in the moment-major layout with slot 0 held at zero.  Uses ws.vec[0..3).
 static int cg_b11(lmdg_t* h, const double* f, double* c, double rtol, hipStream_t st) {
-  const long long nc = h->ncell, N = 4 * nc;
+  const long long nc = h->ncell, N = (long long)h->np * nc;
   double* r = h->ws.vec;
   double* p = h->ws.vec + N;
   double* Ap = h->ws.vec + 2 * N;
@@ -940,6 +948,7 @@ int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, doubl
   if (rc != LMDG_OK) return rc;
   if (scheme == LMDG_SCHEME_RLMDG)
     return set_error(h, LMDG_UNSUPPORTED, "the adjoint covers the Galerkin schemes (standard, LMDG)");
+  if (h->dim != 2) return set_error(h, LMDG_UNSUPPORTED, "the adjoint solve is two-dimensional");
   if (!det || !g_sigma_s || !g_sigma_a || !g_q || !J_out || !(tol > 0) || restart < 1 || restart > 250 ||
       max_iter < 1 || (mode != LMDG_MODE_FP64 && mode != LMDG_MODE_MIXED))
     return set_error(h, LMDG_INVALID_ARG, "bad adjoint arguments");
@@ -947,7 +956,7 @@ int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, doubl
     if (h->neg_dir[l] < 0) return set_error(h, LMDG_INVALID_ARG, "quadrature is not centrally symmetric");
   if (h->n_rhs != 1) return set_error(h, LMDG_INVALID_ARG, "the adjoint solve takes one right-hand side");
   hipStream_t st = (hipStream_t)stream;
-  const long long nc = h->ncell, N = 4 * nc;
+  const long long nc = h->ncell, N = (long long)h->np * nc;
   const int npsi = scheme == LMDG_SCHEME_STD ? 4 : 1;
   const size_t psi_doubles = (size_t)h->ndir * npsi * nc;
   if (h->psi_doubles < psi_doubles) {

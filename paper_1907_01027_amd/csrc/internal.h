@@ -50,10 +50,40 @@ struct SweepParams {
   unsigned int ticket_base;
 };
 
+// Everything the 3D sweep kernel reads (LMDG, RLMDG); passed by value.
+template <typename R>
+struct Sweep3Params {
+  int nx, ny, nz, nstrips, cw, lcw, nchunks, dslots, n_items, n_rhs;
+  double h[3];
+  long long ncell;
+  const double* dirs;    // [8][dslots][kDirStride]: Ox, Oy, Oz, w, index
+  const double* x;       // moment vectors (n_rhs * 8 * ncell) or null
+  const double* sigtA;   // (sigma_s/eps + eps sigma_a) V
+  const double* scatA;   // (sigma_s/eps) V
+  const double* qA;      // eps q V (n_rhs * ncell) or null
+  const double* absA;    // eps sigma_a V
+  int defect;
+  R* part;               // [n_rhs][8][NOUT][ncell]
+  R* yedge;              // [n_rhs][8][nz][nstrips][nx][NF][dslots]
+  R* zbuf;               // [n_rhs][8][2][ny][nx][NF][dslots] (two-plane ring)
+  long long yedge_ostride, zbuf_ostride;   // per (rhs, octant)
+  double* psi;           // optional angular flux [n_rhs][n_dir][ncell]
+  long long psi_rstride;
+  unsigned long long* prog;   // [n_rhs][8][nz][nstrips]
+  unsigned int* ticket;
+  int* err;
+  unsigned long long epoch;
+  unsigned int ticket_base;
+};
+
 struct Workspace {
   double* part = nullptr;       // 4 * 6 * ncell doubles (reused as floats)
   void* edge = nullptr;
   size_t edge_bytes = 0;
+  void* zbuf = nullptr;          // 3D: two-plane ring of z traces
+  size_t zbuf_bytes = 0;          // per right-hand side
+  size_t part_bytes = 0;          // per right-hand side
+  size_t prog_words = 0;          // per right-hand side
   unsigned long long* prog = nullptr;
   unsigned int* ticket = nullptr;
   int* err = nullptr;
@@ -64,8 +94,8 @@ struct Workspace {
 
 struct lmdg_handle {
   int dim = 2;
-  int64_t n[2] = {0, 0};
-  double len[2] = {1, 1}, h[2] = {1, 1}, area = 1;
+  int64_t n[3] = {0, 0, 1};
+  double len[3] = {1, 1, 1}, h[3] = {1, 1, 1}, area = 1;   // area: cell measure (|K| in 2D, V in 3D)
   long long ncell = 0;
   int n_rhs = 1;                   // right-hand sides (sources) of the handle
   int rhs_cap = 1;                 // right-hand sides the workspaces are sized for
@@ -75,9 +105,10 @@ struct lmdg_handle {
   int dslots = 4, waves = 1, nstrips = 0;
   std::vector<int> slot_dir;      // [4][dslots], -1 = padding
   double* d_dirs = nullptr;
-  double cplus[2] = {0, 0}, cminus[2] = {0, 0};
-  // per-quadrant sums of w, w |Omega_x|, w |Omega_y| (used by the defect combine)
-  double qw[4] = {0, 0, 0, 0}, qax[4] = {0, 0, 0, 0}, qay[4] = {0, 0, 0, 0};
+  double cplus[3] = {0, 0, 0}, cminus[3] = {0, 0, 0};
+  int noct = 4;                    // quadrants (2D) or octants (3D)
+  // per-quadrant (octant) sums of w and w |Omega_a| (used by the defect combine)
+  double qw[8] = {0}, qax[8] = {0}, qay[8] = {0}, qaz[8] = {0};
   bool have_mat = false;
   double* d_sigtA = nullptr;
   double* d_scatA = nullptr;
@@ -121,9 +152,15 @@ constexpr int kScratchVecs = 4;
 // launchers (sweep2d.hip / ops.hip)
 int launch_sweep(lmdg_handle* h, int scheme, int prec, const double* x, bool use_q,
                  double* psi, hipStream_t st, bool defect = false);
+int launch_sweep3d(lmdg_handle* h, int scheme, int prec, const double* x, bool use_q, double* psi,
+                   hipStream_t st, bool defect);
 void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double* x,
                     double* out, hipStream_t st);
 void launch_sum_quadrants(lmdg_handle* h, int scheme, int prec, double* out, hipStream_t st);
+void launch_combine3(lmdg_handle* h, int scheme, int prec, int mode, const double* x, double* out,
+                     hipStream_t st);
+void launch_sum_octants(lmdg_handle* h, int scheme, int prec, double* out, hipStream_t st);
+void launch_b11_3d(lmdg_handle* h, const double* x, double* y, hipStream_t st);
 void launch_check_error(lmdg_handle* h, hipStream_t st);
 void launch_b11(lmdg_handle* h, const double* x, double* y, hipStream_t st);
 void launch_gradients(lmdg_handle* h, int npsi, const double* phi, const double* Lam, double* gs, double* ga,

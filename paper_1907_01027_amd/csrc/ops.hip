@@ -364,6 +364,10 @@ int dots_partials() { return kDotBlocks; }
 
 void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double* x, double* out,
                     hipStream_t st) {
+  if (h->dim == 3) {
+    launch_combine3(h, scheme, prec, mode, x, out, st);
+    return;
+  }
   const long long nc = h->ncell;
   const int nr = h->n_rhs;
   const int g = std::min(grid_for(nc * nr), 4096);
@@ -398,6 +402,10 @@ void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double
 }
 
 void launch_sum_quadrants(lmdg_handle* h, int scheme, int prec, double* out, hipStream_t st) {
+  if (h->dim == 3) {
+    launch_sum_octants(h, scheme, prec, out, st);
+    return;
+  }
   const int nout = scheme == LMDG_SCHEME_STD ? 4 : (scheme == LMDG_SCHEME_LMDG ? 3 : 6);
   const int nout_abi = scheme == LMDG_SCHEME_RLMDG ? 6 : 4;
   const int g = std::min(grid_for(h->ncell * h->n_rhs), 4096);
@@ -410,6 +418,10 @@ void launch_sum_quadrants(lmdg_handle* h, int scheme, int prec, double* out, hip
 }
 
 void launch_b11(lmdg_handle* h, const double* x, double* y, hipStream_t st) {
+  if (h->dim == 3) {
+    launch_b11_3d(h, x, y, st);
+    return;
+  }
   const int g = std::min(grid_for(h->ncell), 4096);
   hipLaunchKernelGGL(b11_apply_kernel, dim3(g), dim3(kBlock), 0, st, (int)h->n[0], (int)h->n[1], h->h[0], h->h[1],
                      h->cplus[0], h->cminus[0], h->cplus[1], h->cminus[1], x, h->d_absA, y);

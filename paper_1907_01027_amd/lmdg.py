@@ -135,10 +135,11 @@ def lmdg_create(n, length, omega, w):
     _init_torch_device()
     omega = np.ascontiguousarray(omega, dtype=np.float64)
     w = np.ascontiguousarray(w, dtype=np.float64)
-    nn = (ctypes.c_int64 * 2)(*[int(v) for v in n])
-    ll = (ctypes.c_double * 2)(*[float(v) for v in length])
+    dim = len(n)
+    nn = (ctypes.c_int64 * 3)(*([int(v) for v in n] + [1] * (3 - dim)))
+    ll = (ctypes.c_double * 3)(*([float(v) for v in length] + [1.0] * (3 - dim)))
     h = ctypes.c_void_p()
-    st = _lib.lmdg_create(2, nn, ll, int(w.size), omega.ctypes.data_as(ctypes.c_void_p),
+    st = _lib.lmdg_create(dim, nn, ll, int(w.size), omega.ctypes.data_as(ctypes.c_void_p),
                           w.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h))
     _check(st)
     return h
@@ -214,7 +215,7 @@ class Solver:
 
     def __init__(self, n, length, omega, w):
         self.n = tuple(int(v) for v in n)
-        self.ncell = self.n[0] * self.n[1]
+        self.ncell = int(np.prod(self.n))
         self.ndir = len(w)
         self.h = lmdg_create(n, length, omega, w)
 

@@ -1,0 +1,165 @@
+"""Parity of the 3D low-memory sweeps (LMDG, RLMDG) with the CPU oracle, through the C ABI.
+
+Bars as in the 2D parity tests: 1e-12 relative (max-norm) for FP64 sweeps, operator
+applications and right-hand sides; 2e-5 for FP32 sweeps; solves against the
+oracle's direct solve at 1e-9 with GMRES tolerance 1e-12.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import rel_err
+from oracle import schemes as S
+from oracle.dg import Mesh
+from oracle.quadrature import level_symmetric
+from paper_1907_01027_amd.workloads import materials
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1907_01027_amd import lmdg  # noqa: E402
+
+DEV = torch.device("cuda")
+# ragged strips (ny not a multiple of 16), single planes, two strips, S4 and S8
+SHAPES = [((5, 4, 3), 4), ((9, 20, 3), 4), ((7, 3, 1), 4), ((1, 1, 6), 4), ((6, 5, 4), 8), ((3, 17, 5), 8)]
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def N(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+class Case3:
+    def __init__(self, n, order, eps, seed=5):
+        self.n = tuple(n)
+        self.ncell = int(np.prod(n))
+        self.omega, self.w = level_symmetric(order, 3)
+        ss, sa, ep, q = materials(2, n=self.n, seed=seed)
+        self.sigma_s, self.sigma_a, self.eps, self.q = ss, sa, np.full_like(ep, eps), q[0]
+        self.prob = S.Problem(Mesh(self.n, (1.0, 1.0, 1.0)), self.omega, self.w, self.sigma_s, self.sigma_a,
+                              self.eps, q=self.q)
+
+    def solver(self):
+        s = lmdg.Solver(self.n, (1.0, 1.0, 1.0), self.omega, self.w)
+        lmdg.lmdg_set_materials(s.h, T(self.sigma_s), T(self.sigma_a), T(self.eps), T(self.q))
+        torch.cuda.synchronize()
+        return s
+
+
+def lm_to_abi(x, nc):
+    x1 = x[nc:].reshape(nc, 7)
+    return np.concatenate([x[:nc]] + [x1[:, k] for k in range(7)])
+
+
+def abi_to_lm(v, nc):
+    v = v.reshape(8, nc)
+    return np.concatenate([v[0], v[1:].T.ravel()])
+
+
+def oracle_sweep(case, scheme, x_abi, use_q):
+    nc = case.ncell
+    red = S.LowMemoryReduced(case.prob, scheme == "rlmdg")
+    x = abi_to_lm(x_abi, nc)
+    rhs = red.M0 @ x[:nc] + red.L01 @ (red.St @ x[nc:])
+    if use_q:
+        rhs = rhs + red.Qt0
+    psi = red.Lt00_lu.solve(rhs)
+    g = red.S @ (red.L10 @ psi)
+    if scheme == "rlmdg":
+        g = g + red.S @ (red.L11 @ (red.R @ psi))
+    g = g.reshape(nc, 7)
+    rows = [red.P0 @ psi] + [g[:, k] for k in range(7)]
+    if scheme == "rlmdg":
+        pr = (red.P1 @ (red.R @ psi)).reshape(nc, 7)
+        rows += [pr[:, 0], pr[:, 1], pr[:, 3]]  # xi, eta, zeta slopes (moments 1, 2, 4)
+    return np.concatenate(rows), psi
+
+
+@pytest.mark.parametrize("shape,order", SHAPES)
+@pytest.mark.parametrize("scheme", ["lmdg", "rlmdg"])
+def test_sweep3d_parity_fp64(shape, order, scheme):
+    print(f"case 3d sweep {scheme} {shape} S{order}", flush=True)
+    case = Case3(shape, order, eps=0.05)
+    s = case.solver()
+    nc = case.ncell
+    nout = 11 if scheme == "rlmdg" else 8
+    x = np.random.default_rng(1).normal(size=8 * nc)
+    for use_q in (False, True):
+        out = torch.zeros(nout * nc, dtype=torch.float64, device=DEV)
+        psi = torch.zeros(case.prob.n_dir * nc, dtype=torch.float64, device=DEV)
+        lmdg.lmdg_sweep(s.h, scheme, "fp64", T(x), use_q, out, psi)
+        ref, ref_psi = oracle_sweep(case, scheme, x, use_q)
+        assert rel_err(N(out), ref) < 1e-12
+        assert rel_err(N(psi), ref_psi) < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("shape,order", SHAPES)
+@pytest.mark.parametrize("scheme", ["lmdg", "rlmdg"])
+def test_apply_and_rhs_3d(shape, order, scheme):
+    print(f"case 3d apply {scheme} {shape} S{order}", flush=True)
+    case = Case3(shape, order, eps=0.02)
+    s = case.solver()
+    nc = case.ncell
+    x = np.random.default_rng(2).normal(size=8 * nc)
+    red = S.LowMemoryReduced(case.prob, scheme == "rlmdg")
+    ref_y = lm_to_abi(red.apply(abi_to_lm(x, nc)), nc)
+    ref_b = lm_to_abi(red.rhs(), nc)
+    y = torch.zeros(8 * nc, dtype=torch.float64, device=DEV)
+    b = torch.zeros_like(y)
+    lmdg.lmdg_apply(s.h, scheme, "fp64", T(x), y)
+    lmdg.lmdg_rhs(s.h, scheme, "fp64", b)
+    assert rel_err(N(y), ref_y) < 1e-12
+    assert rel_err(N(b), ref_b) < 1e-12
+    lmdg.lmdg_apply(s.h, scheme, "fp32", T(x), y)
+    assert rel_err(N(y), ref_y) < 2e-5
+    s.close()
+
+
+@pytest.mark.parametrize("scheme", ["lmdg", "rlmdg"])
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_solve_3d_against_direct(scheme, mode):
+    print(f"case 3d solve {scheme} {mode}", flush=True)
+    case = Case3((6, 7, 5), 4, eps=0.1)
+    s = case.solver()
+    nc = case.ncell
+    x = torch.zeros(8 * nc, dtype=torch.float64, device=DEV)
+    phi = torch.zeros_like(x)
+    info = lmdg.lmdg_solve(s.h, scheme, mode, 1e-12, 40, 4000, x, phi)
+    assert info["converged"] == 1
+    fn = S.solve_rlmdg_direct if scheme == "rlmdg" else S.solve_lmdg_direct
+    ref = S.scalar_flux_lm(case.prob, *fn(case.prob))          # (nc, 8) cell-major
+    assert rel_err(N(phi).reshape(8, nc).T, ref) < 1e-9
+    s.close()
+
+
+def test_multi_source_3d_equals_single():
+    case = Case3((5, 18, 4), 4, eps=0.2)
+    nc = case.ncell
+    q = np.random.default_rng(4).uniform(0, 1, size=(3, nc))
+    s = case.solver()
+    x = T(np.random.default_rng(6).normal(size=(3, 8 * nc)))
+    singles = []
+    for k in range(3):
+        lmdg.lmdg_set_materials(s.h, T(case.sigma_s), T(case.sigma_a), T(case.eps), T(q[k]))
+        b = torch.zeros(8 * nc, dtype=torch.float64, device=DEV)
+        y = torch.zeros_like(b)
+        lmdg.lmdg_rhs(s.h, "rlmdg", "fp32", b)
+        lmdg.lmdg_apply(s.h, "rlmdg", "fp32", x[k].contiguous(), y)
+        singles.append((b, y))
+    lmdg.lmdg_set_sources(s.h, T(q))
+    b = torch.zeros(3 * 8 * nc, dtype=torch.float64, device=DEV)
+    y = torch.zeros_like(b)
+    lmdg.lmdg_rhs(s.h, "rlmdg", "fp32", b)
+    lmdg.lmdg_apply(s.h, "rlmdg", "fp32", x.reshape(-1), y)
+    torch.cuda.synchronize()
+    for k in range(3):
+        assert torch.equal(b[k * 8 * nc:(k + 1) * 8 * nc], singles[k][0])
+        assert torch.equal(y[k * 8 * nc:(k + 1) * 8 * nc], singles[k][1])
+    s.close()

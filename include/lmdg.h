@@ -5,8 +5,8 @@
  *     Omega . grad Psi + (sigma_s/eps + eps sigma_a) Psi = (sigma_s/eps) Psibar + eps q
  * (Sun & Hauck, "Low-memory, discrete ordinates, discontinuous Galerkin methods for
  * radiative transport", Sec. 1, eq-main) on a uniform Cartesian mesh of
- * [0, length_0] x [0, length_1] with bilinear (Q^1) upwind DG in space and a discrete
- * ordinates set in angle (Sec. 2.1), for three spaces:
+ * [0, length_0] x [0, length_1] (x [0, length_2] in 3D) with multilinear (Q^1) upwind
+ * DG in space and a discrete ordinates set in angle (Sec. 2.1), for three spaces:
  *   LMDG_SCHEME_STD    standard S_N-DG                       (Sec. 2.1, eq-sndg-scheme)
  *   LMDG_SCHEME_LMDG   low-memory space V_{h,0} + D_{h,1}    (Sec. 3.2, eq-gene-scheme)
  *   LMDG_SCHEME_RLMDG  low-memory space with upwind slope reconstruction
@@ -19,13 +19,14 @@
  * - Every function returns an int status (LMDG_OK on success).  No C++ exception and
  *   no abort crosses this boundary.  lmdg_status_string() names a status; the handle
  *   keeps a longer message for the last failure (lmdg_last_error()).
- * - Cells are numbered x fastest: p = i + n_0 * j (2D).
+ * - Cells are numbered x fastest: p = i + n_0 * j (2D), p = i + n_0 * (j + n_1 * k) (3D).
  * - A "moment vector" holds Legendre moments of a Q^1 field on every cell, moment
- *   major: v[r * n_cells + p], r = 0..n_P-1 with the basis 1, xi, eta, xi*eta
- *   (xi = 2(x - x_c)/h_0, eta = 2(y - y_c)/h_1), n_P = 4 in 2D.  Krylov vectors,
- *   right-hand sides and scalar fluxes all use this layout (n_P * n_cells doubles).
- *   For LMDG/RLMDG moment 0 is X_0 (per-cell scalar-flux average) and moments 1..3
- *   are X_1 of Sec. 3.2 Step 3.
+ *   major: v[r * n_cells + p], r = 0..n_P-1.  2D: n_P = 4, basis 1, xi, eta, xi*eta
+ *   (xi = 2(x - x_c)/h_0, eta = 2(y - y_c)/h_1).  3D: n_P = 8, basis index
+ *   r = bx + 2 by + 4 bz for xi^bx eta^by zeta^bz (1, xi, eta, xi eta, zeta, xi zeta,
+ *   eta zeta, xi eta zeta).  Krylov vectors, right-hand sides and scalar fluxes all
+ *   use this layout (n_P * n_cells doubles).  For LMDG/RLMDG moment 0 is X_0
+ *   (per-cell scalar-flux average) and moments 1..n_P-1 are X_1 of Sec. 3.2 Step 3.
  * - Right-hand sides: a handle carries n_rhs sources (1 after lmdg_set_materials,
  *   n after lmdg_set_sources).  Every vector argument of lmdg_sweep, lmdg_apply,
  *   lmdg_rhs, lmdg_recover and lmdg_solve then holds the n_rhs fields stacked:
@@ -39,8 +40,9 @@
  *   call is enqueued on it; calls that report iteration counts or residuals
  *   synchronise it before returning.
  * - A handle is not re-entrant: calls on one handle must not overlap.
- * - Supported: dim = 2, vacuum inflow (alpha = 0), per-cell constant cross
- *   sections, eps and sources.  Anything else returns LMDG_UNSUPPORTED.
+ * - Supported: dim = 2 (STD, LMDG, RLMDG) and dim = 3 (LMDG, RLMDG), vacuum inflow
+ *   (alpha = 0), per-cell constant cross sections, eps and sources.  Anything else
+ *   returns LMDG_UNSUPPORTED.
  */
 #ifndef LMDG_H
 #define LMDG_H
@@ -108,13 +110,14 @@ int lmdg_quadrature_level_symmetric(int dim, int order, int capacity, int* n_dir
                                     double* omega, double* w);
 
 /*
- * Create a handle on the current HIP device for a uniform mesh of n[0] x n[1] cells
- * of [0, length[0]] x [0, length[1]] and the quadrature (omega, w) (host arrays,
- * copied).  The quadrature must satisfy eq-polyquad (i)-(iii) to 1e-12, have
- * positive weights and no zero component (the upwind direction along every axis
- * must be defined), and at most 36 directions per quadrant (S16 has 36).
+ * Create a handle on the current HIP device for a uniform mesh of n[0] x ... x
+ * n[dim-1] cells of [0, length[0]] x ... (host arrays of dim entries) and the
+ * quadrature (omega: n_dir x dim, w) (host arrays, copied).  The quadrature must
+ * satisfy eq-polyquad (i)-(iii) to 1e-12, have positive weights and no zero
+ * component (the upwind direction along every axis must be defined), and at most 36
+ * directions per quadrant / octant (2D S16 has 36, 3D S8 has 10).
  * Errors: INVALID_ARG (NULL pointers, sizes < 1, quadrature violations),
- *         UNSUPPORTED (dim != 2), HIP_ERROR (allocation).
+ *         UNSUPPORTED (dim not 2 or 3), HIP_ERROR (allocation).
  */
 int lmdg_create(int dim, const int64_t* n, const double* length, int n_dir,
                 const double* omega, const double* w, lmdg_t** out);
@@ -155,9 +158,13 @@ int lmdg_set_sources(lmdg_t* h, int n_rhs, const double* q, void* stream);
  *   STD:   n_P moments of P Psi
  *   LMDG:  [P_0 Psi ; Sigma L_10 Psi (xi, eta, xi*eta rows)]
  *   RLMDG: [P_0 Psi ; Sigma (L_10 + L_11 R) Psi (3 rows) ; P_1 R Psi (xi, eta)]
+ *   3D (rows of Sigma L_10 and Sigma (L_10 + L_11 R) indexed by slope moment 1..7):
+ *   LMDG:  [P_0 Psi ; Sigma L_10 Psi (7 rows)]                              8 rows
+ *   RLMDG: [P_0 Psi ; Sigma (L_10 + L_11 R) Psi (7 rows) ; P_1 R Psi (xi, eta, zeta)] 11 rows
  *   x        device moment vector or NULL (= 0)
  *   use_q    1 adds the source Q, 0 omits it
- *   out      device, n_out * n_cells doubles (n_out = 4, 4, 6 for STD, LMDG, RLMDG)
+ *   out      device, n_out * n_cells doubles (n_out = 4, 4, 6 for STD, LMDG, RLMDG in
+ *            2D; 8, 11 for LMDG, RLMDG in 3D)
  *   psi      optional device output of the angular flux (cell averages for
  *            LMDG/RLMDG, all n_P moments for STD), layout psi[(l*m + r)*n_cells + p]
  *            with l the caller's direction index, m = 1 (LMDG/RLMDG) or n_P (STD);
@@ -215,7 +222,7 @@ int lmdg_solve(lmdg_t* h, int scheme, int mode, double tol, int restart, int max
  *   info               host; iterations, restarts and passes summed over both solves
  * The handle keeps both angular fluxes (2 n_dir n_cells doubles for LMDG, 8 n_dir
  * n_cells for STD) after the first call.
- * Errors: UNSUPPORTED (RLMDG: its adjoint is Petrov-Galerkin), INVALID_ARG (NULL
+ * Errors: UNSUPPORTED (RLMDG: its adjoint is Petrov-Galerkin; 3D meshes), INVALID_ARG (NULL
  * pointers, bad solver arguments, quadrature without central symmetry, more than
  * one right-hand side on the handle),
  * NOT_CONVERGED (either solve, or the conjugate gradients of B_11 that give the

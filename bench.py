@@ -124,8 +124,9 @@ def _apply_rate(torch, lmdg, h, scheme, prec, x, y, ncell, ndir, n_rhs=1, reps=5
 
 def extra_measurements(torch, lmdg, WORKLOADS, materials):
     """Secondary figures: operator throughput on the other 2D workloads (FP64 and FP32
-    sweeps), eight sources swept together, and FP64 vs mixed solves of the 20x20 S4
-    workload to 1e-8 and 1e-10 (the case that converges without preconditioning)."""
+    sweeps), eight sources swept together, FP64 vs mixed solves of the 20x20 S4
+    workload to 1e-8 and 1e-10, and the 128^3 3D workload with eight sources (operator
+    throughput and solves to 1e-8, FP64 vs mixed)."""
     dev = torch.device("cuda:0")
     T = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     res = {}
@@ -178,6 +179,32 @@ def extra_measurements(torch, lmdg, WORKLOADS, materials):
                                                          "ir_passes": info["ir_passes"],
                                                          "rel_residual": info["rel_residual"]}
     res["20x20_S4_eps1_solves"] = solves
+    s.close()
+    # 128^3, 3D S8 (80 directions), RLMDG, eight sources swept together; solves to 1e-8
+    wl = WORKLOADS[5]
+    ss, sa, ep, q = materials(5)
+    om, w = lmdg.lmdg_quadrature_level_symmetric(3, wl.order)
+    s = lmdg.Solver(wl.n, (1.0, 1.0, 1.0), om, w)
+    lmdg.lmdg_set_materials(s.h, T(ss), T(sa), T(ep), T(q[0]))
+    lmdg.lmdg_set_sources(s.h, T(q))
+    nc = int(np.prod(wl.n))
+    nr = q.shape[0]
+    x = T(np.random.default_rng(3).normal(size=nr * 8 * nc))
+    y = torch.empty_like(x)
+    entry = {p: _apply_rate(torch, lmdg, s.h, "rlmdg", p, x, y, nc, len(w), n_rhs=nr, reps=3) for p in ("fp64", "fp32")}
+    del x, y
+    for mode in ("fp64", "mixed"):
+        xs = torch.zeros(nr * 8 * nc, dtype=torch.float64, device=dev)
+        phi = torch.zeros_like(xs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = lmdg.lmdg_solve(s.h, "rlmdg", mode, 1e-8, 30, 1000, xs, phi, raise_on_nonconvergence=False)
+        torch.cuda.synchronize()
+        entry[f"solve_{mode}_tol1e-8"] = {"wall_s": time.perf_counter() - t0, "iterations": info["iterations"],
+                                          "ir_passes": info["ir_passes"], "converged": info["converged"],
+                                          "rel_residual": info["rel_residual"]}
+        del xs, phi
+    res["128^3_S8_rlmdg_8_sources"] = entry
     s.close()
     return res
 

@@ -353,7 +353,8 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
   constexpr int NS = SrcTraits<S>::NS;
   constexpr int NC = SrcTraits<S>::NC;
   constexpr int NRAW = SrcTraits<S>::NRAW;
-  constexpr int MAXC = SrcTraits<S>::MAXC;
+  // staged cells per thread: the 9-wave variant has threads for a whole chunk
+  constexpr int MAXC = MAXW > 4 ? 1 : SrcTraits<S>::MAXC;
   constexpr bool LM = S != LMDG_SCHEME_STD;
   extern __shared__ unsigned char smem_raw[];
   __shared__ int s_item;
@@ -641,7 +642,8 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   // (one workgroup per compute unit; gfx950 gives a workgroup up to 160 KB)
   constexpr size_t kLdsBudget = 144 * 1024;
   int cw = 16;
-  while (cw > kStepGroup && (kRows * cw > SrcTraits<S>::MAXC * 64 * W || lds_bytes<R, S>(cw, W, h->dslots) > kLdsBudget))
+  const int maxc = W > 4 ? 1 : SrcTraits<S>::MAXC;
+  while (cw > kStepGroup && (kRows * cw > maxc * 64 * W || lds_bytes<R, S>(cw, W, h->dslots) > kLdsBudget))
     cw >>= 1;
   P.cw = cw;
   P.lcw = 0;

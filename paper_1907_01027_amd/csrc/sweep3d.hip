@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
   constexpr int NOUT = Traits3<S>::NOUT;
   constexpr int NF = Traits3<S>::NF;
   constexpr int NC = kNC3;
-  constexpr int MAXC = kMAXC3;
+  constexpr int MAXC = MAXW > 4 ? 1 : kMAXC3;
   constexpr bool RLM = S == LMDG_SCHEME_RLMDG;
   extern __shared__ unsigned char smem_raw[];
   __shared__ int s_item;
@@ -453,7 +453,8 @@ int launch3_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipS
   const int W = h->waves;
   constexpr size_t kLdsBudget = 144 * 1024;
   int cw = 16;
-  while (cw > kStepGroup3 && (kRows * cw > kMAXC3 * 64 * W || lds_bytes3<R, S>(cw, W, h->dslots) > kLdsBudget))
+  const int maxc = W > 4 ? 1 : kMAXC3;
+  while (cw > kStepGroup3 && (kRows * cw > maxc * 64 * W || lds_bytes3<R, S>(cw, W, h->dslots) > kLdsBudget))
     cw >>= 1;
   if (lds_bytes3<R, S>(cw, W, h->dslots) > kLdsBudget)
     return set_error(h, LMDG_UNSUPPORTED, "direction set too large for the 3D sweep's LDS staging");

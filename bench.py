@@ -38,7 +38,43 @@ def parse():
                     help="skip the secondary measurements (other workloads, several sources, small solves)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 64 MiB five times (HBM counter calibration)")
+    ap.add_argument("--profile-workload", type=int, default=0,
+                    help="only time K x on workload 3, 4 or 5 (all its sources) for a profiler run")
+    ap.add_argument("--prec", default="fp64", choices=("fp64", "fp32"))
     return ap.parse_args()
+
+
+def profile_workload(key, prec, steps, warmup):
+    """Warm-up and timed operator applications of one workload (for rocprofv3 runs)."""
+    import torch
+    from paper_1907_01027_amd import lmdg
+    from paper_1907_01027_amd.workloads import WORKLOADS, materials
+    wl = WORKLOADS[key]
+    ss, sa, ep, q = materials(key)
+    dim = len(wl.n)
+    om, w = lmdg.lmdg_quadrature_level_symmetric(dim, wl.order)
+    T = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+    s = lmdg.Solver(wl.n, (1.0,) * dim, om, w)
+    lmdg.lmdg_set_materials(s.h, T(ss), T(sa), T(ep), T(q[0]))
+    if q.shape[0] > 1:
+        lmdg.lmdg_set_sources(s.h, T(q))
+    nc = int(np.prod(wl.n))
+    npm = 4 if dim == 2 else 8
+    x = T(np.random.default_rng(5).normal(size=q.shape[0] * npm * nc))
+    y = torch.empty_like(x)
+    for _ in range(warmup):
+        lmdg.lmdg_apply(s.h, wl.scheme, prec, x, y)
+    torch.cuda.synchronize()
+    lmdg.lmdg_profile(s.h, True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        lmdg.lmdg_apply(s.h, wl.scheme, prec, x, y)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    ms, k = lmdg.lmdg_sweep_kernel_time(s.h)
+    s.close()
+    print(json.dumps({"workload": wl.name, "prec": prec, "ms_per_apply": 1e3 * el, "sweep_kernel_ms": ms / max(k, 1),
+                      "updates_per_s": nc * len(w) * q.shape[0] / el}), flush=True)
 
 
 def sweep_bytes_per_launch(ncell, scheme):
@@ -217,6 +253,9 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.profile_workload:
+        profile_workload(args.profile_workload, args.prec, args.steps, args.warmup)
         return
     import torch
     from paper_1907_01027_amd import lmdg

@@ -220,8 +220,11 @@ int lmdg_solve(lmdg_t* h, int scheme, int mode, double tol, int restart, int max
  *   g_sigma_s, g_sigma_a, g_q   device outputs, n_cells doubles each
  *   J_out              host output
  *   info               host; iterations, restarts and passes summed over both solves
- * The handle keeps both angular fluxes (2 n_dir n_cells doubles for LMDG, 8 n_dir
- * n_cells for STD) after the first call.
+ * The angular fluxes are never stored for all directions: the gradient sum is built
+ * one quadrant at a time, recomputing that quadrant's forward fluxes and the opposite
+ * quadrant's adjoint-type fluxes with two restricted sweeps (the handle keeps
+ * 2 x slots x n_cells doubles for LMDG, 8 x slots x n_cells for STD, slots = the
+ * padded directions per quadrant).
  * Errors: UNSUPPORTED (RLMDG: its adjoint is Petrov-Galerkin; 3D meshes), INVALID_ARG (NULL
  * pointers, bad solver arguments, quadrature without central symmetry, more than
  * one right-hand side on the handle),

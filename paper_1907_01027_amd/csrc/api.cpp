@@ -370,17 +370,27 @@ int lmdg_create(int dim, const int64_t* n, const double* length, int n_dir, cons
   int st = check_hip(h, hipMalloc((void**)&h->d_dirs, tab.size() * sizeof(double)), "hipMalloc");
   if (st == LMDG_OK) st = check_hip(h, hipMalloc((void**)&h->ws.ticket, sizeof(unsigned int)), "hipMalloc");
   if (st == LMDG_OK) st = check_hip(h, hipMalloc((void**)&h->ws.err, sizeof(int)), "hipMalloc");
-  if (st == LMDG_OK) st = check_hip(h, hipMalloc((void**)&h->d_adjtab, (size_t)2 * n_dir * sizeof(double)), "hipMalloc");
+  const size_t npairs = (size_t)h->noct * h->dslots * 2;
+  if (st == LMDG_OK) st = check_hip(h, hipMalloc((void**)&h->d_adjpairs, npairs * sizeof(double)), "hipMalloc");
   if (st == LMDG_OK) st = ensure_rhs_capacity(h, 1);
-  std::vector<double> adjtab(2 * n_dir);
-  for (int l = 0; l < n_dir; ++l) {
-    adjtab[2 * l] = w[l];
-    adjtab[2 * l + 1] = h->neg_dir[l] >= 0 ? h->neg_dir[l] : l;
-  }
+  // per quadrant and slot: weight and the slot of -Omega in the opposite quadrant
+  std::vector<double> pairs(npairs, 0.0);
+  const int qmask_all = h->noct - 1;
+  for (int q = 0; q < h->noct; ++q)
+    for (int k = 0; k < h->dslots; ++k) {
+      const int l = h->slot_dir[(size_t)q * h->dslots + k];
+      if (l < 0 || h->neg_dir[l] < 0) continue;
+      const int qo = q ^ qmask_all;
+      for (int k2 = 0; k2 < h->dslots; ++k2)
+        if (h->slot_dir[(size_t)qo * h->dslots + k2] == h->neg_dir[l]) {
+          pairs[((size_t)q * h->dslots + k) * 2] = w[l];
+          pairs[((size_t)q * h->dslots + k) * 2 + 1] = k2;
+        }
+    }
   if (st == LMDG_OK) st = check_hip(h, hipMemcpy(h->d_dirs, tab.data(), tab.size() * sizeof(double),
                                                  hipMemcpyHostToDevice), "copy directions");
-  if (st == LMDG_OK) st = check_hip(h, hipMemcpy(h->d_adjtab, adjtab.data(), adjtab.size() * sizeof(double),
-                                                 hipMemcpyHostToDevice), "copy direction map");
+  if (st == LMDG_OK) st = check_hip(h, hipMemcpy(h->d_adjpairs, pairs.data(), pairs.size() * sizeof(double),
+                                                 hipMemcpyHostToDevice), "copy direction pairs");
   if (st == LMDG_OK) st = check_hip(h, hipMemset(h->ws.ticket, 0, sizeof(unsigned int)), "clear ticket");
   if (st == LMDG_OK) st = check_hip(h, hipMemset(h->ws.err, 0, sizeof(int)), "clear error flag");
   if (st == LMDG_OK) st = check_hip(h, hipDeviceSynchronize(), "create");
@@ -397,7 +407,7 @@ void lmdg_destroy(lmdg_t* h) {
   hipDeviceSynchronize();
   void* ptrs[] = {h->d_dirs, h->d_sigtA, h->d_scatA, h->d_absA, h->d_qA, h->ws.part, h->ws.edge, h->ws.zbuf,
                   h->ws.prog, h->ws.ticket, h->ws.err, h->ws.vec, h->d_krylov, h->d_small,
-                  h->d_epsA, h->d_adjtab, h->d_psi_f, h->d_psi_a, h->d_cvec};
+                  h->d_epsA, h->d_adjpairs, h->d_psi_f, h->d_psi_a, h->d_cvec};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (h->h_small) hipHostFree(h->h_small);
@@ -958,7 +968,8 @@ int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, doubl
   hipStream_t st = (hipStream_t)stream;
   const long long nc = h->ncell, N = (long long)h->np * nc;
   const int npsi = scheme == LMDG_SCHEME_STD ? 4 : 1;
-  const size_t psi_doubles = (size_t)h->ndir * npsi * nc;
+  // angular fluxes of one quadrant at a time (forward and opposite-quadrant adjoint)
+  const size_t psi_doubles = (size_t)h->dslots * npsi * nc;
   if (h->psi_doubles < psi_doubles) {
     if (h->d_psi_f) hipFree(h->d_psi_f);
     if (h->d_psi_a) hipFree(h->d_psi_a);
@@ -970,22 +981,25 @@ int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, doubl
     h->psi_doubles = psi_doubles;
   }
   if (!h->d_cvec) {
-    rc = check_hip(h, hipMalloc((void**)&h->d_cvec, (size_t)4 * N * sizeof(double)), "hipMalloc adjoint vectors");
+    rc = check_hip(h, hipMalloc((void**)&h->d_cvec, (size_t)6 * N * sizeof(double)), "hipMalloc adjoint vectors");
     if (rc != LMDG_OK) return rc;
   }
   double* c = h->d_cvec;
-  double* x = h->d_cvec + N;
+  double* xf = h->d_cvec + N;
   double* phi = h->d_cvec + 2 * N;
   double* Lam = h->d_cvec + 3 * N;
+  double* xa = h->d_cvec + 4 * N;
+  double* bil = h->d_cvec + 5 * N;  // n_cells used
   const auto t_start = std::chrono::steady_clock::now();
-  // forward solve, keeping every direction's angular flux
+  // forward solve
   lmdg_info inf_f{}, inf_a{};
-  rc = solve_impl(h, scheme, mode, tol, restart, max_iter, nullptr, x, phi, h->d_psi_f, &inf_f, st, nullptr, nullptr);
+  rc = solve_impl(h, scheme, mode, tol, restart, max_iter, nullptr, xf, phi, nullptr, &inf_f, st, nullptr, nullptr);
   double J = 0.0;
   if (rc == LMDG_OK) rc = dot(h, det, phi, N, &J, st);
   // adjoint: on a centrally symmetric quadrature L_l^T is the upwind operator of
   // -Omega_l, so A^T lambda = j is the forward system with source moments d and the
   // direction blocks exchanged l <-> -l; the same sweeps solve it
+  const double* xa_rec = xa;  // the adjoint solution as the recovery sweep takes it
   if (rc == LMDG_OK) {
     h->src0 = det;
     h->src1 = scheme == LMDG_SCHEME_STD ? det + nc : nullptr;
@@ -1002,16 +1016,37 @@ int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, doubl
       }
     }
     if (rc == LMDG_OK)
-      rc = solve_impl(h, scheme, mode, tol, restart, max_iter, nullptr, x, Lam, h->d_psi_a, &inf_a, st, rhs_x,
-                      cshift);
+      rc = solve_impl(h, scheme, mode, tol, restart, max_iter, nullptr, xa, Lam, nullptr, &inf_a, st, rhs_x, cshift);
+    if (rc == LMDG_OK && cshift) {
+      double* t = h->ws.vec + 3 * N;  // x - c, the vector the recovery sweep takes
+      lmdg::vec_copy(t, xa, N, st);
+      lmdg::vec_axpby(t, -1.0, cshift, 1.0, N, st);
+      xa_rec = t;
+    }
     h->src0 = nullptr;
     h->src1 = nullptr;
   }
+  // gradients: per quadrant, recompute the forward fluxes of its directions and the
+  // adjoint-type fluxes of the opposite quadrant, and accumulate the angular sum
   if (rc == LMDG_OK) {
-    lmdg::launch_gradients(h, npsi, phi, Lam, g_sigma_s, g_sigma_a, g_q, st);
+    lmdg::vec_fill(bil, 0.0, nc, st);
+    for (int q = 0; q < 4 && rc == LMDG_OK; ++q) {
+      rc = lmdg::launch_sweep(h, scheme, LMDG_PREC_FP64, xf, true, h->d_psi_f, st, false, 1 << q, true);
+      if (rc != LMDG_OK) break;
+      h->src0 = det;
+      h->src1 = scheme == LMDG_SCHEME_STD ? det + nc : nullptr;
+      rc = lmdg::launch_sweep(h, scheme, LMDG_PREC_FP64, xa_rec, true, h->d_psi_a, st, false, 1 << (q ^ 3), true);
+      h->src0 = nullptr;
+      h->src1 = nullptr;
+      if (rc == LMDG_OK) lmdg::launch_grad_accumulate(h, q, npsi, bil, st);
+    }
+  }
+  if (rc == LMDG_OK) {
+    lmdg::launch_gradients(h, npsi, bil, phi, Lam, g_sigma_s, g_sigma_a, g_q, st);
     rc = check_hip(h, hipGetLastError(), "gradients");
   }
   if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "adjoint");
+  if (rc == LMDG_OK) rc = read_error_flag(h, st);
   *J_out = J;
   if (info) {
     info->iterations = inf_f.iterations + inf_a.iterations;

@@ -29,6 +29,9 @@ template <typename R>
 struct SweepParams {
   int nx, ny, nstrips, cw, lcw, nchunks, dslots, n_items;  // cw = 1 << lcw steps per chunk
   int n_rhs;             // right-hand sides swept together (vectors stacked rhs-major)
+  int nq;                // quadrants swept (item index runs over these only)
+  int qsel[4];           // the swept quadrants
+  int psi_by_slot;       // 1: psi indexed by direction slot (one quadrant), 0: by caller index
   long long psi_rstride, edge_rstride;
   double hx, hy;
   long long ncell;
@@ -120,13 +123,14 @@ struct lmdg_handle {
   // slope moments (standard scheme); both null outside the adjoint solve
   const double* src0 = nullptr;
   const double* src1 = nullptr;
-  // directions: index of -Omega_l and the weights on the device (adjoint gradients)
+  // directions: index of -Omega_l; per quadrant and slot the weight and the slot of
+  // -Omega_l in the opposite quadrant (adjoint gradients)
   std::vector<int> neg_dir;
-  double* d_adjtab = nullptr;      // [n_dir][2]: w_l, index of -Omega_l
-  double* d_psi_f = nullptr;       // angular fluxes kept by the adjoint solve
+  double* d_adjpairs = nullptr;    // [4][dslots][2]
+  double* d_psi_f = nullptr;       // one quadrant's angular fluxes (adjoint gradients)
   double* d_psi_a = nullptr;
   size_t psi_doubles = 0;
-  double* d_cvec = nullptr;        // B_11^{-1} of the source slopes (4 * ncell, slot 0 zero)
+  double* d_cvec = nullptr;        // adjoint vectors: c, x (forward), phi, Lambda, x (adjoint), bilinear sums
   lmdg::Workspace ws;
   unsigned long long epoch = 1;
   unsigned int ticket_base = 0;
@@ -151,7 +155,8 @@ constexpr int kScratchVecs = 4;
 
 // launchers (sweep2d.hip / ops.hip)
 int launch_sweep(lmdg_handle* h, int scheme, int prec, const double* x, bool use_q,
-                 double* psi, hipStream_t st, bool defect = false);
+                 double* psi, hipStream_t st, bool defect = false, int qmask = 0xF,
+                 bool psi_by_slot = false);
 int launch_sweep3d(lmdg_handle* h, int scheme, int prec, const double* x, bool use_q, double* psi,
                    hipStream_t st, bool defect);
 void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double* x,
@@ -163,8 +168,9 @@ void launch_sum_octants(lmdg_handle* h, int scheme, int prec, double* out, hipSt
 void launch_b11_3d(lmdg_handle* h, const double* x, double* y, hipStream_t st);
 void launch_check_error(lmdg_handle* h, hipStream_t st);
 void launch_b11(lmdg_handle* h, const double* x, double* y, hipStream_t st);
-void launch_gradients(lmdg_handle* h, int npsi, const double* phi, const double* Lam, double* gs, double* ga,
-                      double* gq, hipStream_t st);
+void launch_grad_accumulate(lmdg_handle* h, int quadrant, int npsi, double* bil, hipStream_t st);
+void launch_gradients(lmdg_handle* h, int npsi, const double* bil, const double* phi, const double* Lam, double* gs,
+                      double* ga, double* gq, hipStream_t st);
 
 // kApplyDefect: K x from a sweep run with the defect source (same operator).
 enum CombineMode { kApply = 0, kRhs = 1, kRecover = 2, kApplyDefect = 3 };

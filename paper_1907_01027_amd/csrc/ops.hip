@@ -249,27 +249,39 @@ __global__ void b11_apply_kernel(int nx, int ny, double hx, double hy, double cx
 //   dJ/dsigma_s = -(1/eps) (sum_l w_l int_K psi_l lambda_l - int_K phi Lambda)
 //   dJ/dq       =  eps int_K Lambda
 // with phi, Lambda the scalar fluxes.  The adjoint field of direction l is the
-// forward-type solution of direction -Omega_l (tab: w_l, index of -Omega_l).
-// npsi = 4 (standard: all moments per direction) or 1 (low-memory: Psi_0 per
-// direction; the slope part is the isotropic Phi_1 of phi / Lambda).  Legendre mass
-// on K is |K| diag(1, 1/3, 1/3, 1/9).
-__global__ void gradient_kernel(long long nc, int ndir, int npsi, const double* __restrict__ tab,
-                                const double* __restrict__ psi, const double* __restrict__ lam,
-                                const double* __restrict__ phi, const double* __restrict__ Lam,
-                                const double* __restrict__ epsA, double area, double* __restrict__ gs,
-                                double* __restrict__ ga, double* __restrict__ gq) {
+// forward-type solution of direction -Omega_l.  The direction sum is accumulated one
+// quadrant at a time from that quadrant's forward fluxes and the opposite quadrant's
+// adjoint-type fluxes, both indexed by direction slot (pairs: w_l and the slot of
+// -Omega_l); npsi = 4 (standard: all moments per direction) or 1 (low-memory: Psi_0
+// per direction, the slope part being the isotropic Phi_1 of phi / Lambda).  Legendre
+// mass on K is |K| diag(1, 1/3, 1/3, 1/9).
+__global__ void grad_accum_kernel(long long nc, int dslots, int npsi, const double* __restrict__ pairs,
+                                  const double* __restrict__ psi, const double* __restrict__ lam,
+                                  double* __restrict__ bil) {
   const double mass[4] = {1.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 9.0};
   for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nc;
        p += (long long)gridDim.x * blockDim.x) {
-    double bil = 0.0;
-    for (int l = 0; l < ndir; ++l) {
-      const double w = tab[2 * l];
-      const long long ln = (long long)tab[2 * l + 1];
-      double acc = 0.0;
+    double acc = 0.0;
+    for (int k = 0; k < dslots; ++k) {
+      const double w = pairs[2 * k];
+      const long long kn = (long long)pairs[2 * k + 1];
+      double a = 0.0;
       for (int m = 0; m < npsi; ++m)
-        acc += mass[m] * psi[((long long)l * npsi + m) * nc + p] * lam[(ln * npsi + m) * nc + p];
-      bil += w * acc;
+        a += mass[m] * psi[((long long)k * npsi + m) * nc + p] * lam[(kn * npsi + m) * nc + p];
+      acc += w * a;
     }
+    bil[p] += acc;
+  }
+}
+
+__global__ void grad_final_kernel(long long nc, int npsi, const double* __restrict__ bil_in,
+                                  const double* __restrict__ phi, const double* __restrict__ Lam,
+                                  const double* __restrict__ epsA, double area, double* __restrict__ gs,
+                                  double* __restrict__ ga, double* __restrict__ gq) {
+  const double mass[4] = {1.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 9.0};
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nc;
+       p += (long long)gridDim.x * blockDim.x) {
+    double bil = bil_in[p];
     double bar = 0.0, slopes = 0.0;
     for (int m = 0; m < 4; ++m) {
       const double t = mass[m] * phi[m * nc + p] * Lam[m * nc + p];
@@ -427,11 +439,17 @@ void launch_b11(lmdg_handle* h, const double* x, double* y, hipStream_t st) {
                      h->cplus[0], h->cminus[0], h->cplus[1], h->cminus[1], x, h->d_absA, y);
 }
 
-void launch_gradients(lmdg_handle* h, int npsi, const double* phi, const double* Lam, double* gs, double* ga,
-                      double* gq, hipStream_t st) {
+void launch_grad_accumulate(lmdg_handle* h, int quadrant, int npsi, double* bil, hipStream_t st) {
   const int g = std::min(grid_for(h->ncell), 4096);
-  hipLaunchKernelGGL(gradient_kernel, dim3(g), dim3(kBlock), 0, st, h->ncell, h->ndir, npsi, h->d_adjtab,
-                     h->d_psi_f, h->d_psi_a, phi, Lam, h->d_epsA, h->area, gs, ga, gq);
+  hipLaunchKernelGGL(grad_accum_kernel, dim3(g), dim3(kBlock), 0, st, h->ncell, h->dslots, npsi,
+                     h->d_adjpairs + (size_t)quadrant * h->dslots * 2, h->d_psi_f, h->d_psi_a, bil);
+}
+
+void launch_gradients(lmdg_handle* h, int npsi, const double* bil, const double* phi, const double* Lam, double* gs,
+                      double* ga, double* gq, hipStream_t st) {
+  const int g = std::min(grid_for(h->ncell), 4096);
+  hipLaunchKernelGGL(grad_final_kernel, dim3(g), dim3(kBlock), 0, st, h->ncell, npsi, bil, phi, Lam, h->d_epsA,
+                     h->area, gs, ga, gq);
 }
 
 void vec_dots(const double* V, long long ld, int nvec, const double* w, long long n, double* partial,

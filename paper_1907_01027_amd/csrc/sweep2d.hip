@@ -382,11 +382,11 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
     __syncthreads();
     const int item = s_item;
     if (item >= P.n_items) break;
-    // item = (strip * n_rhs + rhs) * 4 + quadrant: every item comes after the one
-    // it waits for (same quadrant and right-hand side, strip below)
-    const int q = item & 3;
-    const int s = (item >> 2) / P.n_rhs;
-    const int rh = (item >> 2) - s * P.n_rhs;
+    // item = (strip * n_rhs + rhs) * nq + selected quadrant: every item comes after the
+    // one it waits for (same quadrant and right-hand side, strip below)
+    const int q = P.qsel[item % P.nq];
+    const int s = (item / P.nq) / P.n_rhs;
+    const int rh = (item / P.nq) - s * P.n_rhs;
     const double* xr = P.x ? P.x + (long long)rh * 4 * nc : nullptr;
     const double* qAr = P.qA ? P.qA + (long long)rh * nc : nullptr;
     R* const partr = P.part + (long long)rh * 4 * NOUT * nc;
@@ -576,6 +576,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
           }
         }
         if (psir && d.idx >= 0) {
+          const int pdir = P.psi_by_slot ? slot : d.idx;
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const int c = t0 + tg + u - r;
@@ -583,10 +584,10 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
               const int i = sxi > 0 ? c : nx - 1 - c;
               const long long cell = (long long)j * nx + i;
               if constexpr (LM) {
-                psir[(long long)d.idx * nc + cell] = (double)psi_g[u][0];
+                psir[(long long)pdir * nc + cell] = (double)psi_g[u][0];
               } else {
 #pragma unroll
-                for (int m = 0; m < 4; ++m) psir[((long long)d.idx * 4 + m) * nc + cell] = (double)psi_g[u][m];
+                for (int m = 0; m < 4; ++m) psir[((long long)pdir * 4 + m) * nc + cell] = (double)psi_g[u][m];
               }
             }
           }
@@ -631,7 +632,8 @@ size_t lds_bytes(int cw, int W, int dslots) {
 }
 
 template <typename R, int S>
-int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipStream_t st, bool defect) {
+int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipStream_t st, bool defect, int qmask,
+                 bool psi_by_slot) {
   SweepParams<R> P;
   P.nx = (int)h->n[0];
   P.ny = (int)h->n[1];
@@ -650,7 +652,12 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   while ((1 << P.lcw) < cw) ++P.lcw;
   P.nchunks = (P.nx + kRows - 1 + cw - 1) / cw;
   P.n_rhs = h->n_rhs;
-  P.n_items = 4 * h->nstrips * h->n_rhs;
+  P.nq = 0;
+  for (int q = 0; q < 4; ++q)
+    if (qmask & (1 << q)) P.qsel[P.nq++] = q;
+  for (int q = P.nq; q < 4; ++q) P.qsel[q] = 0;
+  P.psi_by_slot = psi_by_slot ? 1 : 0;
+  P.n_items = P.nq * h->nstrips * h->n_rhs;
   P.hx = h->h[0];
   P.hy = h->h[1];
   P.ncell = h->ncell;
@@ -700,19 +707,23 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
 }  // namespace
 
 int launch_sweep(lmdg_handle* h, int scheme, int prec, const double* x, bool use_q, double* psi,
-                 hipStream_t st, bool defect) {
-  if (h->dim == 3) return launch_sweep3d(h, scheme, prec, x, use_q, psi, st, defect);
+                 hipStream_t st, bool defect, int qmask, bool psi_by_slot) {
+  if (h->dim == 3) {
+    if (qmask != 0xF || psi_by_slot) return set_error(h, LMDG_UNSUPPORTED, "quadrant-restricted 3D sweep");
+    return launch_sweep3d(h, scheme, prec, x, use_q, psi, st, defect);
+  }
+  if ((qmask & 0xF) == 0) return set_error(h, LMDG_INVALID_ARG, "empty quadrant mask");
   if (prec == LMDG_PREC_FP64) {
     switch (scheme) {
-      case LMDG_SCHEME_STD: return launch_typed<double, LMDG_SCHEME_STD>(h, x, use_q, psi, st, defect);
-      case LMDG_SCHEME_LMDG: return launch_typed<double, LMDG_SCHEME_LMDG>(h, x, use_q, psi, st, defect);
-      default: return launch_typed<double, LMDG_SCHEME_RLMDG>(h, x, use_q, psi, st, defect);
+      case LMDG_SCHEME_STD: return launch_typed<double, LMDG_SCHEME_STD>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
+      case LMDG_SCHEME_LMDG: return launch_typed<double, LMDG_SCHEME_LMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
+      default: return launch_typed<double, LMDG_SCHEME_RLMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
     }
   }
   switch (scheme) {
-    case LMDG_SCHEME_STD: return launch_typed<float, LMDG_SCHEME_STD>(h, x, use_q, psi, st, defect);
-    case LMDG_SCHEME_LMDG: return launch_typed<float, LMDG_SCHEME_LMDG>(h, x, use_q, psi, st, defect);
-    default: return launch_typed<float, LMDG_SCHEME_RLMDG>(h, x, use_q, psi, st, defect);
+    case LMDG_SCHEME_STD: return launch_typed<float, LMDG_SCHEME_STD>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
+    case LMDG_SCHEME_LMDG: return launch_typed<float, LMDG_SCHEME_LMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
+    default: return launch_typed<float, LMDG_SCHEME_RLMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
   }
 }
 

@@ -204,16 +204,20 @@ def extra_measurements(torch, lmdg, WORKLOADS, materials):
     solves = {}
     for scheme in ("std", "lmdg"):
         for tol in (1e-8, 1e-10):
+            phi64 = None
             for mode in ("fp64", "mixed"):
                 lmdg.lmdg_solve(s.h, scheme, mode, tol, 30, 2000, xs, phi)  # warm
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 info = lmdg.lmdg_solve(s.h, scheme, mode, tol, 30, 2000, xs, phi)
                 torch.cuda.synchronize()
-                solves[f"{scheme}_{mode}_tol{tol:g}"] = {"wall_ms": 1e3 * (time.perf_counter() - t0),
-                                                         "iterations": info["iterations"],
-                                                         "ir_passes": info["ir_passes"],
-                                                         "rel_residual": info["rel_residual"]}
+                entry = {"wall_ms": 1e3 * (time.perf_counter() - t0), "iterations": info["iterations"],
+                         "ir_passes": info["ir_passes"], "rel_residual": info["rel_residual"]}
+                if mode == "fp64":
+                    phi64 = phi.clone()
+                else:  # scalar flux of the mixed solve against the FP64 solve at the same tolerance
+                    entry["phi_rel_diff_vs_fp64"] = float((phi - phi64).abs().max() / phi64.abs().max())
+                solves[f"{scheme}_{mode}_tol{tol:g}"] = entry
     res["20x20_S4_eps1_solves"] = solves
     s.close()
     # 128^3, 3D S8 (80 directions), RLMDG, eight sources swept together; solves to 1e-8
@@ -229,6 +233,7 @@ def extra_measurements(torch, lmdg, WORKLOADS, materials):
     y = torch.empty_like(x)
     entry = {p: _apply_rate(torch, lmdg, s.h, "rlmdg", p, x, y, nc, len(w), n_rhs=nr, reps=3) for p in ("fp64", "fp32")}
     del x, y
+    phi64 = None
     for mode in ("fp64", "mixed"):
         xs = torch.zeros(nr * 8 * nc, dtype=torch.float64, device=dev)
         phi = torch.zeros_like(xs)
@@ -236,9 +241,14 @@ def extra_measurements(torch, lmdg, WORKLOADS, materials):
         t0 = time.perf_counter()
         info = lmdg.lmdg_solve(s.h, "rlmdg", mode, 1e-8, 30, 1000, xs, phi, raise_on_nonconvergence=False)
         torch.cuda.synchronize()
-        entry[f"solve_{mode}_tol1e-8"] = {"wall_s": time.perf_counter() - t0, "iterations": info["iterations"],
-                                          "ir_passes": info["ir_passes"], "converged": info["converged"],
-                                          "rel_residual": info["rel_residual"]}
+        e = {"wall_s": time.perf_counter() - t0, "iterations": info["iterations"], "ir_passes": info["ir_passes"],
+             "converged": info["converged"], "rel_residual": info["rel_residual"]}
+        if mode == "fp64":
+            phi64 = phi
+        else:
+            e["phi_rel_diff_vs_fp64"] = float((phi - phi64).abs().max() / phi64.abs().max())
+            del phi64
+        entry[f"solve_{mode}_tol1e-8"] = e
         del xs, phi
     res["128^3_S8_rlmdg_8_sources"] = entry
     s.close()

@@ -166,7 +166,6 @@ void launch_combine3(lmdg_handle* h, int scheme, int prec, int mode, const doubl
                      hipStream_t st);
 void launch_sum_octants(lmdg_handle* h, int scheme, int prec, double* out, hipStream_t st);
 void launch_b11_3d(lmdg_handle* h, const double* x, double* y, hipStream_t st);
-void launch_check_error(lmdg_handle* h, hipStream_t st);
 void launch_b11(lmdg_handle* h, const double* x, double* y, hipStream_t st);
 void launch_grad_accumulate(lmdg_handle* h, int quadrant, int npsi, double* bil, hipStream_t st);
 void launch_gradients(lmdg_handle* h, int npsi, const double* bil, const double* phi, const double* Lam, double* gs,

@@ -715,15 +715,21 @@ int launch_sweep(lmdg_handle* h, int scheme, int prec, const double* x, bool use
   if ((qmask & 0xF) == 0) return set_error(h, LMDG_INVALID_ARG, "empty quadrant mask");
   if (prec == LMDG_PREC_FP64) {
     switch (scheme) {
-      case LMDG_SCHEME_STD: return launch_typed<double, LMDG_SCHEME_STD>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
-      case LMDG_SCHEME_LMDG: return launch_typed<double, LMDG_SCHEME_LMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
-      default: return launch_typed<double, LMDG_SCHEME_RLMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
+      case LMDG_SCHEME_STD:
+        return launch_typed<double, LMDG_SCHEME_STD>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
+      case LMDG_SCHEME_LMDG:
+        return launch_typed<double, LMDG_SCHEME_LMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
+      default:
+        return launch_typed<double, LMDG_SCHEME_RLMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
     }
   }
   switch (scheme) {
-    case LMDG_SCHEME_STD: return launch_typed<float, LMDG_SCHEME_STD>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
-    case LMDG_SCHEME_LMDG: return launch_typed<float, LMDG_SCHEME_LMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
-    default: return launch_typed<float, LMDG_SCHEME_RLMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
+    case LMDG_SCHEME_STD:
+      return launch_typed<float, LMDG_SCHEME_STD>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
+    case LMDG_SCHEME_LMDG:
+      return launch_typed<float, LMDG_SCHEME_LMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
+    default:
+      return launch_typed<float, LMDG_SCHEME_RLMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
   }
 }
 

@@ -202,6 +202,21 @@ int lmdg_solve(lmdg_t* h, int scheme, int mode, double tol, int restart, int max
                void* stream);
 
 /*
+ * Restart augmentation of the handle's GMRES solves (lmdg_solve, lmdg_adjoint_solve
+ * and the inner solves of mode MIXED).  With k > 0 each restart cycle also searches
+ * the corrections of the last k cycles (LGMRES of Baker, Jessup and Manteuffel,
+ * SIAM J. Matrix Anal. Appl. 26, 2005): after the restart Krylov steps the basis is
+ * extended with the stored images K z of those corrections, which costs no operator
+ * application, so the cycle minimises the residual over the Krylov space plus the
+ * span of the old corrections.  This counters the stagnation of restarted GMRES on
+ * the reduced systems of small eps, whose spectra reach close to zero.
+ *   k  0 (plain GMRES, the default) .. 250 - restart; a larger k is clamped in each
+ *      solve to 250 - restart.  Memory: 2 k + 2 further vectors of the solve's length.
+ * Errors: INVALID_ARG (k < 0 or k > 249).
+ */
+int lmdg_set_augment(lmdg_t* h, int k);
+
+/*
  * Detector response and its gradients (Galerkin schemes STD and LMDG).
  * J = int_D phi_h d dx for detector moments det (device moment vector,
  * det[r*n_cells + p] = int_{K_p} d b_r dx; for the indicator of a box, the exact

@@ -598,6 +598,10 @@ bool verbose() {
 struct GmresStats {
   int iterations = 0, restarts = 0;
   double apply_ms = 0;
+  // LGMRES store (pairs z, K z in the Krylov workspace): filled pairs and the next ring
+  // slot.  It persists across the gmres calls that share one GmresStats, so the inner
+  // solves of iterative refinement (same FP32 operator) keep the earlier passes' pairs.
+  int n_aug = 0, aug_next = 0;
 };
 
 // Restarted GMRES(m) with classical Gram-Schmidt applied twice, FP64 vectors, for the
@@ -606,32 +610,55 @@ struct GmresStats {
 // K_prec x = b from x (in/out); stops when every true FP64-operator residual
 // ||b - K x|| <= rtol ||b|| (true_prec) or after max_iter applications.  relres is
 // the largest relative residual over the right-hand sides.
+//
+// With h->augment = k > 0 each cycle also searches the directions of the last k
+// cycles' corrections (LGMRES, Baker, Jessup and Manteuffel 2005): after the m Krylov
+// steps the Arnoldi process continues with the stored images K z of those corrections
+// (no operator application), the search directions being the Krylov vectors and the
+// z's (flexible GMRES form, K Z = V H).  The new correction z = Z y and its image
+// K z = V H y enter the store, so restarts keep what the earlier cycles learned.  The
+// store lives in stats and carries over to the next call with the same stats and
+// operator precision.
 int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, double* x, double rtol, int m,
           int max_iter, hipStream_t st, GmresStats& stats, double& relres, bool& converged) {
   const int nr = h->n_rhs;
   const long long N = (long long)h->np * h->ncell;  // one right-hand side
   const long long NT = N * nr;
+  const int ka_max = std::max(0, std::min(h->augment, kMaxRestart - m));
+  const int mt = m + ka_max;                          // steps per cycle at most
   const SmallLayout L = small_layout(nr);
-  int rc = ensure_krylov(h, (size_t)(m + 2) * NT);
+  // V (mt + 1), r; with augmentation also Z, K Z (ka_max each), the correction and its image
+  const double* prev_krylov = h->d_krylov;
+  int rc = ensure_krylov(h, (size_t)(mt + 2 + (ka_max > 0 ? 2 * ka_max + 2 : 0)) * NT);
+  if (h->d_krylov != prev_krylov) stats.n_aug = stats.aug_next = 0;  // store lost with the old buffer
   if (rc == LMDG_OK) rc = ensure_small(h, L.total);
   if (rc != LMDG_OK) return rc;
-  double* V = h->d_krylov;               // m + 1 basis vectors of length NT
-  double* r = V + (size_t)(m + 1) * NT;  // residual work vector
+  double* V = h->d_krylov;                 // mt + 1 basis vectors of length NT
+  double* r = V + (size_t)(mt + 1) * NT;   // residual work vector
+  double* Z = r + NT;                      // ka_max stored corrections
+  double* AZ = Z + (size_t)ka_max * NT;    // their images
+  double* dz = ka_max > 0 ? AZ + (size_t)ka_max * NT : x;  // this cycle's correction (x itself
+  double* adz = dz + NT;                                     // without augmentation), its image
   double* dcoef = h->d_small + L.coef;
   double* dscal = h->d_small + L.scal;
   double* part = h->d_small + L.part;
-  double* hc = h->h_small + L.coef;      // first pass at 0, second at (m + 1) nr
+  double* hc = h->h_small + L.coef;        // first pass at 0, second at (mt + 1) nr
   double* hscal = h->h_small + L.scal;
-  std::vector<double> bnorm(nr), beta(nr), hn(nr);
+  std::vector<double> bnorm(nr), beta(nr), hn(nr), zn(nr);
   rc = seg_norms(h, b, N, nr, bnorm.data(), st);
   if (rc != LMDG_OK) return rc;
   converged = false;
   relres = 1.0;
-  std::vector<std::vector<double>> H(nr, std::vector<double>((size_t)(m + 1) * m)), cs(nr, std::vector<double>(m)),
-      sn(nr, std::vector<double>(m)), g(nr, std::vector<double>(m + 1));
+  const size_t hsz = (size_t)(mt + 1) * mt;
+  std::vector<std::vector<double>> H(nr, std::vector<double>(hsz)), H0(nr, std::vector<double>(hsz)),
+      cs(nr, std::vector<double>(mt)), sn(nr, std::vector<double>(mt)), g(nr, std::vector<double>(mt + 1));
   std::vector<int> kr(nr);
   std::vector<char> done(nr);
-  std::vector<double> y(m);
+  std::vector<double> y(mt);
+  std::vector<std::vector<double>> ys(nr, std::vector<double>(mt, 0.0));
+  int& n_aug = stats.n_aug;                // stored corrections, ring position
+  int& aug_next = stats.aug_next;
+  if (n_aug > ka_max || aug_next >= std::max(ka_max, 1)) n_aug = aug_next = 0;
   double prev_relres = -1.0;
   hipEvent_t e0, e1;
   hipEventCreate(&e0);
@@ -666,8 +693,8 @@ int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, doubl
       relres = std::max(relres, bnorm[k] > 0 ? beta[k] / bnorm[k] : 0.0);
     }
     if (verbose())
-      std::fprintf(stderr, "lmdg GMRES(%d) %s: restart %d, %d its, true rel residual %.3e (max over %d rhs)\n", m,
-                   prec == LMDG_PREC_FP64 ? "fp64" : "fp32", stats.restarts, stats.iterations, relres, nr);
+      std::fprintf(stderr, "lmdg GMRES(%d+%d) %s: restart %d, %d its, true rel residual %.3e (max over %d rhs)\n", m,
+                   n_aug, prec == LMDG_PREC_FP64 ? "fp64" : "fp32", stats.restarts, stats.iterations, relres, nr);
     if (!finite) { rc = set_error(h, LMDG_NONFINITE, "non-finite residual"); break; }
     if (relres <= rtol) { converged = true; break; }
     if (stats.iterations >= max_iter) break;
@@ -686,11 +713,20 @@ int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, doubl
     rc = upload_scales();
     if (rc != LMDG_OK) break;
     lmdg::vec_scale_seg(V, r, dscal, N, nr, st);
-    for (int j = 0; j < m && stats.iterations < max_iter; ++j) {
+    const int steps = m + n_aug;
+    for (int j = 0; j < steps; ++j) {
+      const bool krylov = j < m;
+      if (krylov && stats.iterations >= max_iter) break;
       double* w = V + (size_t)(j + 1) * NT;
-      rc = timed_apply(prec, V + (size_t)j * NT, w);
-      if (rc != LMDG_OK) break;
-      stats.iterations += 1;
+      if (krylov) {
+        rc = timed_apply(prec, V + (size_t)j * NT, w);
+        if (rc != LMDG_OK) break;
+        stats.iterations += 1;
+      } else {
+        // image of a stored correction, newest first
+        const int slot = ((aug_next - 1 - (j - m)) % ka_max + ka_max) % ka_max;
+        lmdg::vec_copy(w, AZ + (size_t)slot * NT, NT, st);
+      }
       // two passes of classical Gram-Schmidt, coefficients kept on the device
       lmdg::vec_dots(V, NT, j + 1, w, N, part, dcoef, st, nr);
       lmdg::vec_axpy_multi(w, V, NT, j + 1, dcoef, -1.0, N, st, nr);
@@ -698,68 +734,124 @@ int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, doubl
       if (rc != LMDG_OK) break;
       lmdg::vec_dots(V, NT, j + 1, w, N, part, dcoef, st, nr);
       lmdg::vec_axpy_multi(w, V, NT, j + 1, dcoef, -1.0, N, st, nr);
-      rc = check_hip(h, hipMemcpyAsync(hc + (size_t)(m + 1) * nr, dcoef, (j + 1) * nr * sizeof(double),
+      rc = check_hip(h, hipMemcpyAsync(hc + (size_t)(mt + 1) * nr, dcoef, (j + 1) * nr * sizeof(double),
                                        hipMemcpyDeviceToHost, st), "h2");
       if (rc != LMDG_OK) break;
       rc = seg_norms(h, w, N, nr, hn.data(), st);  // synchronises: hc is valid afterwards
-      add_time();
+      if (krylov) add_time();
       if (rc != LMDG_OK) break;
       bool all_done = true;
       for (int k = 0; k < nr; ++k) {
-        if (done[k]) {
+        if (done[k]) {  // finished at an earlier step: its segments stay zero
           hscal[k] = 0.0;
           continue;
         }
         if (!std::isfinite(hn[k])) { rc = set_error(h, LMDG_NONFINITE, "non-finite Krylov vector"); break; }
         std::vector<double>& Hk = H[k];
         for (int i = 0; i <= j; ++i)
-          Hk[(size_t)i * m + j] = hc[(size_t)i * nr + k] + hc[(size_t)(m + 1) * nr + (size_t)i * nr + k];
-        Hk[(size_t)(j + 1) * m + j] = hn[k];
+          Hk[(size_t)i * mt + j] = hc[(size_t)i * nr + k] + hc[(size_t)(mt + 1) * nr + (size_t)i * nr + k];
+        Hk[(size_t)(j + 1) * mt + j] = hn[k];
+        for (int i = 0; i <= j + 1; ++i) H0[k][(size_t)i * mt + j] = Hk[(size_t)i * mt + j];
         for (int i = 0; i < j; ++i) {  // previous rotations
-          const double a = Hk[(size_t)i * m + j], c = Hk[(size_t)(i + 1) * m + j];
-          Hk[(size_t)i * m + j] = cs[k][i] * a + sn[k][i] * c;
-          Hk[(size_t)(i + 1) * m + j] = -sn[k][i] * a + cs[k][i] * c;
+          const double a = Hk[(size_t)i * mt + j], c = Hk[(size_t)(i + 1) * mt + j];
+          Hk[(size_t)i * mt + j] = cs[k][i] * a + sn[k][i] * c;
+          Hk[(size_t)(i + 1) * mt + j] = -sn[k][i] * a + cs[k][i] * c;
         }
-        const double a = Hk[(size_t)j * m + j], c = Hk[(size_t)(j + 1) * m + j];
+        const double a = Hk[(size_t)j * mt + j], c = Hk[(size_t)(j + 1) * mt + j];
         const double rr = std::hypot(a, c);
-        cs[k][j] = rr == 0 ? 1.0 : a / rr;
-        sn[k][j] = rr == 0 ? 0.0 : c / rr;
-        Hk[(size_t)j * m + j] = rr;
-        Hk[(size_t)(j + 1) * m + j] = 0.0;
+        hscal[k] = hn[k] > 0.0 ? 1.0 / hn[k] : 0.0;
+        if (rr == 0.0) {
+          // direction already in the span (only a stored correction can be): drop
+          // the column and stop this right-hand side's cycle
+          done[k] = 1;
+          continue;
+        }
+        cs[k][j] = a / rr;
+        sn[k][j] = c / rr;
+        Hk[(size_t)j * mt + j] = rr;
+        Hk[(size_t)(j + 1) * mt + j] = 0.0;
         g[k][j + 1] = -sn[k][j] * g[k][j];
         g[k][j] = cs[k][j] * g[k][j];
         kr[k] = j + 1;
         if (std::fabs(g[k][j + 1]) <= 0.5 * rtol * bnorm[k] || hn[k] == 0.0) done[k] = 1;
-        hscal[k] = done[k] ? 0.0 : 1.0 / hn[k];
         all_done = all_done && done[k];
       }
-      if (rc != LMDG_OK || all_done) break;
+      if (rc != LMDG_OK) break;
+      // normalise the new basis vector of every right-hand side active at this step
+      // (the image of the cycle's correction uses it also when that one just finished)
       rc = upload_scales();
       if (rc != LMDG_OK) break;
-      lmdg::vec_scale_seg(w, w, dscal, N, nr, st);  // finished segments become zero
+      lmdg::vec_scale_seg(w, w, dscal, N, nr, st);
+      if (all_done) break;
     }
     if (rc != LMDG_OK) break;
-    // x[k] += V y_k with H_k y_k = g_k (upper triangular, k_r columns)
+    // per right-hand side: H_k y_k = g_k (upper triangular, k_r columns)
     int kmax = 0;
     for (int k = 0; k < nr; ++k) kmax = std::max(kmax, kr[k]);
-    if (kmax > 0) {
-      std::fill(hc, hc + (size_t)kmax * nr, 0.0);
-      for (int k = 0; k < nr; ++k) {
-        const int kk = kr[k];
-        const std::vector<double>& Hk = H[k];
-        for (int i = kk - 1; i >= 0; --i) {
-          double acc = g[k][i];
-          for (int jj = i + 1; jj < kk; ++jj) acc -= Hk[(size_t)i * m + jj] * y[jj];
-          y[i] = acc / Hk[(size_t)i * m + i];
-        }
-        for (int i = 0; i < kk; ++i) hc[(size_t)i * nr + k] = y[i];
+    if (kmax == 0) continue;
+    for (int k = 0; k < nr; ++k) {
+      std::fill(ys[k].begin(), ys[k].end(), 0.0);
+      const int kk = kr[k];
+      const std::vector<double>& Hk = H[k];
+      for (int i = kk - 1; i >= 0; --i) {
+        double acc = g[k][i];
+        for (int jj = i + 1; jj < kk; ++jj) acc -= Hk[(size_t)i * mt + jj] * y[jj];
+        y[i] = acc / Hk[(size_t)i * mt + i];
       }
-      rc = check_hip(h, hipMemcpyAsync(dcoef, hc, (size_t)kmax * nr * sizeof(double), hipMemcpyHostToDevice, st),
-                     "y");
-      if (rc != LMDG_OK) break;
-      lmdg::vec_axpy_multi(x, V, NT, kmax, dcoef, 1.0, N, st, nr);
-      rc = check_hip(h, hipStreamSynchronize(st), "update");  // hc is reused next cycle
+      for (int i = 0; i < kk; ++i) ys[k][i] = y[i];
     }
+    // correction dz = Z y: Krylov part sum_{j<m} y_j V_j, augmented part sum_l y_{m+l} z_l
+    const int nkry = std::min(kmax, m);
+    std::fill(hc, hc + (size_t)(mt + 1) * nr, 0.0);
+    for (int k = 0; k < nr; ++k)
+      for (int i = 0; i < nkry; ++i) hc[(size_t)i * nr + k] = ys[k][i];
+    rc = check_hip(h, hipMemcpyAsync(dcoef, hc, (size_t)nkry * nr * sizeof(double), hipMemcpyHostToDevice, st), "y");
+    if (rc != LMDG_OK) break;
+    if (ka_max > 0) lmdg::vec_fill(dz, 0.0, NT, st);
+    lmdg::vec_axpy_multi(dz, V, NT, nkry, dcoef, 1.0, N, st, nr);
+    if (kmax > m) {
+      // stored corrections: coefficients by ring slot (step m + l used slot aug_next - 1 - l)
+      double* hz = hc + (size_t)(mt + 1) * nr;
+      std::fill(hz, hz + (size_t)ka_max * nr, 0.0);
+      for (int l = 0; l + m < kmax; ++l) {
+        const int slot = ((aug_next - 1 - l) % ka_max + ka_max) % ka_max;
+        for (int k = 0; k < nr; ++k) hz[(size_t)slot * nr + k] = ys[k][m + l];
+      }
+      double* dz_coef = dcoef + (size_t)(mt + 1) * nr;
+      rc = check_hip(h, hipMemcpyAsync(dz_coef, hz, (size_t)ka_max * nr * sizeof(double), hipMemcpyHostToDevice,
+                                       st), "y aug");
+      if (rc != LMDG_OK) break;
+      lmdg::vec_axpy_multi(dz, Z, NT, n_aug, dz_coef, 1.0, N, st, nr);
+    }
+    if (ka_max > 0) lmdg::vec_axpby(x, 1.0, dz, 1.0, NT, st);
+    rc = check_hip(h, hipStreamSynchronize(st), "update");  // the host coefficients are reused
+    if (rc != LMDG_OK || ka_max == 0) continue;
+    // image K dz = V (H0 y) from the unrotated Hessenberg columns, then store the
+    // normalised pair (z, K z) in the ring
+    std::fill(hc, hc + (size_t)(mt + 1) * nr, 0.0);
+    for (int k = 0; k < nr; ++k) {
+      const int kk = kr[k];
+      for (int i = 0; i <= kk; ++i) {
+        double acc = 0.0;
+        for (int jj = 0; jj < kk; ++jj) acc += (i <= jj + 1 ? H0[k][(size_t)i * mt + jj] : 0.0) * ys[k][jj];
+        hc[(size_t)i * nr + k] = acc;
+      }
+    }
+    rc = check_hip(h, hipMemcpyAsync(dcoef, hc, (size_t)(kmax + 1) * nr * sizeof(double), hipMemcpyHostToDevice,
+                                     st), "hy");
+    if (rc != LMDG_OK) break;
+    lmdg::vec_fill(adz, 0.0, NT, st);
+    lmdg::vec_axpy_multi(adz, V, NT, kmax + 1, dcoef, 1.0, N, st, nr);
+    rc = seg_norms(h, dz, N, nr, zn.data(), st);
+    if (rc != LMDG_OK) break;
+    for (int k = 0; k < nr; ++k) hscal[k] = zn[k] > 0 ? 1.0 / zn[k] : 0.0;
+    rc = upload_scales();
+    if (rc != LMDG_OK) break;
+    lmdg::vec_scale_seg(Z + (size_t)aug_next * NT, dz, dscal, N, nr, st);
+    lmdg::vec_scale_seg(AZ + (size_t)aug_next * NT, adz, dscal, N, nr, st);
+    aug_next = (aug_next + 1) % ka_max;
+    n_aug = std::min(n_aug + 1, ka_max);
+    rc = check_hip(h, hipStreamSynchronize(st), "augment");
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -1058,6 +1150,13 @@ int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, doubl
     info->time_apply_ms = inf_f.time_apply_ms + inf_a.time_apply_ms;
   }
   return rc;
+}
+
+int lmdg_set_augment(lmdg_t* h, int k) {
+  if (!h) return LMDG_INVALID_ARG;
+  if (k < 0 || k > kMaxRestart - 1) return set_error(h, LMDG_INVALID_ARG, "augmentation count out of range");
+  h->augment = k;
+  return LMDG_OK;
 }
 
 int lmdg_profile(lmdg_t* h, int enable) {

@@ -147,6 +147,7 @@ struct lmdg_handle {
   double* d_small = nullptr;       // device scratch for dot products
   double* h_small = nullptr;       // pinned host mirror
   size_t small_doubles = 0;
+  int augment = 0;                 // LGMRES: stored corrections searched per restart cycle
 };
 
 namespace lmdg {

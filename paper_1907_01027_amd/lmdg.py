@@ -28,7 +28,8 @@ MODES = {"fp64": 0, "mixed": 1}
 
 EXPORTED = ["lmdg_status_string", "lmdg_last_error", "lmdg_quadrature_level_symmetric", "lmdg_create",
             "lmdg_destroy", "lmdg_set_materials", "lmdg_set_sources", "lmdg_sweep", "lmdg_apply", "lmdg_rhs",
-            "lmdg_recover", "lmdg_solve", "lmdg_adjoint_solve", "lmdg_profile", "lmdg_sweep_kernel_time"]
+            "lmdg_recover", "lmdg_solve", "lmdg_set_augment", "lmdg_adjoint_solve", "lmdg_profile",
+            "lmdg_sweep_kernel_time"]
 
 
 class LmdgInfo(ctypes.Structure):
@@ -65,6 +66,7 @@ def _load():
         "lmdg_recover": (I, [P, I, I, P, P, P, P]),
         "lmdg_solve": (I, [P, I, I, D, I, I, P, P, P, ctypes.POINTER(LmdgInfo), P]),
         "lmdg_adjoint_solve": (I, [P, I, I, P, D, I, I, P, P, P, ctypes.POINTER(D), ctypes.POINTER(LmdgInfo), P]),
+        "lmdg_set_augment": (I, [P, I]),
         "lmdg_profile": (I, [P, I]),
         "lmdg_sweep_kernel_time": (I, [P, ctypes.POINTER(D), ctypes.POINTER(I)]),
     }
@@ -196,6 +198,11 @@ def lmdg_adjoint_solve(h, scheme, mode, det, tol, restart, max_iter, g_sigma_s, 
                                    int(max_iter), _ptr(g_sigma_s), _ptr(g_sigma_a), _ptr(g_q), ctypes.byref(J),
                                    ctypes.byref(info), _stream(stream)), h)
     return J.value, info.as_dict()
+
+
+def lmdg_set_augment(h, k):
+    """Number of earlier restart corrections each GMRES cycle also searches (LGMRES); 0 = plain GMRES."""
+    _check(_lib.lmdg_set_augment(h, int(k)), h)
 
 
 def lmdg_profile(h, enable):

@@ -5,7 +5,8 @@ low-memory scheme (all four quadrant sweeps with their angular reductions, the
 B_11 stencil and the combine) on the 256 x 256, S8 (40 directions) workload with
 eps = 1e-3 and seeded 8 x 8 block cross sections.  value = n_cells * n_dir * steps
 / timed seconds.  After the timed steps the same workload is solved to a true FP64
-relative residual of 1e-8 in FP64 mode and in mixed mode (FP32 sweeps), and the
+relative residual of 1e-8 in FP64 mode and in mixed mode (FP32 sweeps) with
+LGMRES(60 + 10) (restart cycles augmented with the last ten corrections), and the
 dominant kernel (the sweep) is timed live with HIP events on its launch stream for
 the roofline figure.  The CPU baseline times the CPU oracle's operator on a bounded
 sample of the same recipe (see cpu_baseline.sample).
@@ -33,7 +34,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--solve-max-iter", type=int, default=4000)
+    ap.add_argument("--solve-max-iter", type=int, default=16000)
+    ap.add_argument("--augment", type=int, default=10,
+                    help="LGMRES: earlier corrections searched per restart cycle (0 = plain GMRES)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the secondary measurements (other workloads, several sources, small solves)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -160,9 +163,11 @@ def _apply_rate(torch, lmdg, h, scheme, prec, x, y, ncell, ndir, n_rhs=1, reps=5
 
 def extra_measurements(torch, lmdg, WORKLOADS, materials):
     """Secondary figures: operator throughput on the other 2D workloads (FP64 and FP32
-    sweeps), eight sources swept together, FP64 vs mixed solves of the 20x20 S4
-    workload to 1e-8 and 1e-10, and the 128^3 3D workload with eight sources (operator
-    throughput and solves to 1e-8, FP64 vs mixed)."""
+    sweeps), eight sources swept together, the 512x512 S12 detector gradients (adjoint
+    solves, FP64 vs mixed), FP64 vs mixed solves of the 20x20 S4 workload to 1e-8 and
+    1e-10, and the 128^3 3D workload with eight sources (operator throughput and solves
+    to 1e-8, FP64 vs mixed)."""
+    from paper_1907_01027_amd.adjoint import box_detector_moments
     dev = torch.device("cuda:0")
     T = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     res = {}
@@ -192,6 +197,41 @@ def extra_measurements(torch, lmdg, WORKLOADS, materials):
     res["256x256_S8_rlmdg_8_sources"] = {
         p: _apply_rate(torch, lmdg, s.h, "rlmdg", p, x, y, nc, len(w), n_rhs=8) for p in ("fp64", "fp32")}
     s.close()
+    # 512x512, S12, eps = 1e-2, LMDG: detector response and its gradients (forward and
+    # adjoint solves to 1e-8 with LGMRES(60 + 10), per-quadrant recomputed fluxes)
+    wl = WORKLOADS[4]
+    ss, sa, ep, q = materials(4)
+    om, w = lmdg.lmdg_quadrature_level_symmetric(2, wl.order)
+    s = lmdg.Solver(wl.n, (1.0, 1.0), om, w)
+    lmdg.lmdg_set_materials(s.h, T(ss), T(sa), T(ep), T(q[0]))
+    lmdg.lmdg_set_augment(s.h, 10)
+    nc = wl.n[0] * wl.n[1]
+    lo, hi = wl.extra["detector"]
+    det = T(box_detector_moments(wl.n, (1.0, 1.0), lo, hi).ravel())
+    adj = {}
+    g64 = None
+    for mode in ("fp64", "mixed"):
+        g = [torch.zeros(nc, dtype=torch.float64, device=dev) for _ in range(3)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            J, info = lmdg.lmdg_adjoint_solve(s.h, "lmdg", mode, det, 1e-8, 60, 30000, *g)
+            ok = True
+        except lmdg.LmdgError as e:
+            J, info, ok = float("nan"), {"error": str(e)}, False
+        torch.cuda.synchronize()
+        e = {"wall_s": time.perf_counter() - t0, "J": J, "converged": ok,
+             "iterations": info.get("iterations"), "rel_residual": info.get("rel_residual")}
+        if mode == "fp64":
+            g64, J64 = g, J
+        elif ok and g64 is not None:
+            e["J_rel_diff_vs_fp64"] = abs(J - J64) / abs(J64)
+            for name, a64, a in zip(("sigma_s", "sigma_a", "q"), g64, g):
+                e[f"grad_{name}_rel_diff_vs_fp64"] = float((a - a64).abs().max() / a64.abs().max())
+        adj[mode] = e
+    res["512x512_S12_lmdg_adjoint_gradients"] = adj
+    s.close()
+    del g64
     # 20x20, S4, eps = 1: solve times to 1e-8 and 1e-10, FP64 vs mixed
     wl = WORKLOADS[1]
     ss, sa, ep, q = materials(1)
@@ -328,6 +368,8 @@ def main():
         res = {}
         xs = torch.zeros(N, dtype=torch.float64, device=dev)
         phi = torch.zeros(N, dtype=torch.float64, device=dev)
+        lmdg.lmdg_set_augment(h, args.augment)
+        phi64 = None
         for mode in ("fp64", "mixed"):
             xs.zero_()
             torch.cuda.synchronize()
@@ -336,8 +378,13 @@ def main():
                                    raise_on_nonconvergence=False)
             torch.cuda.synchronize()
             info["wall_s"] = time.perf_counter() - t0
+            if mode == "fp64":
+                phi64 = phi.clone()
+            else:  # scalar flux of the mixed solve against the FP64 solve at the same tolerance
+                info["phi_rel_diff_vs_fp64"] = float((phi - phi64).abs().max() / phi64.abs().max())
             res[mode] = info
-        out["solve"] = {"tol": 1e-8, "restart": 60, "max_iter": args.solve_max_iter, **res}
+        out["solve"] = {"tol": 1e-8, "restart": 60, "augment": args.augment, "max_iter": args.solve_max_iter,
+                        **res}
     solver.close()
     if not args.no_extra:
         out["extra"] = extra_measurements(torch, lmdg, WORKLOADS, materials)

@@ -593,7 +593,18 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
           }
         }
       }
+      // publish this chunk's strip-top traces before the staging and reduction below,
+      // which the strip above does not wait for: every wave waits for its own trace
+      // stores to complete before the barrier, then one thread releases and raises the flag
+      if (s + 1 < P.nstrips) __builtin_amdgcn_s_waitcnt(kWaitVmem);
       __syncthreads();
+      if (s + 1 < P.nstrips && tid == 0) {
+        const int done = min(nx, t0 + cw - (kRows - 1));
+        if (done > 0) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          store_agent(progr + (long long)q * P.nstrips + s, (P.epoch << 32) | (unsigned long long)done);
+        }
+      }
       if (k + 1 < P.nchunks) stage_store(k + 1, buf ^ 1);
       // sums over waves, written with consecutive threads on consecutive columns
       const int nred = (NOUT * kRows) << lcw;
@@ -609,13 +620,6 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
           const int i = sxi > 0 ? c : nx - 1 - c;
           const int jj = syi > 0 ? jr2 : ny - 1 - jr2;
           partr[((long long)q * NOUT + m) * nc + (long long)jj * nx + i] = acc;
-        }
-      }
-      if (s + 1 < P.nstrips && tid == 0) {
-        const int done = min(nx, t0 + cw - (kRows - 1));
-        if (done > 0) {
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          store_agent(progr + (long long)q * P.nstrips + s, (P.epoch << 32) | (unsigned long long)done);
         }
       }
     }

@@ -402,7 +402,20 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
           }
         }
       }
+      // publish: columns below `done` are finished by every row of this strip (also
+      // their z traces, which plane kz + 1 reads, and their reads of plane kz - 1).
+      // Raised before the staging and reduction below, which no other item waits for:
+      // every wave waits for its own trace stores to complete before the barrier.
+      const bool publish = s + 1 < P.nstrips || kz + 1 < nz;
+      if (publish) __builtin_amdgcn_s_waitcnt(kWaitVmem);
       __syncthreads();
+      if (tid == 0 && publish) {
+        const int done = (k + 1 == P.nchunks) ? nx : min(nx, t0 + cw - (kRows - 1));
+        if (done > 0) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          store_agent(progr + (long long)kz * P.nstrips + s, (P.epoch << 32) | (unsigned long long)done);
+        }
+      }
       if (k + 1 < P.nchunks) stage_store(k + 1, buf ^ 1);
       const int nred = (NOUT * kRows) << lcw;
       for (int e = tid; e < nred; e += blockDim.x) {
@@ -417,15 +430,6 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
           const int i = si[0] > 0 ? c : nx - 1 - c;
           const int jj = si[1] > 0 ? jr2 : ny - 1 - jr2;
           partr[((long long)o * NOUT + m) * nc + (long long)kk * nxy + (long long)jj * nx + i] = acc;
-        }
-      }
-      // publish: columns below `done` are finished by every row of this strip (also
-      // their z traces, which plane kz + 1 reads, and their reads of plane kz - 1)
-      if (tid == 0 && (s + 1 < P.nstrips || kz + 1 < nz)) {
-        const int done = (k + 1 == P.nchunks) ? nx : min(nx, t0 + cw - (kRows - 1));
-        if (done > 0) {
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          store_agent(progr + (long long)kz * P.nstrips + s, (P.epoch << 32) | (unsigned long long)done);
         }
       }
     }

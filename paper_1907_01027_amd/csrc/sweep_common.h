@@ -49,6 +49,12 @@ __device__ __forceinline__ void store_agent(T* p, T v) {
 }
 
 constexpr long long kSpinLimit = 1ll << 25;
+
+// Immediate of s_waitcnt vmcnt(0) in the gfx9 encoding (expcnt and lgkmcnt at their
+// maxima, so they are not waited for): the wave's vector memory operations have
+// completed.  Agent-scope atomic stores are written through to the agent's coherence
+// point, so after this wait they are visible to every workgroup.
+constexpr int kWaitVmem = 0x0F70;
 // Reciprocal from a hardware estimate refined by Newton steps r <- r + r (1 - d r);
 // the denominators of the low-memory sweeps do not depend on the upwind values, so
 // this runs off the step's dependency chain.  FP64: the single-precision estimate

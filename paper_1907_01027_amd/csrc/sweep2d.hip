@@ -34,7 +34,10 @@
 namespace lmdg {
 namespace {
 
-constexpr int kStepGroup = 4;  // steps per unrolled group; chunks hold a multiple of it
+// Steps per unrolled group (chunks hold a multiple of it): measured on gfx950, two
+// FP64 steps per group schedule better than four, FP32 steps the other way round.
+template <typename R>
+constexpr int step_group() { return sizeof(R) == 8 ? 2 : 4; }
 
 // Per-lane direction constants.
 template <typename R>
@@ -349,6 +352,7 @@ __device__ __forceinline__ void raw_coef(const double* raw, int c, int jr, int s
 template <typename R, int S, int MAXW>
 __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
   constexpr int NOUT = SchemeTraits<S>::NOUT;
+  constexpr int NOUTP = (NOUT + 3) & ~3;  // rows of red, padded to whole lane groups
   constexpr int NF = SchemeTraits<S>::NF;
   constexpr int NS = SrcTraits<S>::NS;
   constexpr int NC = SrcTraits<S>::NC;
@@ -370,11 +374,14 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
   const int lcw = P.lcw;
   const int cw = 1 << lcw;
   const int ncells = kRows << lcw;  // cells staged per chunk
-  // LDS: red [cw][W][NOUT][16] | coef [2][NC][cw][16] | eds [cw][NF][dslots]
+  // LDS: red [cw][W][NOUTP][16] | coef [2][NC][cw][16] | eds [cw][NF][dslots]
   // (coefficients structure-of-arrays: the 16 rows of one value are contiguous, so
   // 64-bit reads by the 16 rows of a wave hit distinct banks)
   R* red = reinterpret_cast<R*>(smem_raw);
-  R* coef = red + (size_t)cw * W * NOUT * kRows;
+  // one column's block of red holds W x NOUTP x 16 values plus one pad, so that the
+  // reduction's reads of consecutive columns fall in different banks
+  const int red_tt = W * NOUTP * kRows + 1;
+  R* coef = red + (size_t)cw * red_tt;
   R* eds = coef + (size_t)2 * ncells * NC;
 
   for (;;) {
@@ -480,7 +487,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
       // values) are formed first as independent chains, then the U dependent steps
       // follow; the body has no branches except the stores after each group, so one
       // wave can overlap the latencies itself.
-      constexpr int U = kStepGroup;
+      constexpr int U = step_group<R>();
       for (int tg = 0; tg < cw; tg += U) {
         R src_g[U][NS], sig_g[U], inv_g[U], edn_g[U][NF];
 #pragma unroll
@@ -559,9 +566,15 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
           }
 #pragma unroll
           for (int m = 0; m < NOUT; ++m) o[m] = quad_sum(act ? o[m] : R(0));
-          if (lane < kRows) {  // the four lanes of a row hold the same sum
+          // the four 16-lane groups hold the same sums: group g stores rows g, g + 4, ...
+          // (no branch, so the steps of a group stay one scheduling region)
 #pragma unroll
-            for (int m = 0; m < NOUT; ++m) red[((tt * W + wv) * NOUT + m) * kRows + r] = o[m];
+          for (int m0 = 0; m0 < NOUTP; m0 += 4) {
+            R v = o[m0];
+#pragma unroll
+            for (int g = 1; g < 4; ++g)
+              if (m0 + g < NOUT) v = (lane >> 4) == g ? o[m0 + g] : v;
+            red[tt * red_tt + (wv * NOUTP + m0 + (lane >> 4)) * kRows + r] = v;
           }
         }
         if (r == kRows - 1 && s + 1 < P.nstrips) {
@@ -616,7 +629,9 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
         const int jr2 = s * kRows + rr;
         if (jr2 < ny && c >= 0 && c < nx) {
           R acc = 0;
-          for (int w2 = 0; w2 < W; ++w2) acc += red[((tt * W + w2) * NOUT + m) * kRows + rr];
+#pragma unroll
+          for (int w2 = 0; w2 < MAXW; ++w2)
+            if (w2 < W) acc += red[tt * red_tt + (w2 * NOUTP + m) * kRows + rr];
           const int i = sxi > 0 ? c : nx - 1 - c;
           const int jj = syi > 0 ? jr2 : ny - 1 - jr2;
           partr[((long long)q * NOUT + m) * nc + (long long)jj * nx + i] = acc;
@@ -632,7 +647,8 @@ size_t lds_bytes(int cw, int W, int dslots) {
   constexpr int NOUT = SchemeTraits<S>::NOUT;
   constexpr int NF = SchemeTraits<S>::NF;
   constexpr int NC = SrcTraits<S>::NC;
-  return ((size_t)cw * W * NOUT * kRows + (size_t)2 * cw * kRows * NC + (size_t)cw * NF * dslots) * sizeof(R);
+  constexpr int NOUTP = (NOUT + 3) & ~3;
+  return ((size_t)cw * (W * NOUTP * kRows + 1) + (size_t)2 * cw * kRows * NC + (size_t)cw * NF * dslots) * sizeof(R);
 }
 
 template <typename R, int S>
@@ -649,7 +665,7 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   constexpr size_t kLdsBudget = 144 * 1024;
   int cw = 16;
   const int maxc = W > 4 ? 1 : SrcTraits<S>::MAXC;
-  while (cw > kStepGroup && (kRows * cw > maxc * 64 * W || lds_bytes<R, S>(cw, W, h->dslots) > kLdsBudget))
+  while (cw > step_group<R>() && (kRows * cw > maxc * 64 * W || lds_bytes<R, S>(cw, W, h->dslots) > kLdsBudget))
     cw >>= 1;
   P.cw = cw;
   P.lcw = 0;

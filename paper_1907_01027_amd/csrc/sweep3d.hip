@@ -43,7 +43,7 @@ template <> struct Traits3<LMDG_SCHEME_RLMDG> { static constexpr int NOUT = 10, 
 constexpr int kNC3 = 5;     // sigma_t V and the source coefficients a, b_x, b_y, b_z
 constexpr int kNRAW3 = 17;
 constexpr int kMAXC3 = 2;   // staged cells per thread
-constexpr int kStepGroup3 = 4;
+constexpr int kStepGroup3 = 2;  // steps per unrolled group (measured best on gfx950)
 
 template <typename R>
 struct Dir3 {
@@ -127,6 +127,7 @@ __device__ __forceinline__ void raw_coef3(const double* raw, const int pos[3], c
 template <typename R, int S, int MAXW>
 __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
   constexpr int NOUT = Traits3<S>::NOUT;
+  constexpr int NOUTP = (NOUT + 3) & ~3;  // rows of red, padded to whole lane groups
   constexpr int NF = Traits3<S>::NF;
   constexpr int NC = kNC3;
   constexpr int MAXC = MAXW > 4 ? 1 : kMAXC3;
@@ -148,9 +149,12 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
   const int ncells = kRows << lcw;
   const int ds = P.dslots;
   const double A[3] = {P.h[1] * P.h[2], P.h[0] * P.h[2], P.h[0] * P.h[1]};
-  // LDS: red [cw][W][NOUT][16] | coef [2][NC][cw][16] | eds [cw][NF][ds] | zds [cw][16][NF][ds]
+  // LDS: red [cw][W][NOUTP][16] | coef [2][NC][cw][16] | eds [cw][NF][ds] | zds [cw][16][NF][ds]
   R* red = reinterpret_cast<R*>(smem_raw);
-  R* coef = red + (size_t)cw * W * NOUT * kRows;
+  // one column's block of red holds W x NOUTP x 16 values plus one pad, so that the
+  // reduction's reads of consecutive columns fall in different banks
+  const int red_tt = W * NOUTP * kRows + 1;
+  R* coef = red + (size_t)cw * red_tt;
   R* eds = coef + (size_t)2 * ncells * NC;
   R* zds = eds + (size_t)cw * NF * ds;
 
@@ -374,9 +378,15 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
           }
 #pragma unroll
           for (int m = 0; m < NOUT; ++m) o[m] = quad_sum(act ? o[m] : R(0));
-          if (lane < kRows) {
+          // the four 16-lane groups hold the same sums: group g stores rows g, g + 4, ...
+          // (no branch, so the steps of a group stay one scheduling region)
 #pragma unroll
-            for (int m = 0; m < NOUT; ++m) red[((tt * W + wv) * NOUT + m) * kRows + r] = o[m];
+          for (int m0 = 0; m0 < NOUTP; m0 += 4) {
+            R v = o[m0];
+#pragma unroll
+            for (int g = 1; g < 4; ++g)
+              if (m0 + g < NOUT) v = (lane >> 4) == g ? o[m0 + g] : v;
+            red[tt * red_tt + (wv * NOUTP + m0 + (lane >> 4)) * kRows + r] = v;
           }
         }
         // deferred stores of the group: y traces (top row), z traces (every cell), psi
@@ -426,7 +436,9 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
         const int jr2 = s * kRows + rr;
         if (jr2 < ny && c >= 0 && c < nx) {
           R acc = 0;
-          for (int w2 = 0; w2 < W; ++w2) acc += red[((tt * W + w2) * NOUT + m) * kRows + rr];
+#pragma unroll
+          for (int w2 = 0; w2 < MAXW; ++w2)
+            if (w2 < W) acc += red[tt * red_tt + (w2 * NOUTP + m) * kRows + rr];
           const int i = si[0] > 0 ? c : nx - 1 - c;
           const int jj = si[1] > 0 ? jr2 : ny - 1 - jr2;
           partr[((long long)o * NOUT + m) * nc + (long long)kk * nxy + (long long)jj * nx + i] = acc;
@@ -441,7 +453,8 @@ template <typename R, int S>
 size_t lds_bytes3(int cw, int W, int dslots) {
   constexpr int NOUT = Traits3<S>::NOUT;
   constexpr int NF = Traits3<S>::NF;
-  return ((size_t)cw * W * NOUT * kRows + (size_t)2 * cw * kRows * kNC3 + (size_t)cw * NF * dslots +
+  constexpr int NOUTP = (NOUT + 3) & ~3;
+  return ((size_t)cw * (W * NOUTP * kRows + 1) + (size_t)2 * cw * kRows * kNC3 + (size_t)cw * NF * dslots +
           (size_t)cw * kRows * NF * dslots) *
          sizeof(R);
 }

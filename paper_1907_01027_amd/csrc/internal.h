@@ -154,6 +154,14 @@ namespace lmdg {
 
 constexpr int kScratchVecs = 4;
 
+// Slices of the sweep partials per right-hand side, each [NOUT][n_cells]: FP64 2D sweeps
+// with up to four waves per quadrant write one slice per (quadrant, wave), other 2D
+// sweeps one per quadrant, 3D sweeps one per octant.
+inline int part_slices(const lmdg_handle* h, int prec) {
+  if (h->dim == 3) return 8;
+  return (h->waves <= 4 && prec == LMDG_PREC_FP64) ? 4 * h->waves : 4;
+}
+
 // launchers (sweep2d.hip / ops.hip)
 int launch_sweep(lmdg_handle* h, int scheme, int prec, const double* x, bool use_q,
                  double* psi, hipStream_t st, bool defect = false, int qmask = 0xF,

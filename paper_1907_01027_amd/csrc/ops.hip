@@ -130,7 +130,7 @@ __device__ __forceinline__ void iso_g(const double* x0, int nx, int ny, int i, i
 // has no slope moments and the inflow is vacuum).  In kApplyDefect the sweep solved
 // L~_00 psi_D = defect source, and K x = [P_0 psi_D ; B_11 x_1 - G Sigma_0^T x_0 + G psi_D].
 template <typename R, bool RLM>
-__global__ void combine_lm_kernel(int mode, int nr, int nx, int ny, double hx, double hy, double cxp, double cxm,
+__global__ void combine_lm_kernel(int mode, int nr, int nsl, int nx, int ny, double hx, double hy, double cxp, double cxm,
                                   double cyp, double cym, QuadMoments qm, const double* __restrict__ x_all,
                                   const R* __restrict__ part_all, const double* __restrict__ sigtA,
                                   const double* __restrict__ scatA, const double* __restrict__ absA,
@@ -142,14 +142,13 @@ __global__ void combine_lm_kernel(int mode, int nr, int nx, int ny, double hx, d
     // right-hand side rh, cell p; vectors are stacked rhs-major
     const long long rh = pr / nc, p = pr - rh * nc;
     const double* x = x_all ? x_all + rh * 4 * nc : nullptr;
-    const R* part = part_all + rh * 4 * NOUT * nc;
+    const R* part = part_all + rh * nsl * NOUT * nc;
     double* out = out_all + rh * 4 * nc;
     double s[NOUT];
 #pragma unroll
     for (int m = 0; m < NOUT; ++m) {
       double acc = 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc += (double)part[((long long)q * NOUT + m) * nc + p];
+      for (int q = 0; q < nsl; ++q) acc += (double)part[((long long)q * NOUT + m) * nc + p];
       s[m] = acc;
     }
     const double sl = RLM ? scatA[p] * (1.0 / 3.0) : 0.0;  // Sigma M_1 on the xi, eta slopes
@@ -190,19 +189,18 @@ __global__ void combine_lm_kernel(int mode, int nr, int nx, int ny, double hx, d
 // Standard scheme: K Phi = Phi - P L^{-1} M Phi (eq-sndg-phi); right-hand side and
 // recovered scalar flux are the plain quadrant sums.
 template <typename R>
-__global__ void combine_std_kernel(int mode, int nr, long long nc, const double* __restrict__ x_all,
+__global__ void combine_std_kernel(int mode, int nr, int nsl, long long nc, const double* __restrict__ x_all,
                                    const R* __restrict__ part_all, double* __restrict__ out_all) {
   for (long long pr = blockIdx.x * (long long)blockDim.x + threadIdx.x; pr < nr * nc;
        pr += (long long)gridDim.x * blockDim.x) {
     const long long rh = pr / nc, p = pr - rh * nc;
     const double* x = x_all ? x_all + rh * 4 * nc : nullptr;
-    const R* part = part_all + rh * 16 * nc;
+    const R* part = part_all + rh * nsl * 4 * nc;
     double* out = out_all + rh * 4 * nc;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       double acc = 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc += (double)part[((long long)q * 4 + m) * nc + p];
+      for (int q = 0; q < nsl; ++q) acc += (double)part[((long long)q * 4 + m) * nc + p];
       // kApplyDefect: the sweep already produced P L^{-1}(defect source) = K Phi
       out[m * nc + p] = (mode == kApply) ? x[m * nc + p] - acc : acc;
     }
@@ -210,17 +208,17 @@ __global__ void combine_std_kernel(int mode, int nr, long long nc, const double*
 }
 
 template <typename R>
-__global__ void sum_quadrants_kernel(int nout, int nout_abi, int nr, long long nc, const R* __restrict__ part_all,
+__global__ void sum_quadrants_kernel(int nout, int nout_abi, int nr, int nsl, long long nc, const R* __restrict__ part_all,
                                      double* __restrict__ out_all) {
   for (long long pr = blockIdx.x * (long long)blockDim.x + threadIdx.x; pr < nr * nc;
        pr += (long long)gridDim.x * blockDim.x) {
     const long long rh = pr / nc, p = pr - rh * nc;
-    const R* part = part_all + rh * 4 * nout * nc;
+    const R* part = part_all + rh * nsl * nout * nc;
     double* out = out_all + rh * nout_abi * nc;
     for (int m = 0; m < nout_abi; ++m) {
       double acc = 0;
       if (m < nout)
-        for (int q = 0; q < 4; ++q) acc += (double)part[((long long)q * nout + m) * nc + p];
+        for (int q = 0; q < nsl; ++q) acc += (double)part[((long long)q * nout + m) * nc + p];
       out[m * nc + p] = acc;
     }
   }
@@ -386,10 +384,10 @@ void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double
   const int nx = (int)h->n[0], ny = (int)h->n[1];
   if (scheme == LMDG_SCHEME_STD) {
     if (prec == LMDG_PREC_FP64)
-      hipLaunchKernelGGL(combine_std_kernel<double>, dim3(g), dim3(kBlock), 0, st, mode, nr, nc, x,
+      hipLaunchKernelGGL(combine_std_kernel<double>, dim3(g), dim3(kBlock), 0, st, mode, nr, part_slices(h, prec), nc, x,
                          (const double*)h->ws.part, out);
     else
-      hipLaunchKernelGGL(combine_std_kernel<float>, dim3(g), dim3(kBlock), 0, st, mode, nr, nc, x,
+      hipLaunchKernelGGL(combine_std_kernel<float>, dim3(g), dim3(kBlock), 0, st, mode, nr, part_slices(h, prec), nc, x,
                          (const float*)h->ws.part, out);
     return;
   }
@@ -401,7 +399,7 @@ void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double
     qm.ay[q] = h->qay[q];
   }
 #define LMDG_COMBINE(R, RLM)                                                                        \
-  hipLaunchKernelGGL((combine_lm_kernel<R, RLM>), dim3(g), dim3(kBlock), 0, st, mode, nr, nx, ny, hx, hy, \
+  hipLaunchKernelGGL((combine_lm_kernel<R, RLM>), dim3(g), dim3(kBlock), 0, st, mode, nr, part_slices(h, prec), nx, ny, hx, hy, \
                      h->cplus[0], h->cminus[0], h->cplus[1], h->cminus[1], qm, x,                    \
                      (const R*)h->ws.part, h->d_sigtA, h->d_scatA, h->d_absA, out)
   const bool rlm = scheme == LMDG_SCHEME_RLMDG;
@@ -423,10 +421,10 @@ void launch_sum_quadrants(lmdg_handle* h, int scheme, int prec, double* out, hip
   const int g = std::min(grid_for(h->ncell * h->n_rhs), 4096);
   if (prec == LMDG_PREC_FP64)
     hipLaunchKernelGGL(sum_quadrants_kernel<double>, dim3(g), dim3(kBlock), 0, st, nout, nout_abi, h->n_rhs,
-                       h->ncell, (const double*)h->ws.part, out);
+                       part_slices(h, prec), h->ncell, (const double*)h->ws.part, out);
   else
     hipLaunchKernelGGL(sum_quadrants_kernel<float>, dim3(g), dim3(kBlock), 0, st, nout, nout_abi, h->n_rhs,
-                       h->ncell, (const float*)h->ws.part, out);
+                       part_slices(h, prec), h->ncell, (const float*)h->ws.part, out);
 }
 
 void launch_b11(lmdg_handle* h, const double* x, double* y, hipStream_t st) {

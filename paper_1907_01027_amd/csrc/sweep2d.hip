@@ -360,6 +360,11 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
   // staged cells per thread: the 9-wave variant has threads for a whole chunk
   constexpr int MAXC = MAXW > 4 ? 1 : SrcTraits<S>::MAXC;
   constexpr bool LM = S != LMDG_SCHEME_STD;
+  // FP64 with up to four waves: each wave writes its own quadrature sums straight to its
+  // slice of the partials, [quadrant][wave][NOUT][n_cells], summed over the slices by the
+  // combine (measured: this removes the cross-wave reduction from the chunk loop); FP32
+  // and wider kernels first sum across waves through LDS.
+  constexpr bool DIRECT = MAXW <= 4 && sizeof(R) == 8;
   extern __shared__ unsigned char smem_raw[];
   __shared__ int s_item;
 
@@ -374,15 +379,16 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
   const int lcw = P.lcw;
   const int cw = 1 << lcw;
   const int ncells = kRows << lcw;  // cells staged per chunk
-  // LDS: red [cw][W][NOUTP][16] | coef [2][NC][cw][16] | eds [cw][NF][dslots]
+  // LDS: red [cw][W][NOUTP][16] (not with DIRECT) | coef [2][NC][cw][16] | eds [cw][NF][dslots]
   // (coefficients structure-of-arrays: the 16 rows of one value are contiguous, so
   // 64-bit reads by the 16 rows of a wave hit distinct banks)
   R* red = reinterpret_cast<R*>(smem_raw);
   // one column's block of red holds W x NOUTP x 16 values plus one pad, so that the
   // reduction's reads of consecutive columns fall in different banks
   const int red_tt = W * NOUTP * kRows + 1;
-  R* coef = red + (size_t)cw * red_tt;
+  R* coef = red + (DIRECT ? 0 : (size_t)cw * red_tt);
   R* eds = coef + (size_t)2 * ncells * NC;
+  const int nsl = DIRECT ? 4 * W : 4;  // slices of the partials per right-hand side
 
   for (;;) {
     if (tid == 0) s_item = (int)(atomicAdd(P.ticket, 1u) - P.ticket_base);
@@ -396,7 +402,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
     const int rh = (item / P.nq) - s * P.n_rhs;
     const double* xr = P.x ? P.x + (long long)rh * 4 * nc : nullptr;
     const double* qAr = P.qA ? P.qA + (long long)rh * nc : nullptr;
-    R* const partr = P.part + (long long)rh * 4 * NOUT * nc;
+    R* const partr = P.part + (long long)rh * nsl * NOUT * nc;
     R* const edger = P.edge + rh * P.edge_rstride;
     unsigned long long* const progr = P.prog + (long long)rh * 4 * P.nstrips;
     double* const psir = P.psi ? P.psi + rh * P.psi_rstride : nullptr;
@@ -511,7 +517,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
 #pragma unroll
           for (int f = 0; f < NF; ++f) edn_g[u][f] = eds[((tt * NF) + f) * P.dslots + slot];
         }
-        R yo_g[U][NF], psi_g[U][4];
+        R yo_g[U][NF], psi_g[U][4], ov_g[U][NOUTP / 4];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int tt = tg + u;
@@ -566,7 +572,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
           }
 #pragma unroll
           for (int m = 0; m < NOUT; ++m) o[m] = quad_sum(act ? o[m] : R(0));
-          // the four 16-lane groups hold the same sums: group g stores rows g, g + 4, ...
+          // the four 16-lane groups hold the same sums: group g keeps rows g, g + 4, ...
           // (no branch, so the steps of a group stay one scheduling region)
 #pragma unroll
           for (int m0 = 0; m0 < NOUTP; m0 += 4) {
@@ -574,7 +580,26 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
 #pragma unroll
             for (int g = 1; g < 4; ++g)
               if (m0 + g < NOUT) v = (lane >> 4) == g ? o[m0 + g] : v;
-            red[tt * red_tt + (wv * NOUTP + m0 + (lane >> 4)) * kRows + r] = v;
+            if constexpr (DIRECT)
+              ov_g[u][m0 >> 2] = v;
+            else
+              red[tt * red_tt + (wv * NOUTP + m0 + (lane >> 4)) * kRows + r] = v;
+          }
+        }
+        if constexpr (DIRECT) {
+          // this wave's sums of the group's cells: lane group g writes rows g, g + 4, ...
+          const int g4 = lane >> 4;
+          R* const pw = partr + (long long)(q * W + wv) * NOUT * nc;
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int c = t0 + tg + u - r;
+            if (row_ok && c >= 0 && c < nx) {
+              const int i = sxi > 0 ? c : nx - 1 - c;
+              const long long cell = (long long)j * nx + i;
+#pragma unroll
+              for (int m0 = 0; m0 < NOUTP; m0 += 4)
+                if (m0 + g4 < NOUT) pw[(long long)(m0 + g4) * nc + cell] = ov_g[u][m0 >> 2];
+            }
           }
         }
         if (r == kRows - 1 && s + 1 < P.nstrips) {
@@ -620,7 +645,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
       }
       if (k + 1 < P.nchunks) stage_store(k + 1, buf ^ 1);
       // sums over waves, written with consecutive threads on consecutive columns
-      const int nred = (NOUT * kRows) << lcw;
+      const int nred = DIRECT ? 0 : (NOUT * kRows) << lcw;
       for (int e = tid; e < nred; e += blockDim.x) {
         const int tt = e & (cw - 1);
         const int m = (e >> lcw) % NOUT;
@@ -648,7 +673,9 @@ size_t lds_bytes(int cw, int W, int dslots) {
   constexpr int NF = SchemeTraits<S>::NF;
   constexpr int NC = SrcTraits<S>::NC;
   constexpr int NOUTP = (NOUT + 3) & ~3;
-  return ((size_t)cw * (W * NOUTP * kRows + 1) + (size_t)2 * cw * kRows * NC + (size_t)cw * NF * dslots) * sizeof(R);
+  const bool direct = W <= 4 && sizeof(R) == 8;  // no cross-wave reduction through LDS
+  const size_t red = direct ? 0 : (size_t)cw * (W * NOUTP * kRows + 1);
+  return (red + (size_t)2 * cw * kRows * NC + (size_t)cw * NF * dslots) * sizeof(R);
 }
 
 template <typename R, int S>

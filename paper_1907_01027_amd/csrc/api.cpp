@@ -350,7 +350,7 @@ int lmdg_create(int dim, const int64_t* n, const double* length, int n_dir, cons
   // per-right-hand-side workspace sizes
   const long long nc = h->ncell;
   if (dim == 2) {
-    h->ws.part_bytes = (size_t)lmdg::part_slices(h, LMDG_PREC_FP64) * 6 * nc * sizeof(double);
+    h->ws.part_bytes = (size_t)lmdg::part_slices_max(h) * 6 * nc * sizeof(double);
     h->ws.edge_bytes = (size_t)4 * h->nstrips * n[0] * 3 * h->dslots * sizeof(double);
     h->ws.zbuf_bytes = 0;
     h->ws.prog_words = (size_t)4 * h->nstrips;

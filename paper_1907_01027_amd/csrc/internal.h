@@ -155,11 +155,18 @@ namespace lmdg {
 constexpr int kScratchVecs = 4;
 
 // Slices of the sweep partials per right-hand side, each [NOUT][n_cells]: FP64 2D sweeps
-// with up to four waves per quadrant write one slice per (quadrant, wave), other 2D
-// sweeps one per quadrant, 3D sweeps one per octant.
+// with up to four waves per quadrant and at most one work item (quadrant, strip, source)
+// per compute unit write one slice per (quadrant, wave); other 2D sweeps one per
+// quadrant, 3D sweeps one per octant.  The sweep launch and the kernels that read the
+// partials take the same decision from the handle's current state.
+inline int part_slices_max(const lmdg_handle* h) {
+  if (h->dim == 3) return 8;
+  return h->waves <= 4 ? 4 * h->waves : 4;
+}
 inline int part_slices(const lmdg_handle* h, int prec) {
   if (h->dim == 3) return 8;
-  return (h->waves <= 4 && prec == LMDG_PREC_FP64) ? 4 * h->waves : 4;
+  const bool direct = h->waves <= 4 && prec == LMDG_PREC_FP64 && 4LL * h->nstrips * h->n_rhs <= h->n_cu;
+  return direct ? 4 * h->waves : 4;
 }
 
 // launchers (sweep2d.hip / ops.hip)

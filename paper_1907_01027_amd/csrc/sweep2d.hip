@@ -349,7 +349,12 @@ __device__ __forceinline__ void raw_coef(const double* raw, int c, int jr, int s
 }
 
 // MAXW bounds the waves per workgroup so that small direction sets get more registers.
-template <typename R, int S, int MAXW>
+// DIRECT: each wave writes its own quadrature sums straight to its slice of the
+// partials, [quadrant][wave][NOUT][n_cells], summed over the slices by the combine; this
+// takes the cross-wave reduction out of the chunk loop, which pays when few work items
+// run (one source on a small mesh).  Otherwise the waves' sums are first added through
+// LDS and the partials have one slice per quadrant.
+template <typename R, int S, int MAXW, bool DIRECT>
 __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
   constexpr int NOUT = SchemeTraits<S>::NOUT;
   constexpr int NOUTP = (NOUT + 3) & ~3;  // rows of red, padded to whole lane groups
@@ -360,11 +365,6 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
   // staged cells per thread: the 9-wave variant has threads for a whole chunk
   constexpr int MAXC = MAXW > 4 ? 1 : SrcTraits<S>::MAXC;
   constexpr bool LM = S != LMDG_SCHEME_STD;
-  // FP64 with up to four waves: each wave writes its own quadrature sums straight to its
-  // slice of the partials, [quadrant][wave][NOUT][n_cells], summed over the slices by the
-  // combine (measured: this removes the cross-wave reduction from the chunk loop); FP32
-  // and wider kernels first sum across waves through LDS.
-  constexpr bool DIRECT = MAXW <= 4 && sizeof(R) == 8;
   extern __shared__ unsigned char smem_raw[];
   __shared__ int s_item;
 
@@ -668,13 +668,12 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
 }
 
 template <typename R, int S>
-size_t lds_bytes(int cw, int W, int dslots) {
+size_t lds_bytes(int cw, int W, int dslots, bool direct) {
   constexpr int NOUT = SchemeTraits<S>::NOUT;
   constexpr int NF = SchemeTraits<S>::NF;
   constexpr int NC = SrcTraits<S>::NC;
   constexpr int NOUTP = (NOUT + 3) & ~3;
-  const bool direct = W <= 4 && sizeof(R) == 8;  // no cross-wave reduction through LDS
-  const size_t red = direct ? 0 : (size_t)cw * (W * NOUTP * kRows + 1);
+  const size_t red = direct ? 0 : (size_t)cw * (W * NOUTP * kRows + 1);  // cross-wave sums
   return (red + (size_t)2 * cw * kRows * NC + (size_t)cw * NF * dslots) * sizeof(R);
 }
 
@@ -692,7 +691,9 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   constexpr size_t kLdsBudget = 144 * 1024;
   int cw = 16;
   const int maxc = W > 4 ? 1 : SrcTraits<S>::MAXC;
-  while (cw > step_group<R>() && (kRows * cw > maxc * 64 * W || lds_bytes<R, S>(cw, W, h->dslots) > kLdsBudget))
+  const bool direct = part_slices(h, sizeof(R) == 8 ? LMDG_PREC_FP64 : LMDG_PREC_FP32) > 4;
+  while (cw > step_group<R>() &&
+         (kRows * cw > maxc * 64 * W || lds_bytes<R, S>(cw, W, h->dslots, direct) > kLdsBudget))
     cw >>= 1;
   P.cw = cw;
   P.lcw = 0;
@@ -727,7 +728,7 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   P.epoch = h->epoch;
   P.ticket_base = h->ticket_base;
   const int grid = std::min(P.n_items, 4 * h->n_cu);
-  const size_t lds = lds_bytes<R, S>(cw, W, h->dslots);
+  const size_t lds = lds_bytes<R, S>(cw, W, h->dslots, direct);
   hipEvent_t ev_end = nullptr;
   if (h->profiling) {
     if (h->ev_used + 2 > h->ev_pool.size()) {
@@ -741,10 +742,20 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
     ev_end = h->ev_pool[h->ev_used + 1];
     h->ev_used += 2;
   }
-  if (W <= 4)
-    hipLaunchKernelGGL((sweep2d_kernel<R, S, 4>), dim3(grid), dim3(64 * W), lds, st, P);
-  else
-    hipLaunchKernelGGL((sweep2d_kernel<R, S, kMaxWaves>), dim3(grid), dim3(64 * W), lds, st, P);
+  if constexpr (sizeof(R) == 8) {
+    if (direct) {  // only with up to four waves
+      hipLaunchKernelGGL((sweep2d_kernel<R, S, 4, true>), dim3(grid), dim3(64 * W), lds, st, P);
+    } else if (W <= 4) {
+      hipLaunchKernelGGL((sweep2d_kernel<R, S, 4, false>), dim3(grid), dim3(64 * W), lds, st, P);
+    } else {
+      hipLaunchKernelGGL((sweep2d_kernel<R, S, kMaxWaves, false>), dim3(grid), dim3(64 * W), lds, st, P);
+    }
+  } else {
+    if (W <= 4)
+      hipLaunchKernelGGL((sweep2d_kernel<R, S, 4, false>), dim3(grid), dim3(64 * W), lds, st, P);
+    else
+      hipLaunchKernelGGL((sweep2d_kernel<R, S, kMaxWaves, false>), dim3(grid), dim3(64 * W), lds, st, P);
+  }
   if (ev_end) hipEventRecord(ev_end, st);
   h->epoch += 1;
   h->ticket_base += (unsigned)(P.n_items + grid);

@@ -211,7 +211,7 @@ int lmdg_solve(lmdg_t* h, int scheme, int mode, double tol, int restart, int max
  * span of the old corrections.  This counters the stagnation of restarted GMRES on
  * the reduced systems of small eps, whose spectra reach close to zero.
  *   k  0 (plain GMRES, the default) .. 250 - restart; a larger k is clamped in each
- *      solve to 250 - restart.  Memory: 2 k + 2 further vectors of the solve's length.
+ *      solve to 250 - restart.  Memory: 3 k + 2 further vectors of the solve's length.
  * Errors: INVALID_ARG (k < 0 or k > 249).
  */
 int lmdg_set_augment(lmdg_t* h, int k);

@@ -189,7 +189,8 @@ int lmdg_recover(lmdg_t* h, int scheme, int prec, const double* x, double* phi,
  * Solve K x = b with restarted GMRES(restart) from x0 (device, NULL = 0) until the
  * true FP64 relative residual ||b - K x|| / ||b|| <= tol, then recover the scalar
  * flux.  mode FP64: FP64 sweeps.  mode MIXED: an FP64 refinement loop around inner
- * GMRES solves that use FP32 sweeps; the FP64 operator defines the residual.
+ * GMRES solves that use FP32 sweeps; the FP64 operator defines the residual.  The
+ * restarts are augmented with earlier corrections when lmdg_set_augment set k > 0.
  *   x_out    device moment vector (solution of the reduced system)
  *   phi_out  device moment vector (scalar flux), NULL to skip
  *   info     host, filled also when NOT_CONVERGED is returned; with several

@@ -376,16 +376,15 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
             yo_g[u][f] = yo[f];
             zo_g[u][f] = zo[f];
           }
+          // sums over the four direction slots of the wave, four rows at a time: lane
+          // group g receives row m0 + g (no branch, so the steps of a group stay one
+          // scheduling region)
+          R om[NOUTP];
 #pragma unroll
-          for (int m = 0; m < NOUT; ++m) o[m] = quad_sum(act ? o[m] : R(0));
-          // the four 16-lane groups hold the same sums: group g stores rows g, g + 4, ...
-          // (no branch, so the steps of a group stay one scheduling region)
+          for (int m = 0; m < NOUTP; ++m) om[m] = (m < NOUT && act) ? o[m < NOUT ? m : 0] : R(0);
 #pragma unroll
           for (int m0 = 0; m0 < NOUTP; m0 += 4) {
-            R v = o[m0];
-#pragma unroll
-            for (int g = 1; g < 4; ++g)
-              if (m0 + g < NOUT) v = (lane >> 4) == g ? o[m0 + g] : v;
+            const R v = quad_sum4(om[m0], om[m0 + 1], om[m0 + 2], om[m0 + 3]);
             red[tt * red_tt + (wv * NOUTP + m0 + (lane >> 4)) * kRows + r] = v;
           }
         }

@@ -17,26 +17,29 @@ __device__ __forceinline__ double shr1(double v) {
   return __hiloint2double(hi, lo);
 }
 
-// Sum of the four lanes r, r+16, r+32, r+48 (same row, four direction slots),
-// returned to all four; the pairing order is fixed, so results are reproducible.
-__device__ __forceinline__ float quad_sum(float v) {
-  unsigned u = __float_as_uint(v);
-  auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
-  float s = __uint_as_float(a[0]) + __uint_as_float(a[1]);
-  unsigned us = __float_as_uint(s);
-  auto b = __builtin_amdgcn_permlane32_swap(us, us, false, false);
-  return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+// Sums over the four 16-lane groups (direction slots) of four values at once: lane
+// group g receives the sum of its g-th argument over the four groups.  A row swap of two
+// different values pairs rows 0,1 and 2,3 of both (no operand copies), a half-wave swap
+// then pairs the two halves; each sum is (r0 + r1) + (r2 + r3) over the row groups r.
+__device__ __forceinline__ float quad_sum4(float a, float b, float c, float d) {
+  auto ab = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  auto cd = __builtin_amdgcn_permlane16_swap(__float_as_uint(c), __float_as_uint(d), false, false);
+  const float sab = __uint_as_float(ab[0]) + __uint_as_float(ab[1]);  // rows: a01 b01 a23 b23
+  const float scd = __uint_as_float(cd[0]) + __uint_as_float(cd[1]);  // rows: c01 d01 c23 d23
+  auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(sab), __float_as_uint(scd), false, false);
+  return __uint_as_float(h[0]) + __uint_as_float(h[1]);
 }
-__device__ __forceinline__ double quad_sum(double v) {
-  unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
-  auto al = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-  auto ah = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-  double s = __hiloint2double((int)ah[0], (int)al[0]) + __hiloint2double((int)ah[1], (int)al[1]);
-  lo = (unsigned)__double2loint(s);
-  hi = (unsigned)__double2hiint(s);
-  auto bl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-  auto bh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-  return __hiloint2double((int)bh[0], (int)bl[0]) + __hiloint2double((int)bh[1], (int)bl[1]);
+__device__ __forceinline__ double pair_rows(double a, double b) {
+  // rows of the result: a0+a1, b0+b1, a2+a3, b2+b3
+  auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false, false);
+  auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false, false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ double quad_sum4(double a, double b, double c, double d) {
+  const double sab = pair_rows(a, b), scd = pair_rows(c, d);
+  auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(sab), (unsigned)__double2loint(scd), false, false);
+  auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(sab), (unsigned)__double2hiint(scd), false, false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
 }
 
 template <typename T>

@@ -467,7 +467,10 @@ int launch3_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipS
   P.nstrips = h->nstrips;
   P.dslots = h->dslots;
   const int W = h->waves;
-  constexpr size_t kLdsBudget = 144 * 1024;
+  // LDS per workgroup (gfx950 gives a workgroup up to 160 KB): FP64 sweeps take the
+  // widest chunks that fit one workgroup per compute unit; FP32 sweeps are held to 64 KB,
+  // so that two or three workgroups share a compute unit (measured faster, 128^3 S8)
+  constexpr size_t kLdsBudget = sizeof(R) == 8 ? 144 * 1024 : 64 * 1024;
   int cw = 16;
   const int maxc = W > 4 ? 1 : kMAXC3;
   while (cw > kStepGroup3 && (kRows * cw > maxc * 64 * W || lds_bytes3<R, S>(cw, W, h->dslots) > kLdsBudget))

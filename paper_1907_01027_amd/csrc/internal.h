@@ -155,17 +155,19 @@ namespace lmdg {
 constexpr int kScratchVecs = 4;
 
 // Slices of the sweep partials per right-hand side, each [NOUT][n_cells]: FP64 2D sweeps
-// with up to four waves per quadrant and at most one work item (quadrant, strip, source)
-// per compute unit write one slice per (quadrant, wave); other 2D sweeps one per
-// quadrant, 3D sweeps one per octant.  The sweep launch and the kernels that read the
-// partials take the same decision from the handle's current state.
+// with at most one work item (quadrant, strip, source) per compute unit and at most 24
+// per-wave values per cell and quadrant (waves x NOUT; S8 RLMDG 18, S12 LMDG 18) write
+// one slice per (quadrant, wave), measured faster there; other 2D sweeps (S16 RLMDG 54
+// measured slower) one per quadrant, 3D sweeps one per octant.  The sweep launch and the
+// kernels that read the partials take the same decision from the handle's current state.
 inline int part_slices_max(const lmdg_handle* h) {
   if (h->dim == 3) return 8;
-  return h->waves <= 4 ? 4 * h->waves : 4;
+  return 4 * h->waves;
 }
-inline int part_slices(const lmdg_handle* h, int prec) {
+inline int part_slices(const lmdg_handle* h, int scheme, int prec) {
   if (h->dim == 3) return 8;
-  const bool direct = h->waves <= 4 && prec == LMDG_PREC_FP64 && 4LL * h->nstrips * h->n_rhs <= h->n_cu;
+  const int nout = scheme == LMDG_SCHEME_STD ? 4 : (scheme == LMDG_SCHEME_LMDG ? 3 : 6);
+  const bool direct = prec == LMDG_PREC_FP64 && 4LL * h->nstrips * h->n_rhs <= h->n_cu && h->waves * nout <= 24;
   return direct ? 4 * h->waves : 4;
 }
 

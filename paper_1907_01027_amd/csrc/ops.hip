@@ -384,10 +384,10 @@ void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double
   const int nx = (int)h->n[0], ny = (int)h->n[1];
   if (scheme == LMDG_SCHEME_STD) {
     if (prec == LMDG_PREC_FP64)
-      hipLaunchKernelGGL(combine_std_kernel<double>, dim3(g), dim3(kBlock), 0, st, mode, nr, part_slices(h, prec), nc, x,
+      hipLaunchKernelGGL(combine_std_kernel<double>, dim3(g), dim3(kBlock), 0, st, mode, nr, part_slices(h, scheme, prec), nc, x,
                          (const double*)h->ws.part, out);
     else
-      hipLaunchKernelGGL(combine_std_kernel<float>, dim3(g), dim3(kBlock), 0, st, mode, nr, part_slices(h, prec), nc, x,
+      hipLaunchKernelGGL(combine_std_kernel<float>, dim3(g), dim3(kBlock), 0, st, mode, nr, part_slices(h, scheme, prec), nc, x,
                          (const float*)h->ws.part, out);
     return;
   }
@@ -399,7 +399,7 @@ void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double
     qm.ay[q] = h->qay[q];
   }
 #define LMDG_COMBINE(R, RLM)                                                                        \
-  hipLaunchKernelGGL((combine_lm_kernel<R, RLM>), dim3(g), dim3(kBlock), 0, st, mode, nr, part_slices(h, prec), nx, ny, hx, hy, \
+  hipLaunchKernelGGL((combine_lm_kernel<R, RLM>), dim3(g), dim3(kBlock), 0, st, mode, nr, part_slices(h, scheme, prec), nx, ny, hx, hy, \
                      h->cplus[0], h->cminus[0], h->cplus[1], h->cminus[1], qm, x,                    \
                      (const R*)h->ws.part, h->d_sigtA, h->d_scatA, h->d_absA, out)
   const bool rlm = scheme == LMDG_SCHEME_RLMDG;
@@ -421,10 +421,10 @@ void launch_sum_quadrants(lmdg_handle* h, int scheme, int prec, double* out, hip
   const int g = std::min(grid_for(h->ncell * h->n_rhs), 4096);
   if (prec == LMDG_PREC_FP64)
     hipLaunchKernelGGL(sum_quadrants_kernel<double>, dim3(g), dim3(kBlock), 0, st, nout, nout_abi, h->n_rhs,
-                       part_slices(h, prec), h->ncell, (const double*)h->ws.part, out);
+                       part_slices(h, scheme, prec), h->ncell, (const double*)h->ws.part, out);
   else
     hipLaunchKernelGGL(sum_quadrants_kernel<float>, dim3(g), dim3(kBlock), 0, st, nout, nout_abi, h->n_rhs,
-                       part_slices(h, prec), h->ncell, (const float*)h->ws.part, out);
+                       part_slices(h, scheme, prec), h->ncell, (const float*)h->ws.part, out);
 }
 
 void launch_b11(lmdg_handle* h, const double* x, double* y, hipStream_t st) {

@@ -690,7 +690,7 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   constexpr size_t kLdsBudget = 144 * 1024;
   int cw = 16;
   const int maxc = W > 4 ? 1 : SrcTraits<S>::MAXC;
-  const bool direct = part_slices(h, sizeof(R) == 8 ? LMDG_PREC_FP64 : LMDG_PREC_FP32) > 4;
+  const bool direct = part_slices(h, S, sizeof(R) == 8 ? LMDG_PREC_FP64 : LMDG_PREC_FP32) > 4;
   while (cw > step_group<R>() &&
          (kRows * cw > maxc * 64 * W || lds_bytes<R, S>(cw, W, h->dslots, direct) > kLdsBudget))
     cw >>= 1;
@@ -742,8 +742,10 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
     h->ev_used += 2;
   }
   if constexpr (sizeof(R) == 8) {
-    if (direct) {  // only with up to four waves
+    if (direct && W <= 4) {
       hipLaunchKernelGGL((sweep2d_kernel<R, S, 4, true>), dim3(grid), dim3(64 * W), lds, st, P);
+    } else if (direct) {
+      hipLaunchKernelGGL((sweep2d_kernel<R, S, kMaxWaves, true>), dim3(grid), dim3(64 * W), lds, st, P);
     } else if (W <= 4) {
       hipLaunchKernelGGL((sweep2d_kernel<R, S, 4, false>), dim3(grid), dim3(64 * W), lds, st, P);
     } else {

@@ -169,7 +169,8 @@ def _apply_rate(torch, lmdg, h, scheme, prec, x, y, ncell, ndir, n_rhs=1, reps=5
 def extra_measurements(torch, lmdg, WORKLOADS, materials):
     """Secondary figures: operator throughput on the other 2D workloads (FP64 and FP32
     sweeps), eight sources swept together, the 512x512 S12 detector gradients (adjoint
-    solves, FP64 vs mixed), FP64 vs mixed solves of the 20x20 S4 workload to 1e-8 and
+    solves, FP64 vs mixed), a 1024-cell slab (operator rates and solves), FP64 vs mixed
+    solves of the 20x20 S4 workload to 1e-8 and
     1e-10, and the 128^3 3D workload with eight sources (operator throughput and solves
     to 1e-8, FP64 vs mixed)."""
     from paper_1907_01027_amd.adjoint import box_detector_moments
@@ -240,6 +241,37 @@ def extra_measurements(torch, lmdg, WORKLOADS, materials):
     s.close()
     del g64
     _progress("512^2 adjoint gradients done")
+    # slab geometry (a handle with dim 1): 1024 cells of [0, pi], 32-point Gauss rule,
+    # eps = sigma_s = sigma_a = 1, q = (4/3) sin x (cell averages), vacuum inflow, RLMDG
+    ncs = 1024
+    mu, gw = np.polynomial.legendre.leggauss(32)
+    s = lmdg.Solver((ncs,), (np.pi,), mu[:, None], gw / 2.0)
+    edges = np.linspace(0.0, np.pi, ncs + 1)
+    qs = 4.0 / 3.0 * (np.cos(edges[:-1]) - np.cos(edges[1:])) / (edges[1] - edges[0])
+    one = np.ones(ncs)
+    lmdg.lmdg_set_materials(s.h, T(one), T(one), T(one), T(qs))
+    x = T(np.random.default_rng(4).normal(size=4 * ncs))
+    y = torch.empty_like(x)
+    slab = {p: _apply_rate(torch, lmdg, s.h, "rlmdg", p, x, y, ncs, 32) for p in ("fp64", "fp32")}
+    phi64 = None
+    for mode in ("fp64", "mixed"):
+        xs = torch.zeros(4 * ncs, dtype=torch.float64, device=dev)
+        phi = torch.zeros_like(xs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = lmdg.lmdg_solve(s.h, "rlmdg", mode, 1e-8, 30, 2000, xs, phi, raise_on_nonconvergence=False)
+        torch.cuda.synchronize()
+        e = {"wall_ms": 1e3 * (time.perf_counter() - t0), "iterations": info["iterations"],
+             "converged": info["converged"], "rel_residual": info["rel_residual"]}
+        rows = phi.reshape(4, ncs)[:2]  # the slab moments (1, xi)
+        if mode == "fp64":
+            phi64 = rows.clone()
+        else:
+            e["phi_rel_diff_vs_fp64"] = float((rows - phi64).abs().max() / phi64.abs().max())
+        slab[f"solve_{mode}_tol1e-8"] = e
+    res["slab_1024_G32_rlmdg"] = slab
+    s.close()
+    _progress("slab solves done")
     # 20x20, S4, eps = 1: solve times to 1e-8 and 1e-10, FP64 vs mixed
     wl = WORKLOADS[1]
     ss, sa, ep, q = materials(1)

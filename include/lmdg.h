@@ -116,8 +116,16 @@ int lmdg_quadrature_level_symmetric(int dim, int order, int capacity, int* n_dir
  * satisfy eq-polyquad (i)-(iii) to 1e-12, have positive weights and no zero
  * component (the upwind direction along every axis must be defined), and at most 36
  * directions per quadrant / octant (2D S16 has 36, 3D S8 has 10).
+ * dim 1 (slab geometry, eq-1d): n[0] cells of [0, length[0]], omega = the n_dir values
+ * mu (nonzero, sum w = 1, sum w mu = 0, sum w mu^2 = 1/3, e.g. a Gauss rule with weights
+ * halved, at most 36 per sign of mu).  The handle is the 2D problem on n[0] x 1 cells of
+ * [0, length[0]] x [0, 1] with directions (mu, 0): no y face carries flux, so its 1 and
+ * xi moments are the slab scheme's.  Vectors use the 2D layout (4 moments per cell);
+ * rows 0 and 1 are the slab moments, rows 2 and 3 (eta, xi eta) carry no slab
+ * quantity: zero for STD and LMDG, decoupled values of the transverse reconstruction
+ * for RLMDG.  lmdg_adjoint_solve returns UNSUPPORTED on slab handles.
  * Errors: INVALID_ARG (NULL pointers, sizes < 1, quadrature violations),
- *         UNSUPPORTED (dim not 2 or 3), HIP_ERROR (allocation).
+ *         UNSUPPORTED (dim not 1, 2 or 3), HIP_ERROR (allocation).
  */
 int lmdg_create(int dim, const int64_t* n, const double* length, int n_dir,
                 const double* omega, const double* w, lmdg_t** out);
@@ -241,7 +249,7 @@ int lmdg_set_augment(lmdg_t* h, int k);
  * quadrant's adjoint-type fluxes with two restricted sweeps (the handle keeps
  * 2 x slots x n_cells doubles for LMDG, 8 x slots x n_cells for STD, slots = the
  * padded directions per quadrant).
- * Errors: UNSUPPORTED (RLMDG: its adjoint is Petrov-Galerkin; 3D meshes), INVALID_ARG (NULL
+ * Errors: UNSUPPORTED (RLMDG: its adjoint is Petrov-Galerkin; 3D meshes; slab handles), INVALID_ARG (NULL
  * pointers, bad solver arguments, quadrature without central symmetry, more than
  * one right-hand side on the handle),
  * NOT_CONVERGED (either solve, or the conjugate gradients of B_11 that give the

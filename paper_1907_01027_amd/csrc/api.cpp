@@ -242,12 +242,12 @@ static int ensure_rhs_capacity(lmdg_t* h, int n_rhs) {
   return rc;
 }
 
-int lmdg_create(int dim, const int64_t* n, const double* length, int n_dir, const double* omega,
-                const double* w, lmdg_t** out) {
+// Body of lmdg_create for 2D and 3D handles.  slab: a 2D handle standing for the slab
+// problem (one row of cells, every Omega_y = 0), where the y components are exempt from
+// the nonzero-component and second-moment checks.
+static int create_impl(int dim, const int64_t* n, const double* length, int n_dir, const double* omega,
+                       const double* w, lmdg_t** out, bool slab) {
   using namespace lmdg;
-  if (!out || !n || !length || !omega || !w) return LMDG_INVALID_ARG;
-  *out = nullptr;
-  if (dim != 2 && dim != 3) return LMDG_UNSUPPORTED;
   long long ncell = 1;
   for (int a = 0; a < dim; ++a) {
     if (n[a] < 1 || n[a] > (1 << 20) || !(length[a] > 0) || !std::isfinite(length[a])) return LMDG_INVALID_ARG;
@@ -259,7 +259,8 @@ int lmdg_create(int dim, const int64_t* n, const double* length, int n_dir, cons
   for (int l = 0; l < n_dir; ++l) {
     if (!(w[l] > 0) || !std::isfinite(w[l])) return LMDG_INVALID_ARG;
     for (int a = 0; a < dim; ++a)
-      if (!std::isfinite(omega[dim * l + a]) || omega[dim * l + a] == 0.0) return LMDG_INVALID_ARG;
+      if (!std::isfinite(omega[dim * l + a]) || (omega[dim * l + a] == 0.0 && !(slab && a == 1)))
+        return LMDG_INVALID_ARG;
     s0 += w[l];
     for (int a = 0; a < dim; ++a) {
       s1[a] += w[l] * omega[dim * l + a];
@@ -271,11 +272,12 @@ int lmdg_create(int dim, const int64_t* n, const double* length, int n_dir, cons
   for (int a = 0; a < dim; ++a) {
     if (std::fabs(s1[a]) > tq) return LMDG_INVALID_ARG;
     for (int b = 0; b < dim; ++b)
-      if (std::fabs(s2[a][b] - (a == b ? 1.0 / 3.0 : 0.0)) > tq) return LMDG_INVALID_ARG;
+      if (std::fabs(s2[a][b] - (a == b && !(slab && a == 1) ? 1.0 / 3.0 : 0.0)) > tq) return LMDG_INVALID_ARG;
   }
   lmdg_handle* h = new (std::nothrow) lmdg_handle();
   if (!h) return LMDG_HIP_ERROR;
   h->dim = dim;
+  h->slab = slab;
   h->np = dim == 2 ? 4 : 8;
   h->noct = 1 << dim;
   h->area = 1.0;
@@ -400,6 +402,30 @@ int lmdg_create(int dim, const int64_t* n, const double* length, int n_dir, cons
   }
   *out = h;
   return LMDG_OK;
+}
+
+int lmdg_create(int dim, const int64_t* n, const double* length, int n_dir, const double* omega,
+                const double* w, lmdg_t** out) {
+  if (!out || !n || !length || !omega || !w) return LMDG_INVALID_ARG;
+  *out = nullptr;
+  if (dim == 2 || dim == 3) return create_impl(dim, n, length, n_dir, omega, w, out, false);
+  if (dim != 1) return LMDG_UNSUPPORTED;
+  // Slab geometry (eq-1d): the 2D problem on n[0] x 1 cells of [0, length[0]] x [0, 1]
+  // with directions (mu, 0).  With Omega_y = 0 no y face carries flux, so the 1 and xi
+  // moments of its solution are those of the slab scheme; the 1D rule must satisfy
+  // sum w = 1, sum w mu = 0, sum w mu^2 = 1/3 (the 2D second-moment check is replaced).
+  if (n_dir < 1 || n_dir > (1 << 20)) return LMDG_INVALID_ARG;
+  std::vector<double> om2(2 * (size_t)n_dir);
+  for (int l = 0; l < n_dir; ++l) {
+    om2[2 * l] = omega[l];
+    om2[2 * l + 1] = 0.0;
+  }
+  double m2 = 0;
+  for (int l = 0; l < n_dir; ++l) m2 += w[l] * omega[l] * omega[l];
+  if (!(std::fabs(m2 - 1.0 / 3.0) <= 1e-12)) return LMDG_INVALID_ARG;
+  const int64_t n2[2] = {n[0], 1};
+  const double len2[2] = {length[0], 1.0};
+  return create_impl(2, n2, len2, n_dir, om2.data(), w, out, true);
 }
 
 void lmdg_destroy(lmdg_t* h) {
@@ -1051,6 +1077,7 @@ int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, doubl
   if (scheme == LMDG_SCHEME_RLMDG)
     return set_error(h, LMDG_UNSUPPORTED, "the adjoint covers the Galerkin schemes (standard, LMDG)");
   if (h->dim != 2) return set_error(h, LMDG_UNSUPPORTED, "the adjoint solve is two-dimensional");
+  if (h->slab) return set_error(h, LMDG_UNSUPPORTED, "adjoint of a slab handle");
   if (!det || !g_sigma_s || !g_sigma_a || !g_q || !J_out || !(tol > 0) || restart < 1 || restart > 250 ||
       max_iter < 1 || (mode != LMDG_MODE_FP64 && mode != LMDG_MODE_MIXED))
     return set_error(h, LMDG_INVALID_ARG, "bad adjoint arguments");

@@ -97,6 +97,7 @@ struct Workspace {
 
 struct lmdg_handle {
   int dim = 2;
+  bool slab = false;               // 2D handle standing for a slab problem (lmdg_create with dim 1)
   int64_t n[3] = {0, 0, 1};
   double len[3] = {1, 1, 1}, h[3] = {1, 1, 1}, area = 1;   // area: cell measure (|K| in 2D, V in 3D)
   long long ncell = 0;

@@ -1,0 +1,134 @@
+"""Slab geometry (eq-1d) through the C ABI: parity with the oracle's 1D schemes.
+
+A slab handle (lmdg_create with dim 1) is the 2D problem on one row of cells with
+directions (mu, 0): no y face carries flux, so the 1 and xi moments (rows 0 and 1 of
+the 2D moment layout) are those of the slab scheme, and the oracle assembles the slab
+scheme directly on a 1D mesh.  Bars as in the 2D parity tests: 1e-12 (FP64 sweeps) and
+2e-5 (FP32) for operator applications and right-hand sides, 1e-9 for solves at tol 1e-12.
+Materials: seeded per-cell sigma_s, sigma_a, eps and q; 16-point Gauss rule in mu.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import rel_err
+from oracle import schemes as S
+from oracle.dg import Mesh
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1907_01027_amd import lmdg  # noqa: E402
+
+DEV = torch.device("cuda")
+MU, GW = np.polynomial.legendre.leggauss(16)
+OMEGA = MU[:, None]
+W = GW / 2.0
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def N(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+class Slab:
+    def __init__(self, n, eps_scale, seed, length=2.0):
+        rng = np.random.default_rng(seed)
+        self.n, self.length = n, length
+        self.ss = rng.uniform(0.5, 2.0, n)
+        self.sa = rng.uniform(0.5, 2.0, n)
+        self.eps = eps_scale * rng.uniform(0.5, 1.5, n)
+        self.q = rng.uniform(0.0, 1.0, n)
+        self.prob = S.Problem(Mesh((n,), (length,)), OMEGA, W, self.ss, self.sa, self.eps, q=self.q)
+
+    def solver(self):
+        s = lmdg.Solver((self.n,), (self.length,), OMEGA, W)
+        lmdg.lmdg_set_materials(s.h, T(self.ss), T(self.sa), T(self.eps), T(self.q))
+        torch.cuda.synchronize()
+        return s
+
+
+def oracle_apply(slab, scheme, x2):
+    """K x of the slab scheme; x2 = (n, 2) moments (cell-major) -> (n, 2)."""
+    n = slab.n
+    if scheme == "std":
+        return S.StdReduced(slab.prob).apply(x2.ravel()).reshape(n, 2)
+    red = S.LowMemoryReduced(slab.prob, scheme == "rlmdg")
+    y = red.apply(np.concatenate([x2[:, 0], x2[:, 1]]))
+    return np.stack([y[:n], y[n:]], axis=1)
+
+
+def oracle_rhs(slab, scheme):
+    n = slab.n
+    if scheme == "std":
+        return S.StdReduced(slab.prob).rhs().reshape(n, 2)
+    b = S.LowMemoryReduced(slab.prob, scheme == "rlmdg").rhs()
+    return np.stack([b[:n], b[n:]], axis=1)
+
+
+def rows01(v, n):
+    """Rows (1, xi) of a 2D moment-major vector of a slab handle, as (n, 2)."""
+    return v.reshape(4, n)[:2].T
+
+
+@pytest.mark.parametrize("n", [1, 7, 40, 129])
+@pytest.mark.parametrize("scheme", ["std", "lmdg", "rlmdg"])
+def test_slab_apply_and_rhs(scheme, n):
+    print(f"case slab apply {scheme} n={n}", flush=True)
+    slab = Slab(n, 0.05, seed=n)
+    s = slab.solver()
+    x2 = np.random.default_rng(1).normal(size=(n, 2))
+    x = np.zeros((4, n))
+    x[0], x[1] = x2[:, 0], x2[:, 1]
+    ref_y = oracle_apply(slab, scheme, x2)
+    ref_b = oracle_rhs(slab, scheme)
+    y = torch.zeros(4 * n, dtype=torch.float64, device=DEV)
+    b = torch.zeros_like(y)
+    lmdg.lmdg_apply(s.h, scheme, "fp64", T(x.ravel()), y)
+    lmdg.lmdg_rhs(s.h, scheme, "fp64", b)
+    assert rel_err(rows01(N(y), n), ref_y) < 1e-12
+    assert rel_err(rows01(N(b), n), ref_b) < 1e-12
+    if scheme != "rlmdg":
+        # no transverse reconstruction: the eta and xi-eta rows stay zero
+        assert np.abs(N(y).reshape(4, n)[2:]).max() == 0.0
+    lmdg.lmdg_apply(s.h, scheme, "fp32", T(x.ravel()), y)
+    assert rel_err(rows01(N(y), n), ref_y) < 2e-5
+    s.close()
+
+
+@pytest.mark.parametrize("scheme", ["std", "lmdg", "rlmdg"])
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_slab_solve_against_direct(scheme, mode):
+    print(f"case slab solve {scheme} {mode}", flush=True)
+    n = 60
+    slab = Slab(n, 0.1, seed=3)
+    s = slab.solver()
+    x = torch.zeros(4 * n, dtype=torch.float64, device=DEV)
+    phi = torch.zeros_like(x)
+    info = lmdg.lmdg_solve(s.h, scheme, mode, 1e-12, 40, 4000, x, phi)
+    assert info["converged"] == 1
+    if scheme == "std":
+        ref = S.scalar_flux_std(slab.prob, S.solve_std_direct(slab.prob))
+    elif scheme == "lmdg":
+        ref = S.scalar_flux_lm(slab.prob, *S.solve_lmdg_direct(slab.prob))
+    else:
+        ref = S.scalar_flux_lm(slab.prob, *S.solve_rlmdg_direct(slab.prob))
+    assert rel_err(rows01(N(phi), n), ref) < 1e-9
+    s.close()
+
+
+def test_slab_adjoint_unsupported():
+    slab = Slab(8, 0.1, seed=4)
+    s = slab.solver()
+    det = torch.zeros(4 * 8, dtype=torch.float64, device=DEV)
+    g = [torch.zeros(8, dtype=torch.float64, device=DEV) for _ in range(3)]
+    with pytest.raises(lmdg.LmdgError) as e:
+        lmdg.lmdg_adjoint_solve(s.h, "lmdg", "fp64", det, 1e-10, 20, 100, *g)
+    assert e.value.status == lmdg.LMDG_UNSUPPORTED
+    s.close()

@@ -63,6 +63,24 @@ def test_create_rejects_bad_input():
         assert e.value.status == lmdg.LMDG_INVALID_ARG
 
 
+def test_create_rejects_bad_slab_quadrature():
+    """Slab handles (dim 1) need a rule with sum w = 1, sum w mu = 0, sum w mu^2 = 1/3."""
+    lmdg = _lib()
+    mu, gw = np.polynomial.legendre.leggauss(8)
+    w = gw / 2.0
+    bad = [
+        ((4,), (1.0,), mu[:, None], w * 1.01),               # weights do not sum to 1
+        ((4,), (1.0,), 0.9 * mu[:, None], w),                # second moment wrong
+        ((4,), (1.0,), np.abs(mu)[:, None], w),              # first moment not zero
+        ((4,), (1.0,), np.where(mu > 0, mu, 0.0)[:, None], w),  # zero direction
+        ((0,), (1.0,), mu[:, None], w),                      # empty mesh
+    ]
+    for n, length, o, ww in bad:
+        with pytest.raises(lmdg.LmdgError) as e:
+            lmdg.lmdg_create(n, length, o, ww)
+        assert e.value.status == lmdg.LMDG_INVALID_ARG
+
+
 def test_status_strings():
     lmdg = _lib()
     lib = lmdg.library()

@@ -350,7 +350,7 @@ def extra_measurements(torch, lmdg, WORKLOADS, materials):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); this build has no multi-GPU path. "
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the library has no multi-GPU path. "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:

@@ -163,7 +163,7 @@ constexpr int kScratchVecs = 4;
 // kernels that read the partials take the same decision from the handle's current state.
 inline int part_slices_max(const lmdg_handle* h) {
   if (h->dim == 3) return 8;
-  return 4 * h->waves;
+  return h->waves * 3 <= 24 ? 4 * h->waves : 4;  // 3 = the fewest outputs of a scheme (LMDG)
 }
 inline int part_slices(const lmdg_handle* h, int scheme, int prec) {
   if (h->dim == 3) return 8;

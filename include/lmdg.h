@@ -13,6 +13,8 @@
  *                                                            (Sec. 3.3, eq-rlmdg-vari)
  * Each is solved through the paper's dimension-reduced system with a Krylov method
  * (GMRES here); the operator of that system is applied with transport sweeps.
+ * Slab geometry (Sec. 4.1, eq-1d) is a 2D handle with one row of cells and directions
+ * (mu, 0), created with dim 1 (see lmdg_create).
  *
  * Conventions shared by every entry point
  * ---------------------------------------

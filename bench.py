@@ -387,6 +387,7 @@ def main():
         lmdg.lmdg_apply(h, scheme, "fp64", x, y)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    lmdg.lmdg_synchronize(h)  # raises if any sweep wait of the timed launches gave up
     k_ms, k_n = lmdg.lmdg_sweep_kernel_time(h)
     lmdg.lmdg_profile(h, False)
     ms_step = 1e3 * elapsed / args.steps

@@ -41,10 +41,19 @@
  * - `stream` is a hipStream_t (NULL = the default stream).  All device work of a
  *   call is enqueued on it; calls that report iteration counts or residuals
  *   synchronise it before returning.
+ * - lmdg_sweep, lmdg_apply, lmdg_rhs and lmdg_recover only enqueue work and return at
+ *   once.  The sweeps hand data between workgroups through progress words, and every
+ *   wait for one is bounded: a wait that gives up (a fault of the device or of the
+ *   library, never of the caller's data) sets a sticky flag in the handle and the
+ *   kernel still finishes, with wrong numbers.  The flag is read and cleared by the
+ *   next synchronising call on the handle (lmdg_synchronize, lmdg_solve,
+ *   lmdg_adjoint_solve), which then returns LMDG_HIP_ERROR; callers of the
+ *   asynchronous functions check their results with lmdg_synchronize.
  * - A handle is not re-entrant: calls on one handle must not overlap.
- * - Supported: dim = 2 (STD, LMDG, RLMDG) and dim = 3 (LMDG, RLMDG), vacuum inflow
- *   (alpha = 0), per-cell constant cross sections, eps and sources.  Anything else
- *   returns LMDG_UNSUPPORTED.
+ * - Supported: dim = 2 (STD, LMDG, RLMDG) with prescribed inflow and sources given by
+ *   their cell moments (isotropic or per direction); dim 3 (LMDG, RLMDG) with vacuum
+ *   inflow and per-cell constant sources; per-cell constant cross sections and eps.
+ *   Anything else returns LMDG_UNSUPPORTED.
  */
 #ifndef LMDG_H
 #define LMDG_H
@@ -135,18 +144,47 @@ int lmdg_create(int dim, const int64_t* n, const double* length, int n_dir,
 void lmdg_destroy(lmdg_t* h);
 
 /*
- * Cross sections and source (device arrays, n_cells each, copied into the handle):
+ * Cross sections, source and inflow data (device arrays, copied into the handle):
  * sigma_s >= 0, sigma_a >= 0, eps > 0 per cell (eq-main; a per-cell eps describes a
- * multiscale medium), q = per-cell constant source.  sigma_a = 0 is accepted;
- * the paper's analysis assumes sigma_a >= delta_a > 0, and without absorption the
- * reduced systems can be arbitrarily ill-conditioned.  alpha must be NULL (vacuum
- * inflow).
- * Errors: INVALID_ARG (NULL, negative or non-finite values, eps <= 0),
- *         UNSUPPORTED (alpha != NULL).
+ * multiscale medium), q = per-cell constant source (n_cells each).  sigma_a = 0 is
+ * accepted; the paper's analysis assumes sigma_a >= delta_a > 0, and without
+ * absorption the reduced systems can be arbitrarily ill-conditioned.
+ * alpha: the inflow boundary values Psi = alpha on Gamma^- of eq-main, NULL for vacuum.
+ *   2D (device, n_dir x (n_1 + n_0) x 3 doubles): for direction l (the caller's index)
+ *   entries f = 0..n_1-1 describe the x-inflow face of mesh row f (x = 0 if
+ *   Omega_x > 0, x = length_0 otherwise), entries f = n_1 + i the y-inflow face of
+ *   column i (y = 0 if Omega_y > 0, y = length_1 otherwise).  Each entry holds
+ *   (a0, a1, m): a0 = (1/|F|) int_F alpha, a1 = (3/|F|) int_F alpha t with t in
+ *   [-1, 1] the cell coordinate along the face (eta on x faces, xi on y faces), so that
+ *   a0 + a1 t is the L2 projection onto the face's linear functions, which is all the
+ *   Q^1 test functions see of alpha (the boundary term of Q in eq-Ljk), and m = alpha
+ *   at the face midpoint, the upwind value the reconstruction of Sec. 3.3.1 uses in the
+ *   inflow cell (RLMDG).  Slab handles (dim 1): n_dir doubles, alpha of direction l at
+ *   its inflow end (x = 0 for mu > 0, x = length_0 otherwise).  3D: must be NULL.
+ *   Faces on the outflow side of a direction are never read.
+ * The call replaces any sources set before (one right-hand side, q).
+ * Errors: INVALID_ARG (NULL, negative values, eps <= 0), NONFINITE,
+ *         UNSUPPORTED (alpha on a 3D handle).
  */
 int lmdg_set_materials(lmdg_t* h, const double* sigma_s, const double* sigma_a,
                        const double* eps, const double* q, const double* alpha,
                        void* stream);
+
+/*
+ * Replace the handle's source by one given through its cell moments (2D and slab
+ * handles; eq-Ljk: Q_{l,K}(v) = eps int_K q_l v):
+ *   per_direction 0: qm[r * n_cells + p] = (1/|K_p|) int_{K_p} q b_r dx, r = 0..3, an
+ *                    isotropic source (the four Legendre moments of each cell);
+ *   per_direction 1: qm[(l * 4 + r) * n_cells + p], the same for the source q_l of
+ *                    direction l (the caller's index), e.g. a manufactured source.
+ * Device array.  The inflow data of lmdg_set_materials stay; the handle has one
+ * right-hand side afterwards.  Slope moments of the source enter the low-memory
+ * schemes through the isotropic slope rows of the reduced right-hand side (Step 1 of
+ * Sec. 3.2), direction-dependent constant moments through the source sweep.
+ * Errors: INVALID_ARG (materials not set, NULL, per_direction not 0 or 1), NONFINITE,
+ *         UNSUPPORTED (3D handle).
+ */
+int lmdg_set_source_moments(lmdg_t* h, int per_direction, const double* qm, void* stream);
 
 /*
  * n_rhs per-cell constant sources q (device, n_rhs * n_cells doubles, right-hand
@@ -260,6 +298,34 @@ int lmdg_set_augment(lmdg_t* h, int k);
 int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, double tol,
                        int restart, int max_iter, double* g_sigma_s, double* g_sigma_a,
                        double* g_q, double* J_out, lmdg_info* info, void* stream);
+
+/*
+ * Device memory of the handle (host outputs, bytes): *held = what it owns now (mesh
+ * and direction tables, materials and source data, sweep workspaces for its current
+ * number of right-hand sides, Krylov and adjoint buffers of earlier solves);
+ * *solve = what an lmdg_solve with this restart (and the augmentation set by
+ * lmdg_set_augment) would allocate on top of that (0 once a solve of that size ran).
+ * Errors: INVALID_ARG (NULL, restart < 1 or > 250).
+ */
+int lmdg_workspace_bytes(const lmdg_t* h, int restart, int64_t* held, int64_t* solve);
+
+/*
+ * Wait for all work of the handle on `stream` and report whether any sweep launched
+ * since the last synchronising call had a wait that gave up (LMDG_HIP_ERROR; the flag
+ * is cleared).  LMDG_OK means every result enqueued so far is complete and valid.
+ */
+int lmdg_synchronize(lmdg_t* h, void* stream);
+
+/*
+ * Bounded waits of the sweeps, for tests of the failure path: every wait for a
+ * progress word polls it at most `spins` times (default 2^25, about a second) before
+ * it gives up; unreachable = 1 makes every wait target a value no producer writes, so
+ * every wait that is reached gives up after `spins` polls while all kernels still run
+ * to completion (the numbers are then wrong and the next synchronising call reports
+ * LMDG_HIP_ERROR).  unreachable = 0 restores normal waits.
+ * Errors: INVALID_ARG (spins < 1, unreachable not 0 or 1).
+ */
+int lmdg_set_wait_limit(lmdg_t* h, long long spins, int unreachable);
 
 /*
  * Kernel timing for measurement: while enabled, every sweep-kernel launch of this

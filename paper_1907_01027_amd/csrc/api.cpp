@@ -433,7 +433,8 @@ void lmdg_destroy(lmdg_t* h) {
   hipDeviceSynchronize();
   void* ptrs[] = {h->d_dirs, h->d_sigtA, h->d_scatA, h->d_absA, h->d_qA, h->ws.part, h->ws.edge, h->ws.zbuf,
                   h->ws.prog, h->ws.ticket, h->ws.err, h->ws.vec, h->d_krylov, h->d_small,
-                  h->d_epsA, h->d_adjpairs, h->d_psi_f, h->d_psi_a, h->d_cvec};
+                  h->d_epsA, h->d_adjpairs, h->d_psi_f, h->d_psi_a, h->d_cvec, h->d_qS, h->d_qdir,
+                  h->d_alpha, h->d_sq1, h->d_sqa};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (h->h_small) hipHostFree(h->h_small);
@@ -441,11 +442,82 @@ void lmdg_destroy(lmdg_t* h) {
   delete h;
 }
 
+// Free the handle's source data beyond per-cell constants (moments, direction-dependent
+// sources and their right-hand-side corrections); keep_alpha keeps the inflow data.
+static void clear_source_data(lmdg_t* h, bool keep_alpha) {
+  double** ptrs[] = {&h->d_qS, &h->d_qdir, &h->d_sq1, &h->d_alpha, &h->d_sqa};
+  for (int k = 0; k < 5; ++k) {
+    if (keep_alpha && k >= 3) break;
+    if (*ptrs[k]) hipFree(*ptrs[k]);
+    *ptrs[k] = nullptr;
+  }
+}
+
+static int upload(lmdg_t* h, double** dst, const std::vector<double>& v, hipStream_t st) {
+  int rc = check_hip(h, hipMalloc((void**)dst, v.size() * sizeof(double)), "hipMalloc source data");
+  if (rc == LMDG_OK)
+    rc = check_hip(h, hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, st),
+                   "write source data");
+  if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "write source data");
+  return rc;
+}
+
+// Inflow data (eq-main, Gamma^-) of a 2D or slab handle, read from the caller's device
+// array: 2D [n_dir][n_1 + n_0][3], slab [n_dir].  Stores the 2D layout and the part of
+// the LMDG slope-row inflow terms that the ghost face averages do not carry: per
+// inflow face the boundary term -int_F alpha Omega.nu v of a slope test function v
+// (Q_alpha of eq-Ljk) with alpha = a0 + a1 t on the face (t the cell coordinate along
+// the face) is, for an x face, -Ox h_y a0 (xi row), |Ox| h_y a1 / 3 (eta row),
+// -Ox h_y a1 / 3 (xi eta row); the ghost trace a0 of the LMDG sweep gives the xi row.
+static int set_alpha(lmdg_t* h, const double* alpha, hipStream_t st) {
+  const int nx = (int)h->n[0], ny = (int)h->n[1], nf = nx + ny;
+  const long long nc = h->ncell;
+  const size_t nin = h->slab ? (size_t)h->ndir : (size_t)h->ndir * nf * 3;
+  std::vector<double> a(nin);
+  int rc = check_hip(h, hipMemcpyAsync(a.data(), alpha, nin * sizeof(double), hipMemcpyDeviceToHost, st),
+                     "read alpha");
+  if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "read alpha");
+  if (rc != LMDG_OK) return rc;
+  for (double v : a)
+    if (!std::isfinite(v)) return set_error(h, LMDG_NONFINITE, "non-finite inflow value");
+  std::vector<double> full((size_t)h->ndir * nf * 3, 0.0);
+  if (h->slab) {
+    // the x-inflow face of the single row carries the slab datum; y faces carry no flux
+    for (int l = 0; l < h->ndir; ++l) {
+      full[((size_t)l * nf) * 3 + 0] = a[l];
+      full[((size_t)l * nf) * 3 + 2] = a[l];
+    }
+  } else {
+    full = a;
+  }
+  std::vector<double> sqa(3 * (size_t)nc, 0.0);
+  const double hx = h->h[0], hy = h->h[1];
+  for (int l = 0; l < h->ndir; ++l) {
+    const double ox = h->omega[2 * l], oy = h->omega[2 * l + 1], w = h->w[l];
+    const int i0 = ox < 0 ? nx - 1 : 0, j0 = oy < 0 ? ny - 1 : 0;  // inflow column and row
+    for (int j = 0; j < ny; ++j) {
+      const double a1 = full[((size_t)l * nf + j) * 3 + 1];
+      const long long p = (long long)j * nx + i0;
+      sqa[nc + p] += w * std::fabs(ox) * hy * a1 / 3.0;
+      sqa[2 * nc + p] += -w * ox * hy * a1 / 3.0;
+    }
+    for (int i = 0; i < nx; ++i) {
+      const double b1 = full[((size_t)l * nf + ny + i) * 3 + 1];
+      const long long p = (long long)j0 * nx + i;
+      sqa[p] += w * std::fabs(oy) * hx * b1 / 3.0;
+      sqa[2 * nc + p] += -w * oy * hx * b1 / 3.0;
+    }
+  }
+  rc = upload(h, &h->d_alpha, full, st);
+  if (rc == LMDG_OK) rc = upload(h, &h->d_sqa, sqa, st);
+  return rc;
+}
+
 int lmdg_set_materials(lmdg_t* h, const double* sigma_s, const double* sigma_a, const double* eps,
                        const double* q, const double* alpha, void* stream) {
   if (!h) return LMDG_INVALID_ARG;
   if (!sigma_s || !sigma_a || !eps || !q) return set_error(h, LMDG_INVALID_ARG, "NULL material array");
-  if (alpha) return set_error(h, LMDG_UNSUPPORTED, "only vacuum inflow (alpha = NULL) is supported");
+  if (alpha && h->dim == 3) return set_error(h, LMDG_UNSUPPORTED, "inflow data on 3D meshes");
   hipStream_t st = (hipStream_t)stream;
   const long long nc = h->ncell;
   std::vector<double> ss(nc), sa(nc), ep(nc), qq(nc);
@@ -483,7 +555,51 @@ int lmdg_set_materials(lmdg_t* h, const double* sigma_s, const double* sigma_a, 
     h->have_mat = true;
     h->n_rhs = 1;
     h->h_eps = ep;
+    clear_source_data(h, false);
+    if (alpha) rc = set_alpha(h, alpha, st);
+    if (rc != LMDG_OK) clear_source_data(h, false);
   }
+  return rc;
+}
+
+int lmdg_set_source_moments(lmdg_t* h, int per_direction, const double* qm, void* stream) {
+  if (!h) return LMDG_INVALID_ARG;
+  if (!h->have_mat) return set_error(h, LMDG_INVALID_ARG, "materials not set");
+  if (!qm || (per_direction != 0 && per_direction != 1)) return set_error(h, LMDG_INVALID_ARG, "bad source moments");
+  if (h->dim != 2) return set_error(h, LMDG_UNSUPPORTED, "source moments on 3D meshes");
+  hipStream_t st = (hipStream_t)stream;
+  const long long nc = h->ncell;
+  const int nd = per_direction ? h->ndir : 1;
+  std::vector<double> m((size_t)nd * 4 * nc);
+  int rc = check_hip(h, hipMemcpyAsync(m.data(), qm, m.size() * sizeof(double), hipMemcpyDeviceToHost, st),
+                     "read source moments");
+  if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "read source moments");
+  if (rc != LMDG_OK) return rc;
+  for (size_t e = 0; e < m.size(); ++e) {
+    if (!std::isfinite(m[e])) return set_error(h, LMDG_NONFINITE, "non-finite source moment");
+    m[e] *= h->h_eps[e % nc] * h->area;  // eps int_K q b_r = eps |K| q_r
+  }
+  rc = ensure_rhs_capacity(h, 1);
+  if (rc != LMDG_OK) return rc;
+  clear_source_data(h, true);
+  h->n_rhs = 1;
+  std::vector<double> q0(nc, 0.0), sq1(3 * (size_t)nc, 0.0);
+  if (!per_direction) {
+    std::copy(m.begin(), m.begin() + nc, q0.begin());
+    std::copy(m.begin() + nc, m.end(), sq1.begin());
+    rc = upload(h, &h->d_qS, sq1, st);
+  } else {
+    // per-direction moments go to the sweep whole; the isotropic constant is zero
+    for (int l = 0; l < h->ndir; ++l)
+      for (size_t e = 0; e < 3 * (size_t)nc; ++e) sq1[e] += h->w[l] * m[((size_t)l * 4) * nc + nc + e];
+    rc = upload(h, &h->d_qdir, m, st);
+  }
+  if (rc == LMDG_OK) rc = upload(h, &h->d_sq1, sq1, st);
+  if (rc == LMDG_OK)
+    rc = check_hip(h, hipMemcpyAsync(h->d_qA, q0.data(), nc * sizeof(double), hipMemcpyHostToDevice, st),
+                   "write source");
+  if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "write source");
+  if (rc != LMDG_OK) clear_source_data(h, true);
   return rc;
 }
 
@@ -504,6 +620,7 @@ int lmdg_set_sources(lmdg_t* h, int n_rhs, const double* q, void* stream) {
   }
   rc = ensure_rhs_capacity(h, n_rhs);
   if (rc != LMDG_OK) return rc;
+  clear_source_data(h, true);
   rc = check_hip(h, hipMemcpyAsync(h->d_qA, qq.data(), qq.size() * sizeof(double), hipMemcpyHostToDevice, st),
                  "write sources");
   if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "write sources");
@@ -1008,6 +1125,8 @@ static int solve_impl(lmdg_t* h, int scheme, int mode, double tol, int restart, 
     rc = lmdg_recover(h, scheme, LMDG_PREC_FP64, xr, phi_out, psi_out, st);
   }
   if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "solve");
+  // the recovery sweep ran after the last flag check inside gmres
+  if (rc == LMDG_OK) rc = read_error_flag(h, st);
   const double total =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   if (info) {
@@ -1177,6 +1296,50 @@ int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, doubl
     info->time_apply_ms = inf_f.time_apply_ms + inf_a.time_apply_ms;
   }
   return rc;
+}
+
+int lmdg_workspace_bytes(const lmdg_t* h, int restart, int64_t* held, int64_t* solve) {
+  using namespace lmdg;
+  if (!h || !held || !solve || restart < 1 || restart > kMaxRestart) return LMDG_INVALID_ARG;
+  const long long nc = h->ncell;
+  const size_t d = sizeof(double);
+  const size_t nr = (size_t)h->rhs_cap;
+  size_t b = (size_t)h->noct * h->dslots * kDirStride * d + sizeof(unsigned int) + sizeof(int) +
+             (size_t)h->noct * h->dslots * 2 * d;
+  b += nr * (h->ws.part_bytes + std::max<size_t>(h->ws.edge_bytes, 8) + h->ws.zbuf_bytes +
+             h->ws.prog_words * sizeof(unsigned long long) + (size_t)kScratchVecs * h->np * nc * d + nc * d);
+  if (h->have_mat) b += 4 * (size_t)nc * d;  // sigma_t, scattering, absorption, eps (the source is above)
+  if (h->d_qS) b += 3 * (size_t)nc * d;
+  if (h->d_qdir) b += (size_t)h->ndir * 4 * nc * d;
+  if (h->d_sq1) b += 3 * (size_t)nc * d;
+  if (h->d_alpha) b += (size_t)h->ndir * (h->n[0] + h->n[1]) * 3 * d;
+  if (h->d_sqa) b += 3 * (size_t)nc * d;
+  b += h->krylov_doubles * d + h->small_doubles * d + 2 * h->psi_doubles * d;
+  if (h->d_cvec) b += 6 * (size_t)h->np * nc * d;
+  *held = (int64_t)b;
+  // what a solve with this restart (and the handle's augmentation) allocates beyond that
+  const int ka = std::max(0, std::min(h->augment, kMaxRestart - restart));
+  const size_t kry = (size_t)(restart + ka + 2 + (ka > 0 ? 2 * ka + 2 : 0)) * h->np * nc * h->n_rhs;
+  const size_t small = small_layout(h->n_rhs).total;
+  *solve = (int64_t)((kry > h->krylov_doubles ? kry : 0) + (small > h->small_doubles ? small : 0)) * (int64_t)d;
+  return LMDG_OK;
+}
+
+int lmdg_synchronize(lmdg_t* h, void* stream) {
+  if (!h) return LMDG_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = check_hip(h, hipStreamSynchronize(st), "synchronize");
+  if (rc == LMDG_OK) rc = read_error_flag(h, st);
+  return rc;
+}
+
+int lmdg_set_wait_limit(lmdg_t* h, long long spins, int unreachable) {
+  if (!h) return LMDG_INVALID_ARG;
+  if (spins < 1 || (unreachable != 0 && unreachable != 1))
+    return set_error(h, LMDG_INVALID_ARG, "wait limit out of range");
+  h->spin_limit = spins;
+  h->wait_bias = (unsigned)unreachable;
+  return LMDG_OK;
 }
 
 int lmdg_set_augment(lmdg_t* h, int k) {

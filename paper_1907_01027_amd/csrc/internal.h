@@ -42,6 +42,9 @@ struct SweepParams {
   const double* qA;      // eps q |K| (n_rhs * ncell) or null
   const double* qS;      // source slope moments (3 * ncell, standard scheme) or null
   const double* absA;    // eps sigma_a |K|
+  const double* alpha;   // inflow data [n_dir][nfaces][3] (face average, linear coefficient, midpoint) or null
+  const double* qdir;    // direction-dependent source moments eps q_l |K| [n_dir][4][ncell] or null
+  int nfaces;            // inflow faces per direction: n_y x faces, then n_x y faces
   int defect;            // 1: x enters through the defect source (see lm_source)
   R* part;               // [n_rhs][4][NOUT][ncell] per-quadrant sums
   R* edge;               // [n_rhs][4][nstrips][nx][NF][dslots] top-row traces
@@ -51,6 +54,8 @@ struct SweepParams {
   int* err;
   unsigned long long epoch;
   unsigned int ticket_base;
+  long long spin_limit;  // polls of a progress word before a wait gives up
+  unsigned int wait_bias;  // 0; 1 makes every wait target unreachable (failure-handling tests)
 };
 
 // Everything the 3D sweep kernel reads (LMDG, RLMDG); passed by value.
@@ -77,6 +82,8 @@ struct Sweep3Params {
   int* err;
   unsigned long long epoch;
   unsigned int ticket_base;
+  long long spin_limit;
+  unsigned int wait_bias;
 };
 
 struct Workspace {
@@ -124,6 +131,20 @@ struct lmdg_handle {
   // slope moments (standard scheme); both null outside the adjoint solve
   const double* src0 = nullptr;
   const double* src1 = nullptr;
+  // the handle's own source data beyond per-cell constants (2D, one right-hand side):
+  // d_qS   source slope moments eps q_r |K|, r = 1..3, of an isotropic source (STD sweeps)
+  // d_qdir direction-dependent source moments eps q_{l,r} |K| [n_dir][4][ncell]
+  // d_alpha inflow data [n_dir][n_x + n_y][3] (see SweepParams::alpha)
+  // d_sq1  sum_l w_l of the source slope moments (3 x ncell), subtracted from the slope
+  //        rows of the low-memory right-hand sides
+  // d_sqa  the part of the inflow terms of the LMDG slope rows that the sweep's ghost
+  //        traces do not carry (3 x ncell), subtracted likewise
+  double* d_qS = nullptr;
+  double* d_qdir = nullptr;
+  double* d_alpha = nullptr;
+  double* d_sq1 = nullptr;
+  double* d_sqa = nullptr;
+  int last_nsl = 4;                // partial slices written by the last sweep launch
   // directions: index of -Omega_l; per quadrant and slot the weight and the slot of
   // -Omega_l in the opposite quadrant (adjoint gradients)
   std::vector<int> neg_dir;
@@ -135,6 +156,8 @@ struct lmdg_handle {
   lmdg::Workspace ws;
   unsigned long long epoch = 1;
   unsigned int ticket_base = 0;
+  long long spin_limit = 1ll << 25;  // polls per wait (lmdg_set_wait_limit)
+  unsigned int wait_bias = 0;
   int device = 0;
   int n_cu = 256;
   std::string last_error;

@@ -126,14 +126,23 @@ __device__ __forceinline__ void iso_g(const double* x0, int nx, int ny, int i, i
 
 // Reduced operator / right-hand side / recovery for LMDG and RLMDG from the
 // per-quadrant sweep sums (eq-nonrec-block; Sec. 3.3.2 with the second block row
-// G = Sigma (L_10 + L_11 R) - Sigma M_1 P_1 R; Step 4 with c = 0 since the source
-// has no slope moments and the inflow is vacuum).  In kApplyDefect the sweep solved
+// G = Sigma (L_10 + L_11 R) - Sigma M_1 P_1 R).  In kApplyDefect the sweep solved
 // L~_00 psi_D = defect source, and K x = [P_0 psi_D ; B_11 x_1 - G Sigma_0^T x_0 + G psi_D].
+//
+// Source data.  With F(x) = [x_0 - P_0 psi ; B_11 x_1 - G psi], psi the sweep of x with
+// the source and the inflow data (taken as ghost traces upwind of the inflow faces),
+// the isotropic test functions of the slope rows give F(x) = [0 ; -Sigma Q_1^q] with
+// x_1 = -(Phi_1 - P_1 R Psi_0) (LMDG: -Phi_1), Sigma Q_1^q the direction sum of the
+// source slope moments: the inflow part of Sigma Q_1 is carried by the ghost traces
+// (for LMDG only its face averages; sqa holds the rest).  So K x = b with
+// b = -F(0) - [0 ; sq1 + sqa]: the right-hand-side sweep (x = 0) minus the
+// corrections, and recovery Phi_1 = -x_1 + P_1 R Psi_0 needs no c.
 template <typename R, bool RLM>
 __global__ void combine_lm_kernel(int mode, int nr, int nsl, int nx, int ny, double hx, double hy, double cxp, double cxm,
                                   double cyp, double cym, QuadMoments qm, const double* __restrict__ x_all,
                                   const R* __restrict__ part_all, const double* __restrict__ sigtA,
                                   const double* __restrict__ scatA, const double* __restrict__ absA,
+                                  const double* __restrict__ sq1, const double* __restrict__ sqa,
                                   double* __restrict__ out_all) {
   constexpr int NOUT = RLM ? 6 : 3;
   const long long nc = (long long)nx * ny;
@@ -173,11 +182,14 @@ __global__ void combine_lm_kernel(int mode, int nr, int nsl, int nx, int ny, dou
       out[2 * nc + p] = yb - gi[1] + g2;
       out[3 * nc + p] = yc - gi[2] + g3;
     } else if (mode == kRhs) {
+      double c1 = 0.0, c2 = 0.0, c3 = 0.0;
+      if (sq1) { c1 += sq1[p]; c2 += sq1[nc + p]; c3 += sq1[2 * nc + p]; }
+      if (sqa) { c1 += sqa[p]; c2 += sqa[nc + p]; c3 += sqa[2 * nc + p]; }
       out[p] = s[0];
-      out[nc + p] = g1;
-      out[2 * nc + p] = g2;
-      out[3 * nc + p] = g3;
-    } else {  // recovery: Phi_1 = -X_1 + P_1 R Psi_0 (+ c, zero here)
+      out[nc + p] = g1 - c1;
+      out[2 * nc + p] = g2 - c2;
+      out[3 * nc + p] = g3 - c3;
+    } else {  // recovery: Phi_1 = -X_1 + P_1 R Psi_0
       out[p] = s[0];
       out[nc + p] = -x[nc + p] + (RLM ? s[4] : 0.0);
       out[2 * nc + p] = -x[2 * nc + p] + (RLM ? s[5] : 0.0);
@@ -384,10 +396,10 @@ void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double
   const int nx = (int)h->n[0], ny = (int)h->n[1];
   if (scheme == LMDG_SCHEME_STD) {
     if (prec == LMDG_PREC_FP64)
-      hipLaunchKernelGGL(combine_std_kernel<double>, dim3(g), dim3(kBlock), 0, st, mode, nr, part_slices(h, scheme, prec), nc, x,
+      hipLaunchKernelGGL(combine_std_kernel<double>, dim3(g), dim3(kBlock), 0, st, mode, nr, h->last_nsl, nc, x,
                          (const double*)h->ws.part, out);
     else
-      hipLaunchKernelGGL(combine_std_kernel<float>, dim3(g), dim3(kBlock), 0, st, mode, nr, part_slices(h, scheme, prec), nc, x,
+      hipLaunchKernelGGL(combine_std_kernel<float>, dim3(g), dim3(kBlock), 0, st, mode, nr, h->last_nsl, nc, x,
                          (const float*)h->ws.part, out);
     return;
   }
@@ -399,10 +411,14 @@ void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double
     qm.ay[q] = h->qay[q];
   }
 #define LMDG_COMBINE(R, RLM)                                                                        \
-  hipLaunchKernelGGL((combine_lm_kernel<R, RLM>), dim3(g), dim3(kBlock), 0, st, mode, nr, part_slices(h, scheme, prec), nx, ny, hx, hy, \
+  hipLaunchKernelGGL((combine_lm_kernel<R, RLM>), dim3(g), dim3(kBlock), 0, st, mode, nr, h->last_nsl, nx, ny, hx, hy, \
                      h->cplus[0], h->cminus[0], h->cplus[1], h->cminus[1], qm, x,                    \
-                     (const R*)h->ws.part, h->d_sigtA, h->d_scatA, h->d_absA, out)
+                     (const R*)h->ws.part, h->d_sigtA, h->d_scatA, h->d_absA, sq1, sqa, out)
   const bool rlm = scheme == LMDG_SCHEME_RLMDG;
+  // right-hand-side corrections of the handle's own source data (not of an adjoint source)
+  const bool own = mode == kRhs && !h->src0;
+  const double* sq1 = own ? h->d_sq1 : nullptr;
+  const double* sqa = (own && !rlm) ? h->d_sqa : nullptr;
   if (prec == LMDG_PREC_FP64) {
     if (rlm) LMDG_COMBINE(double, true); else LMDG_COMBINE(double, false);
   } else {
@@ -421,10 +437,10 @@ void launch_sum_quadrants(lmdg_handle* h, int scheme, int prec, double* out, hip
   const int g = std::min(grid_for(h->ncell * h->n_rhs), 4096);
   if (prec == LMDG_PREC_FP64)
     hipLaunchKernelGGL(sum_quadrants_kernel<double>, dim3(g), dim3(kBlock), 0, st, nout, nout_abi, h->n_rhs,
-                       part_slices(h, scheme, prec), h->ncell, (const double*)h->ws.part, out);
+                       h->last_nsl, h->ncell, (const double*)h->ws.part, out);
   else
     hipLaunchKernelGGL(sum_quadrants_kernel<float>, dim3(g), dim3(kBlock), 0, st, nout, nout_abi, h->n_rhs,
-                       part_slices(h, scheme, prec), h->ncell, (const float*)h->ws.part, out);
+                       h->last_nsl, h->ncell, (const float*)h->ws.part, out);
 }
 
 void launch_b11(lmdg_handle* h, const double* x, double* y, hipStream_t st) {

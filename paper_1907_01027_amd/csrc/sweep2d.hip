@@ -64,15 +64,14 @@ struct SrcTraits {
 // ---------------------------------------------------------------- local solves
 // Low-memory sweep (L_00 of Sec. 3.2): one unknown per cell and direction.
 // Row "test with the cell constant" of eq-Ljk:
-//   sigma_t|K| psi + |Ox| h_y (psi - psi_left) + |Oy| h_x (psi - psi_down) = src.
-// Reductions: w psi (P_0), w Ox h_y (psi_left - psi), w Oy h_x (psi_down - psi)
-// (rows xi, eta of Sigma L_10; its xi*eta row vanishes).
+//   sigma_t|K| psi + |Ox| h_y (psi - psi_left) + |Oy| h_x (psi - psi_down) = src,
+// solved with inv = 1 / (sigma_t|K| + |Ox| h_y + |Oy| h_x), which does not depend on the
+// upwind values.  Reductions: w psi (P_0), w Ox h_y (psi_left - psi), w Oy h_x
+// (psi_down - psi) (rows xi, eta of Sigma L_10; its xi*eta row vanishes).
 template <typename R>
-__device__ __forceinline__ void cell_lmdg(const Dir<R>& d, R src, R sigtA, const R* xin, const R* ydn,
-                                          R* xo, R* yo, R* o, R& psi_out) {
-  const R num = src + d.axhy * xin[0] + d.ayhx * ydn[0];
-  const R den = sigtA + d.axhy + d.ayhx;
-  const R psi = num / den;
+__device__ __forceinline__ void cell_lmdg(const Dir<R>& d, R src, R inv, const R* xin, const R* ydn, R* xo, R* yo,
+                                          R* o, R& psi_out) {
+  const R psi = (src + d.axhy * xin[0] + d.ayhx * ydn[0]) * inv;
   xo[0] = psi;
   yo[0] = psi;
   o[0] = d.w * psi;
@@ -84,24 +83,25 @@ __device__ __forceinline__ void cell_lmdg(const Dir<R>& d, R src, R sigtA, const
 // Reconstructed sweep (L~_00 = L_00 + L_01 R, Sec. 3.3): the cell function in
 // direction l is psi + c_xi xi + c_eta eta with upwind slopes (Sec. 3.3.1)
 //   c_xi = sign(Ox) k_x (psi - psi_left),  k = 1/2 inside, 1 in the inflow cell
-// (where the upwind value is the vacuum inflow 0).  A face hands downwind its trace
-// average T, its linear coefficient along the face, and the cell average.
-// Reductions: w psi, the xi / eta / xi*eta rows of w (L_10 + L_11 R) applied to the
-// cell function, and w c_xi, w c_eta (for P_1 R).
+// (where the upwind value is the inflow datum: zero for vacuum, the midpoint value of
+// alpha otherwise).  inv = 1 / (sigma_t|K| + |Ox| h_y (1 + k_x) + |Oy| h_x (1 + k_y)).
+// A face hands downwind its trace average T, its linear coefficient along the face,
+// and the cell average.  Reductions: w psi, the xi / eta / xi*eta rows of
+// w (L_10 + L_11 R) applied to the cell function, and w c_xi, w c_eta (for P_1 R).
 template <typename R>
-__device__ __forceinline__ void cell_rlmdg(const Dir<R>& d, R src, R sigtA, R kx, R ky, const R* xin,
+__device__ __forceinline__ void cell_rlmdg(const Dir<R>& d, R src, R sigtA, R inv, R kx, R ky, const R* xin,
                                            const R* ydn, R* xo, R* yo, R* o, R& psi_out) {
   // xin = (T_x of left cell, its c_eta, its average); ydn = (T_y, c_xi, average) of cell below
   const R third = R(1) / R(3);
-  const R num = src + d.axhy * (xin[0] + kx * xin[2]) + d.ayhx * (ydn[0] + ky * ydn[2]);
-  const R den = sigtA + d.axhy * (R(1) + kx) + d.ayhx * (R(1) + ky);
-  const R psi = num / den;
+  const R psi = (src + d.axhy * (xin[0] + kx * xin[2]) + d.ayhx * (ydn[0] + ky * ydn[2])) * inv;
   const R cxi = d.sx * kx * (psi - xin[2]);
   const R ceta = d.sy * ky * (psi - ydn[2]);
-  const R tx = psi + kx * (psi - xin[2]);
-  const R ty = psi + ky * (psi - ydn[2]);
-  xo[0] = tx; xo[1] = ceta; xo[2] = psi;
-  yo[0] = ty; yo[1] = cxi;  yo[2] = psi;
+  xo[0] = psi + kx * (psi - xin[2]);
+  xo[1] = ceta;
+  xo[2] = psi;
+  yo[0] = psi + ky * (psi - ydn[2]);
+  yo[1] = cxi;
+  yo[2] = psi;
   const R sA3 = sigtA * third;
   o[0] = d.w * psi;
   o[1] = d.w * (d.oxhy * (xin[0] - psi) + (sA3 + d.axhy + d.ayhx * third) * cxi - d.ayhx * third * ydn[1]);
@@ -310,7 +310,6 @@ __device__ __forceinline__ void raw_coef(const double* raw, int c, int jr, int s
     cf[0][0] += qA;
     for (int m = 1; m < 4; ++m) cf[m][0] += raw[15 + m];  // source slope moments
     coef[0] = (R)sigtA;
-    for (int m = 0; m < 4; ++m)
     for (int m = 0; m < 4; ++m) {
       // within a quadrant Ox = sx |Ox| and Oy = sy |Oy|
       coef[(1 + 3 * m) * cstride] = (R)cf[m][0];
@@ -354,7 +353,16 @@ __device__ __forceinline__ void raw_coef(const double* raw, int c, int jr, int s
 // takes the cross-wave reduction out of the chunk loop, which pays when few work items
 // run (one source on a small mesh).  Otherwise the waves' sums are first added through
 // LDS and the partials have one slice per quadrant.
-template <typename R, int S, int MAXW, bool DIRECT>
+// DATA: source sweeps with prescribed inflow or direction-dependent sources.  The
+// inflow datum of eq-main enters as the trace of a ghost cell upwind of the inflow
+// face, so that each local solve and reduction takes it exactly where it takes an
+// upwind neighbour's trace: per direction and inflow face, alpha supplies (a0, a1, m),
+// the face average and the linear Legendre coefficient along the face of alpha, and
+// its value at the face midpoint, which is what an upwind cell hands over (STD: the
+// trace a0 + a1 t; LMDG: its average; RLMDG: trace average, its linear coefficient
+// and the upwind value that the reconstruction of Sec. 3.3.1 takes in the inflow
+// cell).  Per-direction source moments are added to the staged isotropic source.
+template <typename R, int S, int MAXW, bool DIRECT, bool DATA = false>
 __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
   constexpr int NOUT = SchemeTraits<S>::NOUT;
   constexpr int NOUTP = (NOUT + 3) & ~3;  // rows of red, padded to whole lane groups
@@ -454,9 +462,17 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
       }
     };
 
-    R xin[NF], yprev[NF];
+    R xin[NF], yprev[NF], gx[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) { xin[f] = 0; yprev[f] = 0; }
+    for (int f = 0; f < NF; ++f) { xin[f] = 0; yprev[f] = 0; gx[f] = 0; }
+    if constexpr (DATA) {
+      // ghost trace at the x-inflow face of this lane's row (mesh row j)
+      if (P.alpha && row_ok && d.idx >= 0) {
+        const double* a = P.alpha + ((long long)d.idx * P.nfaces + j) * 3;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) gx[f] = (R)a[f];
+      }
+    }
 
     stage_load(0);
     stage_store(0, 0);
@@ -465,12 +481,12 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
       const int buf = k & 1;
       if (s > 0 && tid == 0) {
         const int need = min(nx, t0 + cw);
-        const unsigned long long target = (P.epoch << 32) | (unsigned long long)need;
+        const unsigned long long target = ((P.epoch + P.wait_bias) << 32) | (unsigned long long)need;
         const unsigned long long* flag = progr + (long long)q * P.nstrips + (s - 1);
         long long spins = 0;
         while (load_agent(flag) < target) {
           __builtin_amdgcn_s_sleep(2);
-          if (++spins > kSpinLimit) { atomicOr(P.err, 1); break; }
+          if (++spins > P.spin_limit) { atomicOr(P.err, 1); break; }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
@@ -481,7 +497,17 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
         const R* src = edger + (((long long)q * P.nstrips + (s - 1)) * nx + t0) * NF * P.dslots;
         for (int e = tid; e < ne; e += blockDim.x) {
           const int c = t0 + e / (NF * P.dslots);
-          eds[e] = (s > 0 && c < nx) ? load_agent(src + e) : R(0);
+          R v = (s > 0 && c < nx) ? load_agent(src + e) : R(0);
+          if constexpr (DATA) {
+            // ghost traces below the y-inflow faces of the first strip
+            if (s == 0 && P.alpha && c < nx) {
+              const int sl = e % P.dslots, f = (e / P.dslots) % NF;
+              const int l = (int)P.dirs[((long long)q * P.dslots + sl) * kDirStride + 3];
+              const int i = sxi > 0 ? c : nx - 1 - c;
+              if (l >= 0) v = (R)P.alpha[((long long)l * P.nfaces + ny + i) * 3 + f];
+            }
+          }
+          eds[e] = v;
         }
       }
       if (k + 1 < P.nchunks) stage_load(k + 1);  // overlaps the step loop below
@@ -506,6 +532,14 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
             const R* a = cf + (size_t)(1 + 3 * m) * ncells;
             src_g[u][m] = a[0] + d.aox * a[ncells] + d.aoy * a[2 * ncells];
           }
+          if constexpr (DATA) {
+            const int c = t0 + tt - r;
+            if (P.qdir && row_ok && d.idx >= 0 && c >= 0 && c < nx) {
+              const long long cell = (long long)j * nx + (sxi > 0 ? c : nx - 1 - c);
+#pragma unroll
+              for (int m = 0; m < NS; ++m) src_g[u][m] += (R)P.qdir[((long long)d.idx * 4 + m) * nc + cell];
+            }
+          }
           if constexpr (S == LMDG_SCHEME_LMDG) {
             inv_g[u] = recip(sig_g[u] + d.axhy + d.ayhx);
           } else if constexpr (S == LMDG_SCHEME_RLMDG) {
@@ -529,40 +563,16 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
           for (int f = 0; f < NF; ++f) {
             const R v = shr1(yprev[f]);
             ydn[f] = (r == 0) ? edn_g[u][f] : v;
-            xin[f] = (c == 0) ? R(0) : xin[f];
+            xin[f] = (c == 0) ? gx[f] : xin[f];
           }
           R o[NOUT], xo[NF], yo[NF];
           if constexpr (S == LMDG_SCHEME_STD) {
             cell_std<R>(d, src_g[u], sig_g[u], xin, ydn, xo, yo, o, psi_g[u]);
           } else if constexpr (S == LMDG_SCHEME_LMDG) {
-            const R psi = (src_g[u][0] + d.axhy * xin[0] + d.ayhx * ydn[0]) * inv;
-            xo[0] = psi;
-            yo[0] = psi;
-            o[0] = d.w * psi;
-            o[1] = d.w * d.oxhy * (xin[0] - psi);
-            o[2] = d.w * d.oyhx * (ydn[0] - psi);
-            psi_g[u][0] = psi;
+            cell_lmdg<R>(d, src_g[u][0], inv, xin, ydn, xo, yo, o, psi_g[u][0]);
           } else {
             const R kx = (c == 0) ? R(1) : R(0.5);
-            const R third = R(1) / R(3);
-            const R psi =
-                (src_g[u][0] + d.axhy * (xin[0] + kx * xin[2]) + d.ayhx * (ydn[0] + ky * ydn[2])) * inv;
-            const R cxi = d.sx * kx * (psi - xin[2]);
-            const R ceta = d.sy * ky * (psi - ydn[2]);
-            xo[0] = psi + kx * (psi - xin[2]);
-            xo[1] = ceta;
-            xo[2] = psi;
-            yo[0] = psi + ky * (psi - ydn[2]);
-            yo[1] = cxi;
-            yo[2] = psi;
-            const R sA3 = sig_g[u] * third;
-            o[0] = d.w * psi;
-            o[1] = d.w * (d.oxhy * (xin[0] - psi) + (sA3 + d.axhy + d.ayhx * third) * cxi - d.ayhx * third * ydn[1]);
-            o[2] = d.w * (d.oyhx * (ydn[0] - psi) + (sA3 + d.ayhx + d.axhy * third) * ceta - d.axhy * third * xin[1]);
-            o[3] = d.w * third * (d.oxhy * (xin[1] - ceta) + d.oyhx * (ydn[1] - cxi));
-            o[4] = d.w * cxi;
-            o[5] = d.w * ceta;
-            psi_g[u][0] = psi;
+            cell_rlmdg<R>(d, src_g[u][0], sig_g[u], inv, kx, ky, xin, ydn, xo, yo, o, psi_g[u][0]);
           }
 #pragma unroll
           for (int f = 0; f < NF; ++f) {
@@ -690,7 +700,11 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   constexpr size_t kLdsBudget = 144 * 1024;
   int cw = 16;
   const int maxc = W > 4 ? 1 : SrcTraits<S>::MAXC;
-  const bool direct = part_slices(h, S, sizeof(R) == 8 ? LMDG_PREC_FP64 : LMDG_PREC_FP32) > 4;
+  // inflow data and direction-dependent sources belong to the handle's own source
+  // (not to the detector source of an adjoint solve)
+  const bool data = use_q && !h->src0 && (h->d_alpha || h->d_qdir);
+  const bool direct = !data && part_slices(h, S, sizeof(R) == 8 ? LMDG_PREC_FP64 : LMDG_PREC_FP32) > 4;
+  h->last_nsl = direct ? 4 * W : 4;  // slices of the partials the combine adds
   while (cw > step_group<R>() &&
          (kRows * cw > maxc * 64 * W || lds_bytes<R, S>(cw, W, h->dslots, direct) > kLdsBudget))
     cw >>= 1;
@@ -713,7 +727,10 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   P.sigtA = h->d_sigtA;
   P.scatA = h->d_scatA;
   P.qA = use_q ? (h->src0 ? h->src0 : h->d_qA) : nullptr;
-  P.qS = (use_q && S == LMDG_SCHEME_STD) ? h->src1 : nullptr;
+  P.qS = (use_q && S == LMDG_SCHEME_STD) ? (h->src0 ? h->src1 : h->d_qS) : nullptr;
+  P.alpha = data ? h->d_alpha : nullptr;
+  P.qdir = data ? h->d_qdir : nullptr;
+  P.nfaces = (int)(h->n[0] + h->n[1]);
   P.absA = h->d_absA;
   P.defect = defect ? 1 : 0;
   P.part = reinterpret_cast<R*>(h->ws.part);
@@ -726,6 +743,8 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   P.err = h->ws.err;
   P.epoch = h->epoch;
   P.ticket_base = h->ticket_base;
+  P.spin_limit = h->spin_limit;
+  P.wait_bias = h->wait_bias;
   const int grid = std::min(P.n_items, 4 * h->n_cu);
   const size_t lds = lds_bytes<R, S>(cw, W, h->dslots, direct);
   hipEvent_t ev_end = nullptr;
@@ -741,7 +760,12 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
     ev_end = h->ev_pool[h->ev_used + 1];
     h->ev_used += 2;
   }
-  if constexpr (sizeof(R) == 8) {
+  if (data) {
+    if (W <= 4)
+      hipLaunchKernelGGL((sweep2d_kernel<R, S, 4, false, true>), dim3(grid), dim3(64 * W), lds, st, P);
+    else
+      hipLaunchKernelGGL((sweep2d_kernel<R, S, kMaxWaves, false, true>), dim3(grid), dim3(64 * W), lds, st, P);
+  } else if constexpr (sizeof(R) == 8) {
     if (direct && W <= 4) {
       hipLaunchKernelGGL((sweep2d_kernel<R, S, 4, true>), dim3(grid), dim3(64 * W), lds, st, P);
     } else if (direct) {

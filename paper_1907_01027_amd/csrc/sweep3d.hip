@@ -238,20 +238,20 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
       const int buf = k & 1;
       if (tid == 0 && (s > 0 || kz > 0)) {
         const int need = min(nx, t0 + cw);
-        const unsigned long long target = (P.epoch << 32) | (unsigned long long)need;
+        const unsigned long long target = ((P.epoch + P.wait_bias) << 32) | (unsigned long long)need;
         long long spins = 0;
         if (s > 0) {
           const unsigned long long* flag = progr + (long long)kz * P.nstrips + (s - 1);
           while (load_agent(flag) < target) {
             __builtin_amdgcn_s_sleep(2);
-            if (++spins > kSpinLimit) { atomicOr(P.err, 1); break; }
+            if (++spins > P.spin_limit) { atomicOr(P.err, 1); break; }
           }
         }
         if (kz > 0) {
           const unsigned long long* flag = progr + (long long)(kz - 1) * P.nstrips + s;
           while (load_agent(flag) < target) {
             __builtin_amdgcn_s_sleep(2);
-            if (++spins > kSpinLimit) { atomicOr(P.err, 1); break; }
+            if (++spins > P.spin_limit) { atomicOr(P.err, 1); break; }
           }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -493,6 +493,7 @@ int launch3_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipS
   P.absA = h->d_absA;
   P.defect = defect ? 1 : 0;
   P.part = reinterpret_cast<R*>(h->ws.part);
+  h->last_nsl = 8;
   P.yedge = reinterpret_cast<R*>(h->ws.edge);
   P.zbuf = reinterpret_cast<R*>(h->ws.zbuf);
   constexpr int NF = Traits3<S>::NF;
@@ -505,6 +506,8 @@ int launch3_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipS
   P.err = h->ws.err;
   P.epoch = h->epoch;
   P.ticket_base = h->ticket_base;
+  P.spin_limit = h->spin_limit;
+  P.wait_bias = h->wait_bias;
   const int grid = std::min(P.n_items, 4 * h->n_cu);
   const size_t lds = lds_bytes3<R, S>(cw, W, h->dslots);
   hipEvent_t ev_end = nullptr;

@@ -51,8 +51,6 @@ __device__ __forceinline__ void store_agent(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-constexpr long long kSpinLimit = 1ll << 25;
-
 // Immediate of s_waitcnt vmcnt(0) in the gfx9 encoding (expcnt and lgkmcnt at their
 // maxima, so they are not waited for): the wave's vector memory operations have
 // completed.  Agent-scope atomic stores are written through to the agent's coherence

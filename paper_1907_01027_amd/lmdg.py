@@ -29,7 +29,8 @@ MODES = {"fp64": 0, "mixed": 1}
 EXPORTED = ["lmdg_status_string", "lmdg_last_error", "lmdg_quadrature_level_symmetric", "lmdg_create",
             "lmdg_destroy", "lmdg_set_materials", "lmdg_set_sources", "lmdg_sweep", "lmdg_apply", "lmdg_rhs",
             "lmdg_recover", "lmdg_solve", "lmdg_set_augment", "lmdg_adjoint_solve", "lmdg_profile",
-            "lmdg_sweep_kernel_time"]
+            "lmdg_sweep_kernel_time", "lmdg_synchronize", "lmdg_set_wait_limit", "lmdg_set_source_moments",
+            "lmdg_workspace_bytes"]
 
 
 class LmdgInfo(ctypes.Structure):
@@ -69,6 +70,10 @@ def _load():
         "lmdg_set_augment": (I, [P, I]),
         "lmdg_profile": (I, [P, I]),
         "lmdg_sweep_kernel_time": (I, [P, ctypes.POINTER(D), ctypes.POINTER(I)]),
+        "lmdg_synchronize": (I, [P, P]),
+        "lmdg_set_wait_limit": (I, [P, ctypes.c_longlong, I]),
+        "lmdg_set_source_moments": (I, [P, I, P, P]),
+        "lmdg_workspace_bytes": (I, [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -156,6 +161,19 @@ def lmdg_set_materials(h, sigma_s, sigma_a, eps, q, alpha=None, stream=None):
                                    _stream(stream)), h)
 
 
+def lmdg_set_source_moments(h, qm, per_direction=False, stream=None):
+    """qm: CUDA float64 tensor of cell moments, (4, n_cells) isotropic or (n_dir, 4, n_cells)."""
+    _check(_lib.lmdg_set_source_moments(h, int(bool(per_direction)), _ptr(qm), _stream(stream)), h)
+
+
+def lmdg_workspace_bytes(h, restart):
+    """(bytes held by the handle, bytes a solve with this restart would add)."""
+    held = ctypes.c_int64(0)
+    solve = ctypes.c_int64(0)
+    _check(_lib.lmdg_workspace_bytes(h, int(restart), ctypes.byref(held), ctypes.byref(solve)), h)
+    return held.value, solve.value
+
+
 def lmdg_set_sources(h, q, stream=None):
     """q: CUDA float64 tensor (n_rhs, n_cells) or (n_cells,); sets the handle's right-hand sides."""
     n_rhs = 1 if q.dim() == 1 else int(q.shape[0])
@@ -215,6 +233,16 @@ def lmdg_sweep_kernel_time(h):
     n = ctypes.c_int(0)
     _check(_lib.lmdg_sweep_kernel_time(h, ctypes.byref(ms), ctypes.byref(n)), h)
     return ms.value, n.value
+
+
+def lmdg_synchronize(h, stream=None):
+    """Wait for the handle's work; raises LmdgError if a sweep wait gave up."""
+    _check(_lib.lmdg_synchronize(h, _stream(stream)), h)
+
+
+def lmdg_set_wait_limit(h, spins, unreachable=False):
+    """Bounded-wait policy of the sweeps (failure-handling tests)."""
+    _check(_lib.lmdg_set_wait_limit(h, int(spins), int(bool(unreachable))), h)
 
 
 class Solver:

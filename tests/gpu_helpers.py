@@ -26,6 +26,16 @@ class Case:
         self.sigma_s, self.sigma_a, self.eps, self.q = ss, sa, ep, q[0]
         self.ncell = self.n[0] * self.n[1]
         self._prob = None
+        self._red = {}
+
+    def reduced(self, scheme):
+        """The oracle's reduced operator for scheme ("std", "lmdg", "rlmdg"), built once."""
+        if scheme not in self._red:
+            if scheme == "std":
+                self._red[scheme] = S.StdReduced(self.prob)
+            else:
+                self._red[scheme] = S.LowMemoryReduced(self.prob, scheme == "rlmdg")
+        return self._red[scheme]
 
     @property
     def prob(self):
@@ -69,3 +79,34 @@ def rel_err(a, b):
     a = np.asarray(a)
     b = np.asarray(b)
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def oracle_sweep(case, scheme, x_abi, use_q):
+    """Per-cell reductions of one sweep in the ABI layout, from the oracle's matrices."""
+    prob = case.prob
+    nc = case.ncell
+    if scheme == "std":
+        red = case.reduced("std")
+        phi = abi_to_std(x_abi, nc)
+        src = prob.Mu @ phi
+        rhs = np.broadcast_to(src, (prob.n_dir, src.size)) + (prob.Qu if use_q else 0.0)
+        psi = red.Linv(rhs)                       # (n_dir, nc*4) cell-major
+        out = std_to_abi(prob.w @ psi, nc)
+        psi_abi = psi.reshape(prob.n_dir, nc, 4).transpose(0, 2, 1).ravel()
+        return out, psi_abi
+    red = case.reduced(scheme)
+    x = abi_to_lm(x_abi, nc)
+    rhs = red.M0 @ x[:nc] + red.L01 @ (red.St @ x[nc:])
+    if use_q:
+        rhs = rhs + red.Qt0
+    psi = red.Lt00_lu.solve(rhs)
+    p0 = red.P0 @ psi
+    g = red.S @ (red.L10 @ psi)
+    if scheme == "rlmdg":
+        g = g + red.S @ (red.L11 @ (red.R @ psi))
+        pr = (red.P1 @ (red.R @ psi)).reshape(nc, 3)
+    g = g.reshape(nc, 3)
+    rows = [p0, g[:, 0], g[:, 1], g[:, 2]]
+    if scheme == "rlmdg":
+        rows += [pr[:, 0], pr[:, 1]]
+    return np.concatenate(rows), psi

@@ -126,31 +126,36 @@ def test_stacked_solve_against_direct(scheme, mode):
     s.close()
 
 
-def test_eight_sources_mixed_64():
-    """Eight sources at 64^2, S8, eps = 0.05 (RLMDG, mixed precision) against the
-    same eight solved one at a time in FP64 (the batched FP64 solve of the eight is
-    checked exactly against single solves by the tests above at smaller size)."""
-    case = Case((64, 64), 8, eps=0.05, seed=6)
+@pytest.mark.timeout(600)
+def test_eight_sources_mixed_against_oracle():
+    """Eight sources at 32^2, S8, eps = 0.05 (RLMDG), solved together in mixed
+    precision to a relative residual of 1e-12, against the oracle's reduced-route solve
+    of each source (FP64, GMRES to 1e-13, itself equal to the direct solve to 2e-15 on
+    this mesh).  The oracle's reduced operator has 2-norm condition number 2.8e4 here
+    (singular values 0.915 and 3.25e-5, from the dense matrix), so a residual of 1e-12
+    bounds the relative 2-norm error of the reduced solution by 2.8e-8; the bar 1e-6 on
+    the max-norm relative error of the recovered scalar flux leaves room for the norm
+    change and the recovery sweep."""
+    print("case eight sources mixed 32x32 S8", flush=True)
+    case = Case((32, 32), 8, eps=0.05, seed=6)
     nc = case.ncell
     q = sources(case, nr=8, seed=9)
     s = case.solver()
-    single = []
-    for k in range(8):
-        set_single(s, case, q[k])
-        x = torch.zeros(4 * nc, dtype=torch.float64, device=DEV)
-        phi = torch.zeros_like(x)
-        lmdg.lmdg_solve(s.h, "rlmdg", "fp64", 1e-11, 60, 20000, x, phi)
-        single.append(phi.cpu().numpy())
+    lmdg.lmdg_set_augment(s.h, 10)
     lmdg.lmdg_set_sources(s.h, T(q))
     x = torch.zeros(8 * 4 * nc, dtype=torch.float64, device=DEV)
     phi = torch.zeros_like(x)
-    info = lmdg.lmdg_solve(s.h, "rlmdg", "mixed", 1e-11, 60, 20000, x, phi)
+    info = lmdg.lmdg_solve(s.h, "rlmdg", "mixed", 1e-12, 60, 20000, x, phi)
     print("8-source mixed solve:", info, flush=True)
     assert info["converged"] == 1
     phi = phi.cpu().numpy().reshape(8, 4 * nc)
-    # both solves stop at a relative residual of 1e-11; this diffusive system
-    # (eps = 0.05, 64 cells across) has a condition number of order 1e4-1e5, so the
-    # solutions agree to about kappa * 1e-11
-    for k in range(8):
-        assert rel_err(phi[k], single[k]) < 1e-6, k
     s.close()
+    errs = []
+    for k in range(8):
+        prob = S.Problem(Mesh(case.n, case.length), case.omega, case.w, case.sigma_s, case.sigma_a, case.eps,
+                         q=q[k])
+        (p0, p1), _ = S.LowMemoryReduced(prob, True).solve(tol=1e-13, restart=200)
+        ref = S.scalar_flux_lm(prob, p0, p1)
+        errs.append(rel_err(abi_to_std(phi[k], nc), ref.ravel()))
+    print("mixed vs oracle, relative max-norm errors:", [f"{e:.2e}" for e in errs], flush=True)
+    assert max(errs) < 1e-6

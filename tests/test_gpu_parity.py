@@ -9,7 +9,7 @@ and quadrature sums over up to 2n sweep steps).
 import numpy as np
 import pytest
 
-from gpu_helpers import Case, abi_to_lm, abi_to_std, lm_to_abi, rel_err, std_to_abi
+from gpu_helpers import Case, abi_to_lm, abi_to_std, lm_to_abi, oracle_sweep, rel_err, std_to_abi
 from oracle import schemes as S
 
 torch = pytest.importorskip("torch")
@@ -31,37 +31,6 @@ def T(a):
 def N(t):
     torch.cuda.synchronize()
     return t.cpu().numpy()
-
-
-def oracle_sweep(case, scheme, x_abi, use_q):
-    """Per-cell reductions of one sweep in the ABI layout, from the oracle's matrices."""
-    prob = case.prob
-    nc = case.ncell
-    if scheme == "std":
-        red = S.StdReduced(prob)
-        phi = abi_to_std(x_abi, nc)
-        src = prob.Mu @ phi
-        rhs = np.broadcast_to(src, (prob.n_dir, src.size)) + (prob.Qu if use_q else 0.0)
-        psi = red.Linv(rhs)                       # (n_dir, nc*4) cell-major
-        out = std_to_abi(prob.w @ psi, nc)
-        psi_abi = psi.reshape(prob.n_dir, nc, 4).transpose(0, 2, 1).ravel()
-        return out, psi_abi
-    red = S.LowMemoryReduced(prob, scheme == "rlmdg")
-    x = abi_to_lm(x_abi, nc)
-    rhs = red.M0 @ x[:nc] + red.L01 @ (red.St @ x[nc:])
-    if use_q:
-        rhs = rhs + red.Qt0
-    psi = red.Lt00_lu.solve(rhs)
-    p0 = red.P0 @ psi
-    g = red.S @ (red.L10 @ psi)
-    if scheme == "rlmdg":
-        g = g + red.S @ (red.L11 @ (red.R @ psi))
-        pr = (red.P1 @ (red.R @ psi)).reshape(nc, 3)
-    g = g.reshape(nc, 3)
-    rows = [p0, g[:, 0], g[:, 1], g[:, 2]]
-    if scheme == "rlmdg":
-        rows += [pr[:, 0], pr[:, 1]]
-    return np.concatenate(rows), psi
 
 
 @pytest.mark.parametrize("shape,order", SHAPES)
@@ -179,3 +148,33 @@ def test_solve_against_direct(scheme, mode):
         ref = S.scalar_flux_lm(case.prob, *S.solve_rlmdg_direct(case.prob))
     assert rel_err(abi_to_std(N(phi), nc), ref.ravel()) < 1e-9
     s.close()
+
+
+@pytest.mark.parametrize("shape,order", SHAPES)
+@pytest.mark.parametrize("scheme", ["std", "lmdg", "rlmdg"])
+def test_fp32_sweep_and_apply_parity(shape, order, scheme):
+    """FP32 sweeps against the oracle on every shape, including the S12 (six waves
+    per workgroup) and S16 (nine waves) sets; bar 2e-5 relative."""
+    print(f"case fp32 {scheme} {shape} S{order}", flush=True)
+    case = Case(shape, order, eps=0.02)
+    s = case.solver()
+    nc = case.ncell
+    nout = 6 if scheme == "rlmdg" else 4
+    x = np.random.default_rng(5).normal(size=4 * nc)
+    errs = []
+    for use_q in (False, True):
+        out = torch.zeros(nout * nc, dtype=torch.float64, device=DEV)
+        lmdg.lmdg_sweep(s.h, scheme, "fp32", T(x), use_q, out)
+        ref, _ = oracle_sweep(case, scheme, x, use_q)
+        errs.append(rel_err(N(out), ref))
+    y = torch.zeros(4 * nc, dtype=torch.float64, device=DEV)
+    lmdg.lmdg_apply(s.h, scheme, "fp32", T(x), y)
+    if scheme == "std":
+        ref_y = std_to_abi(case.reduced("std").apply(abi_to_std(x, nc)), nc)
+    else:
+        ref_y = lm_to_abi(case.reduced(scheme).apply(abi_to_lm(x, nc)), nc)
+    errs.append(rel_err(N(y), ref_y))
+    lmdg.lmdg_synchronize(s.h)
+    s.close()
+    print("fp32 relative errors (sweep, sweep+q, K x):", [f"{e:.2e}" for e in errs], flush=True)
+    assert max(errs) < 2e-5

@@ -51,7 +51,12 @@ class Problem:
     alpha: None (vacuum inflow) or callable alpha(x, omega).
     """
 
-    def __init__(self, mesh: Mesh, omega, w, sigma_s, sigma_a, eps=1.0, q=None, alpha=None):
+    def __init__(self, mesh: Mesh, omega, w, sigma_s, sigma_a, eps=1.0, q=None, alpha=None,
+                 reconstruction="two-cell", suppress=False):
+        if reconstruction not in ("two-cell", "three-cell"):
+            raise ValueError("reconstruction must be 'two-cell' or 'three-cell'")
+        self.recon_kind = reconstruction
+        self.suppress = bool(suppress)
         self.mesh = mesh
         self.omega = np.asarray(omega, dtype=float)
         self.w = np.asarray(w, dtype=float)
@@ -124,6 +129,18 @@ class Problem:
         Sec. 3.3.1: along axis k the slope is delta^{s_k} u^0 with s_k = -sign(Omega_k);
         interior one-sided difference over h, boundary difference with alpha over h/2.
         Legendre coefficient of the slope = delta * h_k / 2 (basis xi_k = 2(x-x_c)/h_k).
+
+        Variants (readings of passages that name them without a formula):
+        * three-cell (RLMDG*, the wider upwind stencil of the discussion of
+          fig-efficiency): where a cell has two upwind neighbours along k, the slope is
+          the derivative at the cell centre of the quadratic with the three cell averages
+          u_i, u_{i-1}, u_{i-2}, (3 u_i - 4 u_{i-1} + u_{i-2}) / (2h), Legendre
+          coefficient (3 u_i - 4 u_{i-1} + u_{i-2}) / 4; with one upwind neighbour the
+          two-cell difference, in the inflow cell the boundary difference as above.
+        * suppress (examp-disccross1): no slope along k in a cell whose upwind
+          neighbour along k has other cross sections (sigma_s/eps or eps sigma_a), and a
+          three-cell stencil falls back to two cells when its far cell differs from the
+          near one.  The inflow cell keeps its boundary difference.
         """
         mesh = self.mesh
         nd, nx, n_p, d = self.n_dir, mesh.n_cells, self.n_p, mesh.dim
@@ -142,10 +159,28 @@ class Problem:
                 nb = mesh.neighbor(k, upwind_side)
                 row = (l * nx + cells) * (n_p - 1) + (lin[k] - 1)
                 inner = nb >= 0
+                nb2 = np.full(nx, -1)
+                nb2[inner] = mesh.neighbor(k, upwind_side)[nb[inner]]
+                if self.suppress:
+                    same = np.zeros(nx, dtype=bool)
+                    same[inner] = self._same_material(cells[inner], nb[inner])
+                    has2 = nb2 >= 0
+                    same2 = np.zeros(nx, dtype=bool)
+                    same2[has2] = self._same_material(nb[has2], nb2[has2])
+                    inner = inner & same
+                    nb2 = np.where(same2, nb2, -1)
+                three = inner & (nb2 >= 0) if self.recon_kind == "three-cell" else np.zeros(nx, dtype=bool)
+                two = inner & ~three
                 coef = (hk / 2.0) / hk                         # interior: difference over h
-                rows += [row[inner], row[inner]]
-                cols += [l * nx + cells[inner], l * nx + nb[inner]]
-                vals += [np.full(inner.sum(), sgn * coef), np.full(inner.sum(), -sgn * coef)]
+                rows += [row[two], row[two]]
+                cols += [l * nx + cells[two], l * nx + nb[two]]
+                vals += [np.full(two.sum(), sgn * coef), np.full(two.sum(), -sgn * coef)]
+                # quadratic through three upwind cell averages: (3 u - 4 u_up + u_upup) / 4
+                rows += [row[three]] * 3
+                cols += [l * nx + cells[three], l * nx + nb[three], l * nx + nb2[three]]
+                vals += [np.full(three.sum(), sgn * 0.75), np.full(three.sum(), -sgn * 1.0),
+                         np.full(three.sum(), sgn * 0.25)]
+                inner = nb >= 0                                # boundary rule below: inflow cells only
                 bnd = ~inner
                 coef_b = (hk / 2.0) / (hk / 2.0)               # inflow cell: difference over h/2
                 rows.append(row[bnd])
@@ -160,6 +195,10 @@ class Problem:
         R1 = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                            shape=(nd * nx * (n_p - 1), nd * nx))
         return R1, r_alpha.ravel()
+
+    def _same_material(self, a, b):
+        """Cells a and b have the same cross sections (sigma_s/eps and eps sigma_a)."""
+        return (self.scat[a] == self.scat[b]) & (self.eps[a] * self.sigma_a[a] == self.eps[b] * self.sigma_a[b])
 
 
 # ---------------------------------------------------------------------------

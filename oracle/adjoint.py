@@ -9,8 +9,16 @@ the adjoint lambda_h in W_h solves  B(u, lambda_h) = J(u) for all u in W_h, and
 Algebraically, with A y = b the assembled system and j = dJ/dy,
     A^T lambda = j,    dJ/dtheta = lambda . (db/dtheta - dA/dtheta y).
 The derivative matrices are assembled by the same Gauss assembly with unit
-per-cell coefficients, so no closed forms enter.  This module covers STD and LMDG
-(Galerkin schemes); RLMDG is Petrov-Galerkin and not treated here.
+per-cell coefficients, so no closed forms enter.
+
+RLMDG is Petrov-Galerkin (eq-rlmdg-vari): trial functions Psi = T_R y + t_alpha carry
+the upwind reconstruction, test functions T z do not, A = T^T (L - M P) T_R.  Its
+adjoint is the transpose of that system, A^T lambda = j, whose solution lives in the
+test space: the adjoint field is T lambda (per-direction cell constants plus isotropic
+slopes), and dJ/dtheta = (T lambda) . (dQ/dtheta - dB/dtheta Psi) with the forward
+field Psi including its reconstructed slopes.  The reconstruction itself does not depend
+on the cross sections (the variant that suppresses it at cross-section jumps is only
+piecewise differentiable and is not covered).
 """
 from __future__ import annotations
 
@@ -19,7 +27,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .dg import Mesh, assemble_mass, assemble_source, assemble_transport, eval_basis, tensor_rule
-from .schemes import Problem, lm_trial_map
+from .schemes import Problem, lm_trial_map, rlm_trial_map
 
 
 def detector_moments(mesh: Mesh, lo, hi, nq=4):
@@ -40,15 +48,27 @@ def detector_moments(mesh: Mesh, lo, hi, nq=4):
 
 
 def _system(prob: Problem, scheme: str):
-    """(A, b, T) with A y = b and Psi = T y for 'std' or 'lmdg'."""
+    """(A, b, T) with A y = b and Psi = T y for 'std' or 'lmdg'; for 'rlmdg' T is the
+    test map and the trial field is given by _trial_field."""
     B = prob.L() - prob.M() @ prob.P()
     if scheme == "std":
         T = sp.identity(B.shape[0], format="csr")
-    elif scheme == "lmdg":
+    elif scheme in ("lmdg", "rlmdg"):
         T = lm_trial_map(prob)
     else:
         raise ValueError(scheme)
+    if scheme == "rlmdg":
+        TR, t_alpha = rlm_trial_map(prob)
+        return (T.T @ B @ TR).tocsc(), T.T @ (prob.Q() - B @ t_alpha), T
     return (T.T @ B @ T).tocsc(), T.T @ prob.Q(), T
+
+
+def _trial_field(prob: Problem, scheme: str, y, T):
+    """Forward angular field (all moments) of the solution y."""
+    if scheme == "rlmdg":
+        TR, t_alpha = rlm_trial_map(prob)
+        return TR @ y + t_alpha
+    return T @ y
 
 
 def functional_vector(prob: Problem, scheme: str, det):
@@ -92,7 +112,7 @@ def gradients(prob: Problem, scheme: str, det):
     zero = _weighted_blocks(prob, np.zeros(nx), np.zeros(nx))
     g_s, g_a, g_q = np.zeros(nx), np.zeros(nx), np.zeros(nx)
     lam_full = T @ lam
-    psi_full = T @ y
+    psi_full = _trial_field(prob, scheme, y, T)
     for K in range(nx):
         e = np.zeros(nx)
         e[K] = 1.0
@@ -110,4 +130,4 @@ def adjoint_flux(prob: Problem, scheme: str, det):
     """Adjoint angular field lambda_h as moments (n_dir, n_x, n_P) and forward Psi."""
     y, lam, J, T = forward_adjoint(prob, scheme, det)
     shape = (prob.n_dir, prob.mesh.n_cells, prob.n_p)
-    return (T @ y).reshape(shape), (T @ lam).reshape(shape), J
+    return _trial_field(prob, scheme, y, T).reshape(shape), (T @ lam).reshape(shape), J

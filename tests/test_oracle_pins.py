@@ -450,7 +450,7 @@ def test_diffusion_limit(scheme):
 
 
 # --------------------------------------------------------------------------- adjoint
-@pytest.mark.parametrize("scheme", ["std", "lmdg"])
+@pytest.mark.parametrize("scheme", ["std", "lmdg", "rlmdg"])
 def test_adjoint_duality_and_finite_differences(scheme):
     mesh = Mesh((4, 3))
     om, w = level_symmetric(4, 2)
@@ -491,7 +491,7 @@ def test_adjoint_gradient_bilinear_forms():
                      q=rng.uniform(0, 1, 12))
     det = ADJ.detector_moments(mesh, np.array([0.3, 0.2]), np.array([0.8, 0.9]))
     ref = ReferenceIntegrals(mesh)
-    for scheme in ("std", "lmdg"):
+    for scheme in ("std", "lmdg", "rlmdg"):
         psi, lam, _ = ADJ.adjoint_flux(prob, scheme, det)
         _, gs, ga, gq = ADJ.gradients(prob, scheme, det)
         wpl = np.einsum("l,lpr,rs,lps->p", w, psi, ref.mass, lam)

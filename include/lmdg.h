@@ -133,8 +133,7 @@ int lmdg_quadrature_level_symmetric(int dim, int order, int capacity, int* n_dir
  * [0, length[0]] x [0, 1] with directions (mu, 0): no y face carries flux, so its 1 and
  * xi moments are the slab scheme's.  Vectors use the 2D layout (4 moments per cell);
  * rows 0 and 1 are the slab moments, rows 2 and 3 (eta, xi eta) carry no slab
- * quantity: zero for STD and LMDG, decoupled values of the transverse reconstruction
- * for RLMDG.  lmdg_adjoint_solve returns UNSUPPORTED on slab handles.
+ * quantity and stay zero (RLMDG reconstructs along x only on slab handles).  lmdg_adjoint_solve returns UNSUPPORTED on slab handles.
  * Errors: INVALID_ARG (NULL pointers, sizes < 1, quadrature violations),
  *         UNSUPPORTED (dim not 1, 2 or 3), HIP_ERROR (allocation).
  */
@@ -205,10 +204,12 @@ int lmdg_set_sources(lmdg_t* h, int n_rhs, const double* q, void* stream);
  * and returns the per-cell sums over directions (device, out_moments x n_cells):
  *   STD:   n_P moments of P Psi
  *   LMDG:  [P_0 Psi ; Sigma L_10 Psi (xi, eta, xi*eta rows)]
- *   RLMDG: [P_0 Psi ; Sigma (L_10 + L_11 R) Psi (3 rows) ; P_1 R Psi (xi, eta)]
- *   3D (rows of Sigma L_10 and Sigma (L_10 + L_11 R) indexed by slope moment 1..7):
+ *   RLMDG: [P_0 Psi ; G Psi (3 rows) ; P_1 R Psi (xi, eta)] with the second block row
+ *          G = Sigma (L_10 + L_11 R) - Sigma M_1 P_1 R of Sec. 3.3.2 (the scattering
+ *          part is taken per direction, where it cancels most of L_11 R)
+ *   3D (rows of Sigma L_10 and G indexed by slope moment 1..7):
  *   LMDG:  [P_0 Psi ; Sigma L_10 Psi (7 rows)]                              8 rows
- *   RLMDG: [P_0 Psi ; Sigma (L_10 + L_11 R) Psi (7 rows) ; P_1 R Psi (xi, eta, zeta)] 11 rows
+ *   RLMDG: [P_0 Psi ; G Psi (7 rows) ; P_1 R Psi (xi, eta, zeta)]           11 rows
  *   x        device moment vector or NULL (= 0)
  *   use_q    1 adds the source Q, 0 omits it
  *   out      device, n_out * n_cells doubles (n_out = 4, 4, 6 for STD, LMDG, RLMDG in
@@ -249,6 +250,27 @@ int lmdg_recover(lmdg_t* h, int scheme, int prec, const double* x, double* phi,
 int lmdg_solve(lmdg_t* h, int scheme, int mode, double tol, int restart, int max_iter,
                const double* x0, double* x_out, double* phi_out, lmdg_info* info,
                void* stream);
+
+/*
+ * Reconstruction of the RLMDG scheme (Sec. 3.3.1) used by every later RLMDG call on
+ * this handle (2D and slab handles).  The paper names two variants without formulas;
+ * the library takes these readings:
+ *   stencil 2   the two-cell upwind difference of Sec. 3.3.1 (the default);
+ *   stencil 3   RLMDG* (discussion of fig-efficiency): in cells with two upwind
+ *               neighbours along an axis the slope is the derivative at the cell centre
+ *               of the quadratic through the three upwind-inclusive cell averages,
+ *               Legendre coefficient s (3 u - 4 u_up + u_upup) / 4; two-cell difference
+ *               with one upwind neighbour, boundary difference in the inflow cell;
+ *   suppress 1  (examp-disccross1) no slope along an axis where the upwind neighbour
+ *               has other cross sections (sigma_s/eps or eps sigma_a); a three-cell
+ *               stencil falls back to two cells when its far cell differs.
+ * With a variant the RLMDG operator is applied in the plain form of eq-nonrec-block
+ * (the defect form that keeps FP32 sweeps accurate at small eps covers the default
+ * reconstruction only), and the sweeps hand four trace values downwind.
+ * Errors: INVALID_ARG (stencil not 2 or 3, suppress not 0 or 1), UNSUPPORTED (a variant
+ * on a 3D handle).
+ */
+int lmdg_set_reconstruction(lmdg_t* h, int stencil, int suppress);
 
 /*
  * Restart augmentation of the handle's GMRES solves (lmdg_solve, lmdg_adjoint_solve

@@ -353,7 +353,8 @@ static int create_impl(int dim, const int64_t* n, const double* length, int n_di
   const long long nc = h->ncell;
   if (dim == 2) {
     h->ws.part_bytes = (size_t)lmdg::part_slices_max(h) * 6 * nc * sizeof(double);
-    h->ws.edge_bytes = (size_t)4 * h->nstrips * n[0] * 3 * h->dslots * sizeof(double);
+    // up to four trace values per direction slot (RLMDG with a reconstruction variant)
+    h->ws.edge_bytes = (size_t)4 * h->nstrips * n[0] * 4 * h->dslots * sizeof(double);
     h->ws.zbuf_bytes = 0;
     h->ws.prog_words = (size_t)4 * h->nstrips;
   } else {
@@ -645,9 +646,12 @@ int check_call(lmdg_t* h, int scheme, int prec) {
 // eq-nonrec-block / eq-sndg-phi, arranged so that no O(sigma_s/eps) terms cancel
 // after the sweep; this is what keeps FP32 sweeps usable at small eps.
 int apply_op(lmdg_t* h, int scheme, int prec, const double* x, double* y, hipStream_t st) {
-  int rc = lmdg::launch_sweep(h, scheme, prec, x, false, nullptr, st, true);
+  // the reconstruction variants of RLMDG use the plain form (eq-nonrec-block applied as
+  // printed: K x = [x_0 - P_0 psi ; B_11 x_1 - G psi])
+  const bool defect = !(scheme == LMDG_SCHEME_RLMDG && h->recon_flags != 0);
+  int rc = lmdg::launch_sweep(h, scheme, prec, x, false, nullptr, st, defect);
   if (rc != LMDG_OK) return rc;
-  lmdg::launch_combine(h, scheme, prec, lmdg::kApplyDefect, x, y, st);
+  lmdg::launch_combine(h, scheme, prec, defect ? lmdg::kApplyDefect : lmdg::kApply, x, y, st);
   return check_hip(h, hipGetLastError(), "combine");
 }
 
@@ -1004,6 +1008,13 @@ int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, doubl
 
 }  // namespace
 
+namespace lmdg {
+// K x for entry points outside this file (lmdg_apply_noalloc).
+int apply_op_impl(lmdg_handle* h, int scheme, int prec, const double* x, double* y, hipStream_t st) {
+  return apply_op(h, scheme, prec, x, y, st);
+}
+}  // namespace lmdg
+
 extern "C" {
 
 int lmdg_sweep(lmdg_t* h, int scheme, int prec, const double* x, int use_q, double* out, double* psi,
@@ -1339,6 +1350,16 @@ int lmdg_set_wait_limit(lmdg_t* h, long long spins, int unreachable) {
     return set_error(h, LMDG_INVALID_ARG, "wait limit out of range");
   h->spin_limit = spins;
   h->wait_bias = (unsigned)unreachable;
+  return LMDG_OK;
+}
+
+int lmdg_set_reconstruction(lmdg_t* h, int stencil, int suppress) {
+  if (!h) return LMDG_INVALID_ARG;
+  if ((stencil != 2 && stencil != 3) || (suppress != 0 && suppress != 1))
+    return set_error(h, LMDG_INVALID_ARG, "stencil must be 2 or 3 and suppress 0 or 1");
+  const int flags = (stencil == 3 ? 1 : 0) | (suppress ? 2 : 0);
+  if (flags && h->dim != 2) return set_error(h, LMDG_UNSUPPORTED, "reconstruction variants on 3D meshes");
+  h->recon_flags = flags;
   return LMDG_OK;
 }
 

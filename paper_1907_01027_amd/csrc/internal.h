@@ -45,6 +45,8 @@ struct SweepParams {
   const double* alpha;   // inflow data [n_dir][nfaces][3] (face average, linear coefficient, midpoint) or null
   const double* qdir;    // direction-dependent source moments eps q_l |K| [n_dir][4][ncell] or null
   int nfaces;            // inflow faces per direction: n_y x faces, then n_x y faces
+  int recon_y;           // 1: RLMDG reconstructs along y; 0 on slab handles
+  int rflags;            // reconstruction variant: bit 0 three-cell, bit 1 suppression, bit 2 y axis
   int defect;            // 1: x enters through the defect source (see lm_source)
   R* part;               // [n_rhs][4][NOUT][ncell] per-quadrant sums
   R* edge;               // [n_rhs][4][nstrips][nx][NF][dslots] top-row traces
@@ -145,6 +147,7 @@ struct lmdg_handle {
   double* d_sq1 = nullptr;
   double* d_sqa = nullptr;
   int last_nsl = 4;                // partial slices written by the last sweep launch
+  int recon_flags = 0;             // RLMDG reconstruction variant (lmdg_set_reconstruction)
   // directions: index of -Omega_l; per quadrant and slot the weight and the slot of
   // -Omega_l in the opposite quadrant (adjoint gradients)
   std::vector<int> neg_dir;

@@ -70,6 +70,7 @@ __device__ __forceinline__ void b11_cell(const double* x, long long nc, int nx, 
 
 struct QuadMoments {
   double w[4], ax[4], ay[4];  // per quadrant: sum w, sum w |Omega_x|, sum w |Omega_y|
+  int recon_y;                // 0 on slab handles: no reconstruction along y (see the sweep)
 };
 
 // G Sigma_0^T x_0: the second block row applied to the isotropic field x_0 copied to
@@ -82,14 +83,13 @@ struct QuadMoments {
 // the inflow cell of the quadrant, traces zero outside the mesh).
 template <bool RLM>
 __device__ __forceinline__ void iso_g(const double* x0, int nx, int ny, int i, int j, double hx, double hy,
-                                      double sigtA, double scatA, const QuadMoments& qm, double g[3]) {
+                                      double absA, const QuadMoments& qm, double g[3]) {
   auto val = [&](int ii, int jj) -> double {
     return (ii >= 0 && ii < nx && jj >= 0 && jj < ny) ? x0[(long long)jj * nx + ii] : 0.0;
   };
   const double v = x0[(long long)j * nx + i];
   const double t3 = 1.0 / 3.0;
   g[0] = g[1] = g[2] = 0.0;
-  double prx = 0.0, pry = 0.0;  // P_1 R x_0
   for (int q = 0; q < 4; ++q) {
     const int sx = (q & 1) ? -1 : 1, sy = (q & 2) ? -1 : 1;
     const double W = qm.w[q], AX = qm.ax[q], AY = qm.ay[q];
@@ -102,7 +102,7 @@ __device__ __forceinline__ void iso_g(const double* x0, int nx, int ny, int i, i
       continue;
     }
     const double u2 = val(i - 2 * sx, j), d2 = val(i, j - 2 * sy), ud = val(i - sx, j - sy);
-    const double kx = upx ? 0.5 : 1.0, ky = upy ? 0.5 : 1.0;
+    const double kx = upx ? 0.5 : 1.0, ky = qm.recon_y ? (upy ? 0.5 : 1.0) : 0.0;
     // is the upwind neighbour itself the inflow cell of its line?
     const double kxu = (sx > 0 ? i - 1 == 0 : i + 1 == nx - 1) ? 1.0 : 0.5;
     const double kyd = (sy > 0 ? j - 1 == 0 : j + 1 == ny - 1) ? 1.0 : 0.5;
@@ -112,15 +112,10 @@ __device__ __forceinline__ void iso_g(const double* x0, int nx, int ny, int i, i
     const double tyd = upy ? d1 + kyd * (d1 - d2) : 0.0;
     const double cxi_d = upy ? sx * kx * (d1 - ud) : 0.0;    // xi slope of the cell below
     const double ceta_u = upx ? sy * ky * (u1 - ud) : 0.0;   // eta slope of the cell on the left
-    g[0] += sx * AX * hy * (txu - v) + (sigtA * t3 * W + AX * hy + AY * hx * t3) * cxi - AY * hx * t3 * cxi_d;
-    g[1] += sy * AY * hx * (tyd - v) + (sigtA * t3 * W + AY * hx + AX * hy * t3) * ceta - AX * hy * t3 * ceta_u;
+    // slope mass terms: sigma_t|K|/3 of L_11 R minus (sigma_s/eps)|K|/3 of M_1 P_1 R
+    g[0] += sx * AX * hy * (txu - v) + (absA * t3 * W + AX * hy + AY * hx * t3) * cxi - AY * hx * t3 * cxi_d;
+    g[1] += sy * AY * hx * (tyd - v) + (absA * t3 * W + AY * hx + AX * hy * t3) * ceta - AX * hy * t3 * ceta_u;
     g[2] += t3 * (sx * AX * hy * (ceta_u - ceta) + sy * AY * hx * (cxi_d - cxi));
-    prx += W * cxi;
-    pry += W * ceta;
-  }
-  if (RLM) {
-    g[0] -= scatA * t3 * prx;
-    g[1] -= scatA * t3 * pry;
   }
 }
 
@@ -140,8 +135,7 @@ __device__ __forceinline__ void iso_g(const double* x0, int nx, int ny, int i, i
 template <typename R, bool RLM>
 __global__ void combine_lm_kernel(int mode, int nr, int nsl, int nx, int ny, double hx, double hy, double cxp, double cxm,
                                   double cyp, double cym, QuadMoments qm, const double* __restrict__ x_all,
-                                  const R* __restrict__ part_all, const double* __restrict__ sigtA,
-                                  const double* __restrict__ scatA, const double* __restrict__ absA,
+                                  const R* __restrict__ part_all, const double* __restrict__ absA,
                                   const double* __restrict__ sq1, const double* __restrict__ sqa,
                                   double* __restrict__ out_all) {
   constexpr int NOUT = RLM ? 6 : 3;
@@ -160,9 +154,8 @@ __global__ void combine_lm_kernel(int mode, int nr, int nsl, int nx, int ny, dou
       for (int q = 0; q < nsl; ++q) acc += (double)part[((long long)q * NOUT + m) * nc + p];
       s[m] = acc;
     }
-    const double sl = RLM ? scatA[p] * (1.0 / 3.0) : 0.0;  // Sigma M_1 on the xi, eta slopes
-    const double g1 = s[1] - (RLM ? sl * s[4] : 0.0);
-    const double g2 = s[2] - (RLM ? sl * s[5] : 0.0);
+    // the sweep's slope rows already hold G Psi (with Sigma M_1 P_1 R taken per direction)
+    const double g1 = s[1], g2 = s[2];
     const double g3 = RLM ? s[3] : 0.0;
     if (mode == kApply) {
       const int i = (int)(p % nx), j = (int)(p / nx);
@@ -176,7 +169,7 @@ __global__ void combine_lm_kernel(int mode, int nr, int nsl, int nx, int ny, dou
       const int i = (int)(p % nx), j = (int)(p / nx);
       double ya, yb, yc, gi[3];
       b11_cell(x, nc, nx, ny, i, j, hx, hy, cxp, cxm, cyp, cym, absA[p], ya, yb, yc);
-      iso_g<RLM>(x, nx, ny, i, j, hx, hy, sigtA[p], scatA[p], qm, gi);
+      iso_g<RLM>(x, nx, ny, i, j, hx, hy, absA[p], qm, gi);
       out[p] = s[0];
       out[nc + p] = ya - gi[0] + g1;
       out[2 * nc + p] = yb - gi[1] + g2;
@@ -405,6 +398,7 @@ void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double
   }
   const double hx = h->h[0], hy = h->h[1];
   QuadMoments qm;
+  qm.recon_y = h->slab ? 0 : 1;
   for (int q = 0; q < 4; ++q) {
     qm.w[q] = h->qw[q];
     qm.ax[q] = h->qax[q];
@@ -413,7 +407,7 @@ void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double
 #define LMDG_COMBINE(R, RLM)                                                                        \
   hipLaunchKernelGGL((combine_lm_kernel<R, RLM>), dim3(g), dim3(kBlock), 0, st, mode, nr, h->last_nsl, nx, ny, hx, hy, \
                      h->cplus[0], h->cminus[0], h->cplus[1], h->cminus[1], qm, x,                    \
-                     (const R*)h->ws.part, h->d_sigtA, h->d_scatA, h->d_absA, sq1, sqa, out)
+                     (const R*)h->ws.part, h->d_absA, sq1, sqa, out)
   const bool rlm = scheme == LMDG_SCHEME_RLMDG;
   // right-hand-side corrections of the handle's own source data (not of an adjoint source)
   const bool own = mode == kRhs && !h->src0;

@@ -70,11 +70,10 @@ __device__ void b11_cell3(const double* x, long long nc, const Geo3& g, const in
 // sweep kernel evaluated with psi = x_0; upwind slopes k (u - u_up), k = 1 in the
 // inflow cell of a line, traces zero outside the mesh).  Rows indexed by moment.
 template <bool RLM>
-__device__ void iso_g3(const double* x0, const Geo3& g, const int idx[3], long long p, double sigtA, double scatA,
+__device__ void iso_g3(const double* x0, const Geo3& g, const int idx[3], long long p, double absA,
                        const OctMoments& om, double out[8]) {
   for (int m = 0; m < 8; ++m) out[m] = 0.0;
   const double v = x0[p];
-  double pr[3] = {0, 0, 0};
   for (int o = 0; o < 8; ++o) {
     int s[3];
     for (int a = 0; a < 3; ++a) s[a] = ((o >> a) & 1) ? -1 : 1;
@@ -110,7 +109,8 @@ __device__ void iso_g3(const double* x0, const Geo3& g, const int idx[3], long l
         const bool up_first = s[a] > 0 ? idx[a] - 1 == 0 : idx[a] + 1 == g.n[a] - 1;
         T = up[a] + (up_first ? 1.0 : 0.5) * (up[a] - val(nb, a));
       }
-      double row = s[a] * g.A[a] * om.a[o][a] * (T - v) + g.A[a] * om.a[o][a] * c[a] + sigtA / 3.0 * W * c[a];
+      // slope mass term: sigma_t V / 3 of L_11 R minus (sigma_s/eps) V / 3 of M_1 P_1 R
+      double row = s[a] * g.A[a] * om.a[o][a] * (T - v) + g.A[a] * om.a[o][a] * c[a] + absA / 3.0 * W * c[a];
       for (int b = 0; b < 3; ++b) {
         if (b == a) continue;
         // a-slope of the b-upwind cell (it shares K's index along a, so the same k_a)
@@ -118,7 +118,6 @@ __device__ void iso_g3(const double* x0, const Geo3& g, const int idx[3], long l
         row += g.A[b] * om.a[o][b] * (c[a] - cab) / 3.0;
       }
       out[nb] += row;
-      pr[a] += W * c[a];
     }
     for (int a = 0; a < 3; ++a)
       for (int b = a + 1; b < 3; ++b) {
@@ -128,8 +127,6 @@ __device__ void iso_g3(const double* x0, const Geo3& g, const int idx[3], long l
                                      s[b] * g.A[b] * om.a[o][b] * (cab - c[a])) / 3.0;
       }
   }
-  if (RLM)
-    for (int a = 0; a < 3; ++a) out[1 << a] -= scatA / 3.0 * pr[a];
 }
 
 // K x, right-hand side and recovery from the per-octant sweep sums (3D analogue of
@@ -137,8 +134,7 @@ __device__ void iso_g3(const double* x0, const Geo3& g, const int idx[3], long l
 // eta zeta rows, P_1 R xi, eta, zeta)].
 template <typename R, bool RLM>
 __global__ void combine3_kernel(int mode, int nr, Geo3 g, OctMoments om, const double* __restrict__ x_all,
-                                const R* __restrict__ part_all, const double* __restrict__ sigtA,
-                                const double* __restrict__ scatA, const double* __restrict__ absA,
+                                const R* __restrict__ part_all, const double* __restrict__ absA,
                                 double* __restrict__ out_all) {
   constexpr int NOUT = RLM ? 10 : 4;
   const long long nc = (long long)g.n[0] * g.n[1] * g.n[2];
@@ -156,12 +152,12 @@ __global__ void combine3_kernel(int mode, int nr, Geo3 g, OctMoments om, const d
       for (int o = 0; o < 8; ++o) acc += (double)part[((long long)o * NOUT + m) * nc + p];
       s[m] = acc;
     }
-    const double corr = RLM ? scatA[p] / 3.0 : 0.0;  // Sigma M_1 on the single-axis slopes
+    // the sweep's slope rows already hold G Psi (Sigma M_1 P_1 R taken per direction)
     double gr[8];
     gr[0] = 0.0;
-    gr[1] = s[1] - (RLM ? corr * s[7] : 0.0);
-    gr[2] = s[2] - (RLM ? corr * s[8] : 0.0);
-    gr[4] = s[3] - (RLM ? corr * s[9] : 0.0);
+    gr[1] = s[1];
+    gr[2] = s[2];
+    gr[4] = s[3];
     gr[3] = RLM ? s[4] : 0.0;
     gr[5] = RLM ? s[5] : 0.0;
     gr[6] = RLM ? s[6] : 0.0;
@@ -174,7 +170,7 @@ __global__ void combine3_kernel(int mode, int nr, Geo3 g, OctMoments om, const d
         out[p] = x[p] - s[0];
         for (int m = 1; m < 8; ++m) out[m * nc + p] = y[m] - gr[m];
       } else {
-        iso_g3<RLM>(x, g, idx, p, sigtA[p], scatA[p], om, gi);
+        iso_g3<RLM>(x, g, idx, p, absA[p], om, gi);
         out[p] = s[0];
         for (int m = 1; m < 8; ++m) out[m * nc + p] = y[m] - gi[m] + gr[m];
       }
@@ -261,7 +257,7 @@ void launch_combine3(lmdg_handle* h, int scheme, int prec, int mode, const doubl
   const bool rlm = scheme == LMDG_SCHEME_RLMDG;
 #define LMDG_COMBINE3(R, RLM)                                                                                  \
   hipLaunchKernelGGL((combine3_kernel<R, RLM>), dim3(grid), dim3(kBlock3), 0, st, mode, nr, g, om, x,          \
-                     (const R*)h->ws.part, h->d_sigtA, h->d_scatA, h->d_absA, out)
+                     (const R*)h->ws.part, h->d_absA, out)
   if (prec == LMDG_PREC_FP64) {
     if (rlm) LMDG_COMBINE3(double, true); else LMDG_COMBINE3(double, false);
   } else {

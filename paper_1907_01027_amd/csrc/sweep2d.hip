@@ -56,9 +56,21 @@ struct Dir {
 template <int S>
 struct SrcTraits {
   static constexpr int NS = (S == LMDG_SCHEME_STD) ? 4 : 1;
-  static constexpr int NC = 1 + 3 * NS;  // sigma_t|K| and 3 source coefficients per moment
+  // sigma_t|K|, 3 source coefficients per moment, and for RLMDG eps sigma_a|K|
+  static constexpr int NC = 1 + 3 * NS + (S == LMDG_SCHEME_RLMDG ? 1 : 0);
   static constexpr int NRAW = (S == LMDG_SCHEME_STD) ? 19 : 13;
   static constexpr int MAXC = (S == LMDG_SCHEME_STD) ? 1 : 2;  // staged cells per thread
+};
+
+// With the reconstruction variants (VAR, RLMDG only) every cell also stages its upwind
+// rule per axis (a_up, a_uu; see cell_rlmdg_var) and loads the cross sections of its
+// two upwind neighbours along each axis; cells hand one more trace value downwind
+// (their own upwind average).
+template <int S, bool VAR>
+struct SrcTraitsV : SrcTraits<S> {
+  static constexpr int NC = SrcTraits<S>::NC + (VAR ? 4 : 0);
+  static constexpr int NRAW = SrcTraits<S>::NRAW + (VAR ? 8 : 0);
+  static constexpr int NF = SchemeTraits<S>::NF + (VAR ? 1 : 0);
 };
 
 // ---------------------------------------------------------------- local solves
@@ -86,10 +98,15 @@ __device__ __forceinline__ void cell_lmdg(const Dir<R>& d, R src, R inv, const R
 // (where the upwind value is the inflow datum: zero for vacuum, the midpoint value of
 // alpha otherwise).  inv = 1 / (sigma_t|K| + |Ox| h_y (1 + k_x) + |Oy| h_x (1 + k_y)).
 // A face hands downwind its trace average T, its linear coefficient along the face,
-// and the cell average.  Reductions: w psi, the xi / eta / xi*eta rows of
-// w (L_10 + L_11 R) applied to the cell function, and w c_xi, w c_eta (for P_1 R).
+// and the cell average.  Reductions: w psi; the xi / eta / xi*eta rows of
+// w (L_10 + L_11 R) applied to the cell function minus the scattering part w M_1 R of
+// the second block row G = Sigma (L_10 + L_11 R) - Sigma M_1 P_1 R (the slope mass
+// term of L_11 R carries sigma_t |K| / 3, that of M_1 P_1 R (sigma_s/eps) |K| / 3, so
+// per direction they combine to eps sigma_a |K| / 3 = aA3: the O(sigma_s/eps) parts
+// cancel before any rounding instead of after the direction sum); and w c_xi,
+// w c_eta (for P_1 R).
 template <typename R>
-__device__ __forceinline__ void cell_rlmdg(const Dir<R>& d, R src, R sigtA, R inv, R kx, R ky, const R* xin,
+__device__ __forceinline__ void cell_rlmdg(const Dir<R>& d, R src, R aA3, R inv, R kx, R ky, const R* xin,
                                            const R* ydn, R* xo, R* yo, R* o, R& psi_out) {
   // xin = (T_x of left cell, its c_eta, its average); ydn = (T_y, c_xi, average) of cell below
   const R third = R(1) / R(3);
@@ -102,10 +119,44 @@ __device__ __forceinline__ void cell_rlmdg(const Dir<R>& d, R src, R sigtA, R in
   yo[0] = psi + ky * (psi - ydn[2]);
   yo[1] = cxi;
   yo[2] = psi;
-  const R sA3 = sigtA * third;
   o[0] = d.w * psi;
-  o[1] = d.w * (d.oxhy * (xin[0] - psi) + (sA3 + d.axhy + d.ayhx * third) * cxi - d.ayhx * third * ydn[1]);
-  o[2] = d.w * (d.oyhx * (ydn[0] - psi) + (sA3 + d.ayhx + d.axhy * third) * ceta - d.axhy * third * xin[1]);
+  o[1] = d.w * (d.oxhy * (xin[0] - psi) + (aA3 + d.axhy + d.ayhx * third) * cxi - d.ayhx * third * ydn[1]);
+  o[2] = d.w * (d.oyhx * (ydn[0] - psi) + (aA3 + d.ayhx + d.axhy * third) * ceta - d.axhy * third * xin[1]);
+  o[3] = d.w * third * (d.oxhy * (xin[1] - ceta) + d.oyhx * (ydn[1] - cxi));
+  o[4] = d.w * cxi;
+  o[5] = d.w * ceta;
+  psi_out = psi;
+}
+
+// Reconstructed sweep with a per-cell upwind rule (the reconstruction variants): along
+// each axis the slope is c = s (k psi - a_up psi_up + a_uu psi_upup) with k = a_up - a_uu
+// (constants have no slope): (a_up, a_uu) = (1, 0) in the inflow cell (psi_up the
+// inflow value), (1/2, 0) for the two-cell difference, (1, 1/4) for the three-cell
+// quadratic (3 psi - 4 psi_up + psi_upup) / 4, (0, 0) where the reconstruction is
+// suppressed.  Traces handed downwind: (outflow face average, linear coefficient along
+// the face, cell average, the cell's own upwind average along that axis).
+template <typename R>
+__device__ __forceinline__ void cell_rlmdg_var(const Dir<R>& d, R src, R aA3, R inv, const R* ru, const R* xin,
+                                               const R* ydn, R* xo, R* yo, R* o, R& psi_out) {
+  const R third = R(1) / R(3);
+  const R psi = (src + d.axhy * (xin[0] + ru[0] * xin[2] - ru[1] * xin[3]) +
+                 d.ayhx * (ydn[0] + ru[2] * ydn[2] - ru[3] * ydn[3])) *
+                inv;
+  const R dx = (ru[0] - ru[1]) * psi - ru[0] * xin[2] + ru[1] * xin[3];  // = s_x c_xi
+  const R dy = (ru[2] - ru[3]) * psi - ru[2] * ydn[2] + ru[3] * ydn[3];
+  const R cxi = d.sx * dx;
+  const R ceta = d.sy * dy;
+  xo[0] = psi + dx;
+  xo[1] = ceta;
+  xo[2] = psi;
+  xo[3] = xin[2];
+  yo[0] = psi + dy;
+  yo[1] = cxi;
+  yo[2] = psi;
+  yo[3] = ydn[2];
+  o[0] = d.w * psi;
+  o[1] = d.w * (d.oxhy * (xin[0] - psi) + (aA3 + d.axhy + d.ayhx * third) * cxi - d.ayhx * third * ydn[1]);
+  o[2] = d.w * (d.oyhx * (ydn[0] - psi) + (aA3 + d.ayhx + d.axhy * third) * ceta - d.axhy * third * xin[1]);
   o[3] = d.w * third * (d.oxhy * (xin[1] - ceta) + d.oyhx * (ydn[1] - cxi));
   o[4] = d.w * cxi;
   o[5] = d.w * ceta;
@@ -200,10 +251,10 @@ __device__ __forceinline__ void cell_std(const Dir<R>& d, const R* src, R sigtA,
 //   STD:        the 4 moments at the cell, at its x-upwind and y-upwind neighbours,
 //               and the same four material values
 // Values outside the mesh are zero (zero exterior traces, vacuum inflow).
-template <typename R, int S>
+template <typename R, int S, bool VAR = false>
 __device__ __forceinline__ void raw_load(const SweepParams<R>& P, const double* x, const double* qA, int sxi, int syi,
                                          int c, int jr, double* raw) {
-  constexpr int NRAW = SrcTraits<S>::NRAW;
+  constexpr int NRAW = SrcTraitsV<S, VAR>::NRAW;
 #pragma unroll
   for (int k = 0; k < NRAW; ++k) raw[k] = 0.0;
   if (c < 0 || c >= P.nx || jr >= P.ny) return;
@@ -250,7 +301,27 @@ __device__ __forceinline__ void raw_load(const SweepParams<R>& P, const double* 
     raw[10] = P.absA[cell];
     raw[11] = P.scatA[cell];
     raw[12] = qA ? qA[cell] : 0.0;
+    if constexpr (VAR) {
+      // cross sections of the two upwind neighbours along x and along y
+      if (c > 0) { raw[13] = P.scatA[cell - sxs]; raw[14] = P.absA[cell - sxs]; }
+      if (c > 1) { raw[15] = P.scatA[cell - 2 * sxs]; raw[16] = P.absA[cell - 2 * sxs]; }
+      if (jr > 0) { raw[17] = P.scatA[cell - sys]; raw[18] = P.absA[cell - sys]; }
+      if (jr > 1) { raw[19] = P.scatA[cell - 2 * sys]; raw[20] = P.absA[cell - 2 * sys]; }
+    }
   }
+}
+
+// Upwind rule (a_up, a_uu) along one axis of a cell with `pos` upwind cells inside the
+// mesh; same1: the cell and its upwind neighbour have the same cross sections, same2:
+// that neighbour and the next one do.  rflags: bit 0 three-cell stencil, bit 1
+// suppression at cross-section jumps.
+__device__ __forceinline__ void upwind_rule(int pos, bool same1, bool same2, int rflags, double& a_up,
+                                            double& a_uu) {
+  const bool three = rflags & 1, suppress = rflags & 2;
+  if (pos == 0) { a_up = 1.0; a_uu = 0.0; }
+  else if (suppress && !same1) { a_up = 0.0; a_uu = 0.0; }
+  else if (three && pos >= 2 && !(suppress && !same2)) { a_up = 1.0; a_uu = 0.25; }
+  else { a_up = 0.5; a_uu = 0.0; }
 }
 
 // Source coefficients of one cell (FP64 arithmetic, stored in the sweep precision).
@@ -272,9 +343,9 @@ __device__ __forceinline__ void raw_load(const SweepParams<R>& P, const double* 
 //   factor (1, Ox, Oy, |Ox|, |Oy|) each term carries.
 // Within a quadrant Ox = sx |Ox| and Oy = sy |Oy|, so the five factors fold into
 // three stored coefficients per moment: src = a + |Ox| b + |Oy| c.
-template <typename R, int S>
+template <typename R, int S, bool VAR = false>
 __device__ __forceinline__ void raw_coef(const double* raw, int c, int jr, int sxi, int syi, double hx,
-                                         double hy, bool defect, R* coef, int cstride) {
+                                         double hy, bool defect, R* coef, int cstride, int rflags = 0) {
   if constexpr (S == LMDG_SCHEME_STD) {
     const double* p = raw;       // moments at the cell
     const double* u = raw + 4;   // x-upwind neighbour
@@ -344,6 +415,24 @@ __device__ __forceinline__ void raw_coef(const double* raw, int c, int jr, int s
     coef[1 * cstride] = (R)c0;
     coef[2 * cstride] = (R)(sxi * c1 + c3);  // |Ox| factor (Ox = sx |Ox| in the quadrant)
     coef[3 * cstride] = (R)(syi * c2 + c4);  // |Oy| factor
+    if (S == LMDG_SCHEME_RLMDG) coef[4 * cstride] = (R)(absA * (1.0 / 3.0));
+    if constexpr (VAR) {
+      // upwind rules along x and y (no y rule on slab handles, rflags bit 2 clear)
+      // cross sections (sigma_s/eps |K|, eps sigma_a |K|): cell raw[11], raw[10]; x-upwind
+      // raw[13], raw[14] and the next raw[15], raw[16]; y likewise at raw[17..20]
+      const bool same1x = raw[11] == raw[13] && raw[10] == raw[14];
+      const bool same2x = raw[13] == raw[15] && raw[14] == raw[16];
+      const bool same1y = raw[11] == raw[17] && raw[10] == raw[18];
+      const bool same2y = raw[17] == raw[19] && raw[18] == raw[20];
+      double axu, axuu, ayu, ayuu;
+      upwind_rule(c, same1x, same2x, rflags, axu, axuu);
+      upwind_rule(jr, same1y, same2y, rflags, ayu, ayuu);
+      if (!(rflags & 4)) ayu = ayuu = 0.0;
+      coef[5 * cstride] = (R)axu;
+      coef[6 * cstride] = (R)axuu;
+      coef[7 * cstride] = (R)ayu;
+      coef[8 * cstride] = (R)ayuu;
+    }
   }
 }
 
@@ -362,14 +451,17 @@ __device__ __forceinline__ void raw_coef(const double* raw, int c, int jr, int s
 // trace a0 + a1 t; LMDG: its average; RLMDG: trace average, its linear coefficient
 // and the upwind value that the reconstruction of Sec. 3.3.1 takes in the inflow
 // cell).  Per-direction source moments are added to the staged isotropic source.
-template <typename R, int S, int MAXW, bool DIRECT, bool DATA = false>
+// VAR (RLMDG): the reconstruction variants, with a per-cell upwind rule staged beside
+// the source coefficients (cell_rlmdg_var); used with the plain form of the source.
+template <typename R, int S, int MAXW, bool DIRECT, bool DATA = false, bool VAR = false>
 __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
+  static_assert(!VAR || S == LMDG_SCHEME_RLMDG, "reconstruction variants are RLMDG sweeps");
   constexpr int NOUT = SchemeTraits<S>::NOUT;
   constexpr int NOUTP = (NOUT + 3) & ~3;  // rows of red, padded to whole lane groups
-  constexpr int NF = SchemeTraits<S>::NF;
+  constexpr int NF = SrcTraitsV<S, VAR>::NF;
   constexpr int NS = SrcTraits<S>::NS;
-  constexpr int NC = SrcTraits<S>::NC;
-  constexpr int NRAW = SrcTraits<S>::NRAW;
+  constexpr int NC = SrcTraitsV<S, VAR>::NC;
+  constexpr int NRAW = SrcTraitsV<S, VAR>::NRAW;
   // staged cells per thread: the 9-wave variant has threads for a whole chunk
   constexpr int MAXC = MAXW > 4 ? 1 : SrcTraits<S>::MAXC;
   constexpr bool LM = S != LMDG_SCHEME_STD;
@@ -436,7 +528,9 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
     const int jr = s * kRows + r;  // row in sweep order
     const bool row_ok = jr < ny;
     const int j = syi > 0 ? jr : ny - 1 - jr;
-    const R ky = (jr == 0) ? R(1) : R(0.5);
+    // slab handles (every Omega_y = 0) reconstruct along x only: a y slope would only
+    // feed the decoupled eta rows, whose block scales with eps sigma_a
+    const R ky = P.recon_y ? ((jr == 0) ? R(1) : R(0.5)) : R(0);
 
     // staging of chunk k's cells: thread handles cells e = tid + m * blockDim,
     // e -> (row e / cw, step e % cw) so consecutive threads read consecutive columns
@@ -447,7 +541,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
         const int e = tid + m * blockDim.x;
         const int rr = e >> lcw, tt = e & (cw - 1);
         const int c = (e < ncells) ? (k << lcw) + tt - rr : -1;
-        raw_load<R, S>(P, xr, qAr, sxi, syi, c, s * kRows + rr, raw[m]);
+        raw_load<R, S, VAR>(P, xr, qAr, sxi, syi, c, s * kRows + rr, raw[m]);
       }
     };
     auto stage_store = [&](int k, int buf) {
@@ -456,8 +550,8 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
         const int e = tid + m * blockDim.x;
         if (e < ncells) {
           const int rr = e >> lcw, tt = e & (cw - 1);
-          raw_coef<R, S>(raw[m], (k << lcw) + tt - rr, s * kRows + rr, sxi, syi, P.hx, P.hy, P.defect != 0,
-                         coef + (size_t)buf * NC * ncells + (tt << 4) + rr, ncells);
+          raw_coef<R, S, VAR>(raw[m], (k << lcw) + tt - rr, s * kRows + rr, sxi, syi, P.hx, P.hy, P.defect != 0,
+                              coef + (size_t)buf * NC * ncells + (tt << 4) + rr, ncells, P.rflags);
         }
       }
     };
@@ -470,7 +564,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
       if (P.alpha && row_ok && d.idx >= 0) {
         const double* a = P.alpha + ((long long)d.idx * P.nfaces + j) * 3;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) gx[f] = (R)a[f];
+        for (int f = 0; f < NF; ++f) gx[f] = f < 3 ? (R)a[f] : R(0);
       }
     }
 
@@ -504,14 +598,14 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
               const int sl = e % P.dslots, f = (e / P.dslots) % NF;
               const int l = (int)P.dirs[((long long)q * P.dslots + sl) * kDirStride + 3];
               const int i = sxi > 0 ? c : nx - 1 - c;
-              if (l >= 0) v = (R)P.alpha[((long long)l * P.nfaces + ny + i) * 3 + f];
+              if (l >= 0 && f < 3) v = (R)P.alpha[((long long)l * P.nfaces + ny + i) * 3 + f];
             }
           }
           eds[e] = v;
         }
       }
       if (k + 1 < P.nchunks) stage_load(k + 1);  // overlaps the step loop below
-      __syncthreads();
+      lds_barrier();  // staged traces and coefficients visible; the prefetch stays in flight
 
       const R* cbuf = coef + (size_t)buf * NC * ncells;
       // Steps run in fully unrolled groups of U: the source, sigma_t, reciprocal of the
@@ -521,7 +615,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
       // wave can overlap the latencies itself.
       constexpr int U = step_group<R>();
       for (int tg = 0; tg < cw; tg += U) {
-        R src_g[U][NS], sig_g[U], inv_g[U], edn_g[U][NF];
+        R src_g[U][NS], sig_g[U], inv_g[U], edn_g[U][NF], ru_g[U][VAR ? 4 : 1];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int tt = tg + u;
@@ -542,6 +636,11 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
           }
           if constexpr (S == LMDG_SCHEME_LMDG) {
             inv_g[u] = recip(sig_g[u] + d.axhy + d.ayhx);
+          } else if constexpr (VAR) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) ru_g[u][e] = cf[(5 + e) * ncells];
+            inv_g[u] = recip(sig_g[u] + d.axhy * (R(1) + ru_g[u][0] - ru_g[u][1]) +
+                             d.ayhx * (R(1) + ru_g[u][2] - ru_g[u][3]));
           } else if constexpr (S == LMDG_SCHEME_RLMDG) {
             const R kx = (t0 + tt - r == 0) ? R(1) : R(0.5);
             inv_g[u] = recip(sig_g[u] + d.axhy * (R(1) + kx) + d.ayhx * (R(1) + ky));
@@ -570,9 +669,13 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
             cell_std<R>(d, src_g[u], sig_g[u], xin, ydn, xo, yo, o, psi_g[u]);
           } else if constexpr (S == LMDG_SCHEME_LMDG) {
             cell_lmdg<R>(d, src_g[u][0], inv, xin, ydn, xo, yo, o, psi_g[u][0]);
+          } else if constexpr (VAR) {
+            cell_rlmdg_var<R>(d, src_g[u][0], cbuf[((tt << 4) + r) + 4 * ncells], inv, ru_g[u], xin, ydn, xo, yo, o,
+                              psi_g[u][0]);
           } else {
             const R kx = (c == 0) ? R(1) : R(0.5);
-            cell_rlmdg<R>(d, src_g[u][0], sig_g[u], inv, kx, ky, xin, ydn, xo, yo, o, psi_g[u][0]);
+            cell_rlmdg<R>(d, src_g[u][0], cbuf[((tt << 4) + r) + 4 * ncells], inv, kx, ky, xin, ydn, xo, yo, o,
+                          psi_g[u][0]);
           }
 #pragma unroll
           for (int f = 0; f < NF; ++f) {
@@ -676,11 +779,11 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
   }
 }
 
-template <typename R, int S>
+template <typename R, int S, bool VAR = false>
 size_t lds_bytes(int cw, int W, int dslots, bool direct) {
   constexpr int NOUT = SchemeTraits<S>::NOUT;
-  constexpr int NF = SchemeTraits<S>::NF;
-  constexpr int NC = SrcTraits<S>::NC;
+  constexpr int NF = SrcTraitsV<S, VAR>::NF;
+  constexpr int NC = SrcTraitsV<S, VAR>::NC;
   constexpr int NOUTP = (NOUT + 3) & ~3;
   const size_t red = direct ? 0 : (size_t)cw * (W * NOUTP * kRows + 1);  // cross-wave sums
   return (red + (size_t)2 * cw * kRows * NC + (size_t)cw * NF * dslots) * sizeof(R);
@@ -703,11 +806,15 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   // inflow data and direction-dependent sources belong to the handle's own source
   // (not to the detector source of an adjoint solve)
   const bool data = use_q && !h->src0 && (h->d_alpha || h->d_qdir);
-  const bool direct = !data && part_slices(h, S, sizeof(R) == 8 ? LMDG_PREC_FP64 : LMDG_PREC_FP32) > 4;
+  // reconstruction variants (RLMDG): their own kernel, always with the plain source
+  constexpr bool kRlm = S == LMDG_SCHEME_RLMDG;
+  const bool var = kRlm && h->recon_flags != 0;
+  const bool direct = !data && !var && part_slices(h, S, sizeof(R) == 8 ? LMDG_PREC_FP64 : LMDG_PREC_FP32) > 4;
   h->last_nsl = direct ? 4 * W : 4;  // slices of the partials the combine adds
-  while (cw > step_group<R>() &&
-         (kRows * cw > maxc * 64 * W || lds_bytes<R, S>(cw, W, h->dslots, direct) > kLdsBudget))
-    cw >>= 1;
+  auto lds_of = [&](int c) {
+    return var ? lds_bytes<R, S, kRlm>(c, W, h->dslots, direct) : lds_bytes<R, S>(c, W, h->dslots, direct);
+  };
+  while (cw > step_group<R>() && (kRows * cw > maxc * 64 * W || lds_of(cw) > kLdsBudget)) cw >>= 1;
   P.cw = cw;
   P.lcw = 0;
   while ((1 << P.lcw) < cw) ++P.lcw;
@@ -731,13 +838,15 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   P.alpha = data ? h->d_alpha : nullptr;
   P.qdir = data ? h->d_qdir : nullptr;
   P.nfaces = (int)(h->n[0] + h->n[1]);
+  P.recon_y = h->slab ? 0 : 1;
+  P.rflags = h->recon_flags | (h->slab ? 0 : 4);
   P.absA = h->d_absA;
-  P.defect = defect ? 1 : 0;
+  P.defect = (defect && !var) ? 1 : 0;
   P.part = reinterpret_cast<R*>(h->ws.part);
   P.edge = reinterpret_cast<R*>(h->ws.edge);
   P.psi = psi;
   P.psi_rstride = (long long)h->ndir * (S == LMDG_SCHEME_STD ? 4 : 1) * h->ncell;
-  P.edge_rstride = (long long)4 * h->nstrips * P.nx * SchemeTraits<S>::NF * h->dslots;
+  P.edge_rstride = (long long)4 * h->nstrips * P.nx * (SchemeTraits<S>::NF + (var ? 1 : 0)) * h->dslots;
   P.prog = h->ws.prog;
   P.ticket = h->ws.ticket;
   P.err = h->ws.err;
@@ -746,7 +855,7 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   P.spin_limit = h->spin_limit;
   P.wait_bias = h->wait_bias;
   const int grid = std::min(P.n_items, 4 * h->n_cu);
-  const size_t lds = lds_bytes<R, S>(cw, W, h->dslots, direct);
+  const size_t lds = lds_of(cw);
   hipEvent_t ev_end = nullptr;
   if (h->profiling) {
     if (h->ev_used + 2 > h->ev_pool.size()) {
@@ -760,7 +869,17 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
     ev_end = h->ev_pool[h->ev_used + 1];
     h->ev_used += 2;
   }
-  if (data) {
+  if constexpr (kRlm) {
+    if (var) {
+      if (W <= 4)
+        hipLaunchKernelGGL((sweep2d_kernel<R, S, 4, false, true, true>), dim3(grid), dim3(64 * W), lds, st, P);
+      else
+        hipLaunchKernelGGL((sweep2d_kernel<R, S, kMaxWaves, false, true, true>), dim3(grid), dim3(64 * W), lds, st,
+                           P);
+    }
+  }
+  if (var) {
+  } else if (data) {
     if (W <= 4)
       hipLaunchKernelGGL((sweep2d_kernel<R, S, 4, false, true>), dim3(grid), dim3(64 * W), lds, st, P);
     else

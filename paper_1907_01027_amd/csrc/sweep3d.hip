@@ -38,9 +38,10 @@ namespace {
 template <int S> struct Traits3;
 // NOUT: per-cell outputs [P_0, xi, eta, zeta rows (, xi eta, xi zeta, eta zeta rows,
 // P_1 R xi, eta, zeta)]; NF: values handed downwind per axis; NRAW: FP64 inputs per cell
-template <> struct Traits3<LMDG_SCHEME_LMDG> { static constexpr int NOUT = 4, NF = 1; };
-template <> struct Traits3<LMDG_SCHEME_RLMDG> { static constexpr int NOUT = 10, NF = 4; };
-constexpr int kNC3 = 5;     // sigma_t V and the source coefficients a, b_x, b_y, b_z
+// NC: staged values per cell: sigma_t V, the source coefficients a, b_x, b_y, b_z, and for
+// RLMDG eps sigma_a V / 3 (the slope mass term of the second block row)
+template <> struct Traits3<LMDG_SCHEME_LMDG> { static constexpr int NOUT = 4, NF = 1, NC = 5; };
+template <> struct Traits3<LMDG_SCHEME_RLMDG> { static constexpr int NOUT = 10, NF = 4, NC = 6; };
 constexpr int kNRAW3 = 17;
 constexpr int kMAXC3 = 2;   // staged cells per thread
 constexpr int kStepGroup3 = 2;  // steps per unrolled group (measured best on gfx950)
@@ -122,6 +123,7 @@ __device__ __forceinline__ void raw_coef3(const double* raw, const int pos[3], c
     }
     coef[(2 + a) * cstride] = (R)b;
   }
+  if (S == LMDG_SCHEME_RLMDG) coef[5 * cstride] = (R)(absA * (1.0 / 3.0));
 }
 
 template <typename R, int S, int MAXW>
@@ -129,7 +131,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
   constexpr int NOUT = Traits3<S>::NOUT;
   constexpr int NOUTP = (NOUT + 3) & ~3;  // rows of red, padded to whole lane groups
   constexpr int NF = Traits3<S>::NF;
-  constexpr int NC = kNC3;
+  constexpr int NC = Traits3<S>::NC;
   constexpr int MAXC = MAXW > 4 ? 1 : kMAXC3;
   constexpr bool RLM = S == LMDG_SCHEME_RLMDG;
   extern __shared__ unsigned char smem_raw[];
@@ -265,25 +267,37 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
           const int c = t0 + e / (NF * ds);
           eds[e] = (s > 0 && c < nx) ? load_agent(src + e) : R(0);
         }
-        // z traces of plane kz - 1 for every cell of the chunk
+        // z traces of plane kz - 1 for every cell of the chunk, in batches of kZB values
+        // per thread whose loads are all issued before the first is stored to LDS (one
+        // load's latency per batch instead of per value)
         const int nz_e = cw * kRows * NF * ds;
-        for (int e = tid; e < nz_e; e += blockDim.x) {
-          const int fs = e % (NF * ds);
-          const int cellc = e / (NF * ds);
-          const int rr = cellc & 15, tt = cellc >> 4;
-          const int c = t0 + tt - rr;
-          const int jr2 = s * kRows + rr;
-          R v = R(0);
-          if (kz > 0 && c >= 0 && c < nx && jr2 < ny) {
-            const int i2 = si[0] > 0 ? c : nx - 1 - c;
-            const int j2 = si[1] > 0 ? jr2 : ny - 1 - jr2;
-            v = load_agent(zin_ring + ((long long)j2 * nx + i2) * NF * ds + fs);
+        constexpr int kZB = 16;
+        for (int base = 0; base < nz_e; base += kZB * (int)blockDim.x) {
+          R v[kZB];
+#pragma unroll
+          for (int m = 0; m < kZB; ++m) {
+            const int e = base + tid + m * (int)blockDim.x;
+            const int fs = e % (NF * ds);
+            const int cellc = e / (NF * ds);
+            const int rr = cellc & 15, tt = cellc >> 4;
+            const int c = t0 + tt - rr;
+            const int jr2 = s * kRows + rr;
+            v[m] = R(0);
+            if (e < nz_e && kz > 0 && c >= 0 && c < nx && jr2 < ny) {
+              const int i2 = si[0] > 0 ? c : nx - 1 - c;
+              const int j2 = si[1] > 0 ? jr2 : ny - 1 - jr2;
+              v[m] = load_agent(zin_ring + ((long long)j2 * nx + i2) * NF * ds + fs);
+            }
           }
-          zds[e] = v;
+#pragma unroll
+          for (int m = 0; m < kZB; ++m) {
+            const int e = base + tid + m * (int)blockDim.x;
+            if (e < nz_e) zds[e] = v[m];
+          }
         }
       }
-      if (k + 1 < P.nchunks) stage_load(k + 1);
-      __syncthreads();
+      if (k + 1 < P.nchunks) stage_load(k + 1);  // overlaps the step loop below
+      lds_barrier();  // staged traces and coefficients visible; the prefetch stays in flight
 
       const R* cbuf = coef + (size_t)buf * NC * ncells;
       constexpr int U = kStepGroup3;
@@ -353,7 +367,8 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
             zo[1] = cx;
             zo[2] = cy;
             zo[3] = psi;
-            const R sV3 = sig_g[u] * third;
+            // eps sigma_a V / 3: sigma_t V / 3 of L_11 R minus (sigma_s/eps) V / 3 of M_1 P_1 R
+            const R sV3 = cbuf[((tt << 4) + r) + 5 * ncells];
             o[0] = d.w * psi;
             o[1] = d.w * (d.oA[0] * (xin[0] - psi) + (sV3 + d.aA[0]) * cx +
                           third * (d.aA[1] * (cx - ydn[1]) + d.aA[2] * (cx - zin[1])));
@@ -453,7 +468,7 @@ size_t lds_bytes3(int cw, int W, int dslots) {
   constexpr int NOUT = Traits3<S>::NOUT;
   constexpr int NF = Traits3<S>::NF;
   constexpr int NOUTP = (NOUT + 3) & ~3;
-  return ((size_t)cw * (W * NOUTP * kRows + 1) + (size_t)2 * cw * kRows * kNC3 + (size_t)cw * NF * dslots +
+  return ((size_t)cw * (W * NOUTP * kRows + 1) + (size_t)2 * cw * kRows * Traits3<S>::NC + (size_t)cw * NF * dslots +
           (size_t)cw * kRows * NF * dslots) *
          sizeof(R);
 }

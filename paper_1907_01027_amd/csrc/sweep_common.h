@@ -42,6 +42,15 @@ __device__ __forceinline__ double quad_sum4(double a, double b, double c, double
   return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
 }
 
+// Workgroup barrier that orders LDS accesses only: it waits for the wave's own LDS
+// operations, not for its global loads in flight (a plain __syncthreads waits for
+// those too, which would expose the latency of every prefetch issued before it).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <typename T>
 __device__ __forceinline__ T load_agent(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -30,7 +30,7 @@ EXPORTED = ["lmdg_status_string", "lmdg_last_error", "lmdg_quadrature_level_symm
             "lmdg_destroy", "lmdg_set_materials", "lmdg_set_sources", "lmdg_sweep", "lmdg_apply", "lmdg_rhs",
             "lmdg_recover", "lmdg_solve", "lmdg_set_augment", "lmdg_adjoint_solve", "lmdg_profile",
             "lmdg_sweep_kernel_time", "lmdg_synchronize", "lmdg_set_wait_limit", "lmdg_set_source_moments",
-            "lmdg_workspace_bytes"]
+            "lmdg_workspace_bytes", "lmdg_set_reconstruction"]
 
 
 class LmdgInfo(ctypes.Structure):
@@ -74,6 +74,7 @@ def _load():
         "lmdg_set_wait_limit": (I, [P, ctypes.c_longlong, I]),
         "lmdg_set_source_moments": (I, [P, I, P, P]),
         "lmdg_workspace_bytes": (I, [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+        "lmdg_set_reconstruction": (I, [P, I, I]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -216,6 +217,11 @@ def lmdg_adjoint_solve(h, scheme, mode, det, tol, restart, max_iter, g_sigma_s, 
                                    int(max_iter), _ptr(g_sigma_s), _ptr(g_sigma_a), _ptr(g_q), ctypes.byref(J),
                                    ctypes.byref(info), _stream(stream)), h)
     return J.value, info.as_dict()
+
+
+def lmdg_set_reconstruction(h, stencil=2, suppress=False):
+    """RLMDG reconstruction variant: stencil 2 (default) or 3 (RLMDG*), suppression at jumps."""
+    _check(_lib.lmdg_set_reconstruction(h, int(stencil), int(bool(suppress))), h)
 
 
 def lmdg_set_augment(h, k):

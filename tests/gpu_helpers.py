@@ -101,10 +101,12 @@ def oracle_sweep(case, scheme, x_abi, use_q):
         rhs = rhs + red.Qt0
     psi = red.Lt00_lu.solve(rhs)
     p0 = red.P0 @ psi
-    g = red.S @ (red.L10 @ psi)
     if scheme == "rlmdg":
-        g = g + red.S @ (red.L11 @ (red.R @ psi))
+        # second block row G = Sigma (L_10 + L_11 R) - Sigma M_1 P_1 R of Sec. 3.3.2 (corrected)
+        g = red.G @ psi
         pr = (red.P1 @ (red.R @ psi)).reshape(nc, 3)
+    else:
+        g = red.S @ (red.L10 @ psi)
     g = g.reshape(nc, 3)
     rows = [p0, g[:, 0], g[:, 1], g[:, 2]]
     if scheme == "rlmdg":

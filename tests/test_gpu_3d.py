@@ -70,10 +70,8 @@ def oracle_sweep(case, scheme, x_abi, use_q):
     if use_q:
         rhs = rhs + red.Qt0
     psi = red.Lt00_lu.solve(rhs)
-    g = red.S @ (red.L10 @ psi)
-    if scheme == "rlmdg":
-        g = g + red.S @ (red.L11 @ (red.R @ psi))
-    g = g.reshape(nc, 7)
+    # second block row: Sigma L_10 (LMDG); G = Sigma (L_10 + L_11 R) - Sigma M_1 P_1 R (RLMDG)
+    g = (red.G @ psi).reshape(nc, 7)
     rows = [red.P0 @ psi] + [g[:, k] for k in range(7)]
     if scheme == "rlmdg":
         pr = (red.P1 @ (red.R @ psi)).reshape(nc, 7)

@@ -1,0 +1,183 @@
+"""RLMDG reconstruction variants through the C ABI (lmdg_set_reconstruction).
+
+* Parity with the oracle's variants (oracle.schemes.Problem with reconstruction=
+  "three-cell" / suppress=True): angular fluxes and reductions of sweeps, K x and the
+  right-hand side at the FP64 bar 1e-12, solves against the direct solve at 1e-9, on
+  blocky media (cross sections constant on a coarse block grid, so that suppression acts
+  at many faces), ragged meshes, with and without inflow data.
+* The paper's statements about the variants, computed on the GPU: RLMDG* is second
+  order with errors comparable to P^1-DG and well below RLMDG (fabricated slab solutions
+  of Table tab-1d-aniso); suppression lowers the error of RLMDG near the cross-section
+  discontinuity of examp-disccross1.
+"""
+import numpy as np
+import pytest
+
+from data_inputs import direction_moments_1d, inflow_faces_2d, inflow_points_1d
+from gpu_helpers import abi_to_lm, lm_to_abi, rel_err
+from oracle import schemes as S
+from oracle.dg import Mesh, l1_error, tensor_rule
+from oracle.quadrature import level_symmetric
+from paper_1907_01027_amd.workloads import materials
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1907_01027_amd import lmdg  # noqa: E402
+
+DEV = torch.device("cuda")
+VARIANTS = [(3, False), (2, True), (3, True)]
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def _alpha(x, o):
+    return 1.0 + 0.5 * np.sin(2.0 * x[:, 0] + x[:, 1]) + 0.3 * o[0]
+
+
+@pytest.mark.parametrize("with_alpha", [False, True])
+@pytest.mark.parametrize("shape,order", [((23, 19), 4), ((37, 18), 8)])
+@pytest.mark.parametrize("stencil,suppress", VARIANTS)
+def test_variant_parity_with_oracle(stencil, suppress, shape, order, with_alpha):
+    print(f"case variant stencil={stencil} suppress={suppress} {shape} S{order} alpha={with_alpha}", flush=True)
+    nc = shape[0] * shape[1]
+    om, w = level_symmetric(order, 2)
+    ss, sa, _, q = materials(2, n=shape, seed=41)
+    ep = np.full(nc, 0.2)
+    kw = {"reconstruction": "three-cell" if stencil == 3 else "two-cell", "suppress": suppress}
+    prob = S.Problem(Mesh(shape), om, w, ss, sa, ep, q=q[0], alpha=_alpha if with_alpha else None, **kw)
+    red = S.LowMemoryReduced(prob, True)
+    s = lmdg.Solver(shape, (1.0, 1.0), om, w)
+    lmdg.lmdg_set_materials(s.h, T(ss), T(sa), T(ep), T(q[0]),
+                            T(inflow_faces_2d(shape, (1.0, 1.0), om, _alpha)) if with_alpha else None)
+    lmdg.lmdg_set_reconstruction(s.h, stencil, suppress)
+    x = np.random.default_rng(9).normal(size=4 * nc)
+    # sweep of x (no source): angular flux and reductions [P_0 ; G ; P_1 R]
+    out = torch.zeros(6 * nc, dtype=torch.float64, device=DEV)
+    psi = torch.zeros(len(w) * nc, dtype=torch.float64, device=DEV)
+    lmdg.lmdg_sweep(s.h, "rlmdg", "fp64", T(x), False, out, psi)
+    xl = abi_to_lm(x, nc)
+    ref_psi = red.Lt00_lu.solve(red.M0 @ xl[:nc] + red.L01 @ (red.St @ xl[nc:]))
+    g = (red.G @ ref_psi).reshape(nc, 3)
+    pr = (red.P1 @ (red.R @ ref_psi)).reshape(nc, 3)
+    ref_out = np.concatenate([red.P0 @ ref_psi, g[:, 0], g[:, 1], g[:, 2], pr[:, 0], pr[:, 1]])
+    y = torch.zeros(4 * nc, dtype=torch.float64, device=DEV)
+    lmdg.lmdg_apply(s.h, "rlmdg", "fp64", T(x), y)
+    lmdg.lmdg_synchronize(s.h)
+    assert rel_err(psi.cpu().numpy(), ref_psi) < 1e-12
+    assert rel_err(out.cpu().numpy(), ref_out) < 1e-12
+    assert rel_err(y.cpu().numpy(), lm_to_abi(red.apply(xl), nc)) < 1e-12
+    # the solve against the direct solve of the variant's discrete system
+    xs = torch.zeros(4 * nc, dtype=torch.float64, device=DEV)
+    phi = torch.zeros_like(xs)
+    info = lmdg.lmdg_solve(s.h, "rlmdg", "fp64", 1e-13, 60, 8000, xs, phi)
+    s.close()
+    assert info["converged"] == 1
+    ref_phi = S.scalar_flux_lm(prob, *S.solve_rlmdg_direct(prob))
+    err = rel_err(phi.cpu().numpy().reshape(4, nc).T, ref_phi)
+    print(f"scalar flux vs direct solve: {err:.2e} ({info['iterations']} iterations)", flush=True)
+    assert err < 1e-9
+
+
+def test_variant_arguments():
+    om, w = level_symmetric(4, 2)
+    s = lmdg.Solver((4, 4), (1.0, 1.0), om, w)
+    for st, sup in ((1, 0), (4, 0), (2, 2)):
+        with pytest.raises(lmdg.LmdgError):
+            lmdg.lmdg_set_reconstruction(s.h, st, sup)
+    s.close()
+    om3, w3 = level_symmetric(4, 3)
+    s3 = lmdg.Solver((3, 3, 3), (1.0, 1.0, 1.0), om3, w3)
+    with pytest.raises(lmdg.LmdgError) as exc:
+        lmdg.lmdg_set_reconstruction(s3.h, 3, False)
+    assert exc.value.status == lmdg.LMDG_UNSUPPORTED
+    lmdg.lmdg_set_reconstruction(s3.h, 2, False)   # the default stays available
+    s3.close()
+
+
+MU, GW = np.polynomial.legendre.leggauss(32)
+
+
+def _fab(case):
+    if case == "cos x":
+        psi = lambda x, o: np.cos(x[:, 0])
+        q = lambda x, o: -o[0] * np.sin(x[:, 0]) + np.cos(x[:, 0])
+        phi = lambda x: np.cos(x[:, 0])
+    else:
+        psi = lambda x, o: np.cos(x[:, 0] + o[0])
+        q = lambda x, o: -o[0] * np.sin(x[:, 0] + o[0]) + 2 * np.cos(x[:, 0] + o[0]) - np.sin(1.0) * np.cos(x[:, 0])
+        phi = lambda x: np.sin(1.0) * np.cos(x[:, 0])
+    return psi, q, phi
+
+
+def _slab_solve(n, length, ss, sa, ep, alpha_pts, moments, scheme, stencil=2, suppress=False, per_dir=True,
+                mu=MU, gw=GW, tol=1e-12):
+    s = lmdg.Solver((n,), (length,), mu[:, None], gw / 2.0)
+    full = lambda v: np.broadcast_to(np.asarray(v, float), (n,)).copy()
+    lmdg.lmdg_set_materials(s.h, T(full(ss)), T(full(sa)), T(full(ep)), T(np.zeros(n)), T(alpha_pts))
+    if moments is not None:
+        lmdg.lmdg_set_source_moments(s.h, T(moments), per_dir)
+    lmdg.lmdg_set_reconstruction(s.h, stencil, suppress)
+    lmdg.lmdg_set_augment(s.h, 20)
+    xs = torch.zeros(4 * n, dtype=torch.float64, device=DEV)
+    phi = torch.zeros_like(xs)
+    info = lmdg.lmdg_solve(s.h, scheme, "fp64", tol, 250, 8000, xs, phi)
+    s.close()
+    assert info["converged"] == 1, info
+    return phi.cpu().numpy().reshape(4, n)[:2].T
+
+
+@pytest.mark.parametrize("case", ["cos x", "cos(x+mu)"])
+def test_rlmdg_star_on_fabricated_slab_solutions(case):
+    psi, q, phi = _fab(case)
+    err = {"P1": [], "RLMDG": [], "RLMDG*": []}
+    for n in (40, 80, 160):
+        a = inflow_points_1d(1.0, MU, psi)
+        m = direction_moments_1d(n, 1.0, MU, q)
+        mesh = Mesh((n,), (1.0,))
+        err["P1"].append(l1_error(mesh, _slab_solve(n, 1.0, 1.0, 1.0, 1.0, a, m, "std"), phi))
+        err["RLMDG"].append(l1_error(mesh, _slab_solve(n, 1.0, 1.0, 1.0, 1.0, a, m, "rlmdg"), phi))
+        err["RLMDG*"].append(l1_error(mesh, _slab_solve(n, 1.0, 1.0, 1.0, 1.0, a, m, "rlmdg", stencil=3), phi))
+    e = {k: np.array(v) for k, v in err.items()}
+    print("L1 errors:", {k: [f"{x:.3e}" for x in v] for k, v in e.items()}, flush=True)
+    assert np.abs(np.log2(e["RLMDG*"][:-1] / e["RLMDG*"][1:]) - 2.0).max() < 0.1
+    assert np.all(e["RLMDG*"] < 2.0 * e["P1"])
+    assert np.all(e["RLMDG*"] < 0.5 * e["RLMDG"])
+
+
+def test_suppressed_reconstruction_at_the_discontinuity():
+    """examp-disccross1 on a uniform mesh of h = 0.1 (the example's finest spacing)."""
+    mu, gw = np.polynomial.legendre.leggauss(16)
+    n, length = 110, 11.0
+    xc = (np.arange(n) + 0.5) * length / n
+    ss, sa = np.where(xc < 1.0, 0.0, 100.0), np.where(xc < 1.0, 2.0, 0.0)
+    a = np.where(mu > 0, 1.0, 0.0)
+    f = _slab_solve(n, length, ss, sa, 1.0, a, None, "rlmdg", mu=mu, gw=gw, tol=1e-11)
+    fs = _slab_solve(n, length, ss, sa, 1.0, a, None, "rlmdg", suppress=True, mu=mu, gw=gw, tol=1e-11)
+    nref = 1100
+    xr = (np.arange(nref) + 0.5) * length / nref
+    pref = S.Problem(Mesh((nref,), (length,)), mu[:, None], gw / 2, np.where(xr < 1.0, 0.0, 100.0),
+                     np.where(xr < 1.0, 2.0, 0.0), 1.0,
+                     alpha=lambda x, o: np.full(x.shape[0], 1.0 if o[0] > 0 else 0.0))
+    ref = S.scalar_flux_std(pref, S.solve_std_direct(pref))
+    pts, wts = tensor_rule(1, 6)
+
+    def window(fl, lo=0.5, hi=3.0):
+        h, href = length / n, length / nref
+        tot = 0.0
+        for p in range(n):
+            x = (p + 0.5) * h + 0.5 * h * pts[:, 0]
+            msk = (x >= lo) & (x <= hi)
+            if msk.any():
+                k = np.minimum((x / href).astype(int), nref - 1)
+                ex = ref[k, 0] + ref[k, 1] * 2 * (x - (k + 0.5) * href) / href
+                tot += 0.5 * h * (wts * msk) @ np.abs(fl[p, 0] + fl[p, 1] * pts[:, 0] - ex)
+        return tot
+    e, es = window(f), window(fs)
+    print(f"L1 error on [0.5, 3]: RLMDG {e:.3e}, suppressed {es:.3e}", flush=True)
+    assert es < 0.85 * e

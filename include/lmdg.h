@@ -288,20 +288,27 @@ int lmdg_set_reconstruction(lmdg_t* h, int stencil, int suppress);
 int lmdg_set_augment(lmdg_t* h, int k);
 
 /*
- * Detector response and its gradients (Galerkin schemes STD and LMDG).
+ * Detector response and its gradients (2D, all three schemes).
  * J = int_D phi_h d dx for detector moments det (device moment vector,
  * det[r*n_cells + p] = int_{K_p} d b_r dx; for the indicator of a box, the exact
  * integral of each basis function over the part of the cell inside the box).
  * The scheme's discrete system A y = b (eq-sndg-scheme; eq-lmdg-block with the
- * trial map of eq-gene-scheme) is solved forward, then A^T lambda = dJ/dy, and the
- * derivatives of the bilinear form of eq-Ljk with respect to the per-cell data give
+ * trial map of eq-gene-scheme; eq-rlmdg-vari) is solved forward, then A^T lambda =
+ * dJ/dy, and the derivatives of the bilinear form of eq-Ljk with respect to the
+ * per-cell data give
  *   g_sigma_a = -eps sum_l w_l int_K psi_l lambda_l,
  *   g_sigma_s = -(1/eps) (sum_l w_l int_K psi_l lambda_l - int_K phi Lambda),
  *   g_q       =  eps int_K Lambda           (Lambda = sum_l w_l lambda_l),
- * i.e. dJ/d(sigma_s, sigma_a, q) of cell K for the discrete J.  Both solves use
- * mode, tol, restart and max_iter as lmdg_solve does.  The quadrature must be
- * centrally symmetric (-Omega with the same weight for every Omega): the adjoint
- * sweep of direction Omega is then the forward sweep of -Omega.
+ * i.e. dJ/d(sigma_s, sigma_a, q) of cell K for the discrete J, with psi the forward
+ * field of the trial space (for RLMDG including its reconstructed slopes) and lambda
+ * the adjoint field of the test space.  Both solves use mode, tol, restart and
+ * max_iter as lmdg_solve does.  The quadrature must be centrally symmetric (-Omega with
+ * the same weight for every Omega): the adjoint sweep of direction Omega is then a
+ * forward-type sweep of -Omega.  STD and LMDG are Galerkin, so their adjoint is the
+ * forward system with the detector as source.  RLMDG is Petrov-Galerkin: its adjoint is
+ * the scheme with trial space V^lm and test functions reconstructed from the downwind
+ * side, which the library solves by its own reduced system (sweeps with the local
+ * operator L_00 + R'^T L_10, R' the downwind reconstruction, and the same GMRES).
  *   det                device, 4 * n_cells doubles (moment-major)
  *   g_sigma_s, g_sigma_a, g_q   device outputs, n_cells doubles each
  *   J_out              host output
@@ -309,13 +316,13 @@ int lmdg_set_augment(lmdg_t* h, int k);
  * The angular fluxes are never stored for all directions: the gradient sum is built
  * one quadrant at a time, recomputing that quadrant's forward fluxes and the opposite
  * quadrant's adjoint-type fluxes with two restricted sweeps (the handle keeps
- * 2 x slots x n_cells doubles for LMDG, 8 x slots x n_cells for STD, slots = the
- * padded directions per quadrant).
- * Errors: UNSUPPORTED (RLMDG: its adjoint is Petrov-Galerkin; 3D meshes; slab handles), INVALID_ARG (NULL
- * pointers, bad solver arguments, quadrature without central symmetry, more than
- * one right-hand side on the handle),
- * NOT_CONVERGED (either solve, or the conjugate gradients of B_11 that give the
- * slope part of the LMDG adjoint source), HIP_ERROR.
+ * 2 x slots x n_cells doubles for LMDG and RLMDG, 8 x slots x n_cells for STD, slots =
+ * the padded directions per quadrant; RLMDG also n_dir x n_cells for the adjoint source).
+ * Errors: UNSUPPORTED (3D meshes, slab handles, RLMDG with a reconstruction variant),
+ * INVALID_ARG (NULL pointers, bad solver arguments, quadrature without central symmetry,
+ * more than one right-hand side on the handle), NOT_CONVERGED (either solve, or the
+ * conjugate gradients of B_11 that give the slope part of the LMDG adjoint source),
+ * HIP_ERROR.
  */
 int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, double tol,
                        int restart, int max_iter, double* g_sigma_s, double* g_sigma_a,

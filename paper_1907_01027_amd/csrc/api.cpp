@@ -435,7 +435,7 @@ void lmdg_destroy(lmdg_t* h) {
   void* ptrs[] = {h->d_dirs, h->d_sigtA, h->d_scatA, h->d_absA, h->d_qA, h->ws.part, h->ws.edge, h->ws.zbuf,
                   h->ws.prog, h->ws.ticket, h->ws.err, h->ws.vec, h->d_krylov, h->d_small,
                   h->d_epsA, h->d_adjpairs, h->d_psi_f, h->d_psi_a, h->d_cvec, h->d_qS, h->d_qdir,
-                  h->d_alpha, h->d_sq1, h->d_sqa};
+                  h->d_alpha, h->d_sq1, h->d_sqa, h->d_adjsrc};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (h->h_small) hipHostFree(h->h_small);
@@ -646,6 +646,15 @@ int check_call(lmdg_t* h, int scheme, int prec) {
 // eq-nonrec-block / eq-sndg-phi, arranged so that no O(sigma_s/eps) terms cancel
 // after the sweep; this is what keeps FP32 sweeps usable at small eps.
 int apply_op(lmdg_t* h, int scheme, int prec, const double* x, double* y, hipStream_t st) {
+  if (h->adj_rlm) {
+    // adjoint of RLMDG: K' X' = [X_0 - P_0 mu ; B_11 X'_1 - Sigma L_10 mu], mu the adjoint
+    // sweep of the source formed from X' (adj_rlm_source_kernel)
+    lmdg::launch_adj_rlm_source(h, x, nullptr, st);
+    int rc = lmdg::launch_sweep(h, LMDG_SCHEME_RLMDG, prec, nullptr, false, nullptr, st, false);
+    if (rc != LMDG_OK) return rc;
+    lmdg::launch_combine(h, LMDG_SCHEME_RLMDG, prec, lmdg::kApply, x, y, st);
+    return check_hip(h, hipGetLastError(), "combine");
+  }
   // the reconstruction variants of RLMDG use the plain form (eq-nonrec-block applied as
   // printed: K x = [x_0 - P_0 psi ; B_11 x_1 - G psi])
   const bool defect = !(scheme == LMDG_SCHEME_RLMDG && h->recon_flags != 0);
@@ -1041,6 +1050,13 @@ int lmdg_rhs(lmdg_t* h, int scheme, int prec, double* b, void* stream) {
   if (rc != LMDG_OK) return rc;
   if (!b) return set_error(h, LMDG_INVALID_ARG, "NULL vector");
   hipStream_t st = (hipStream_t)stream;
+  if (h->adj_rlm) {  // adjoint of RLMDG (inside lmdg_adjoint_solve): source from the detector
+    lmdg::launch_adj_rlm_source(h, nullptr, h->adj_det, st);
+    rc = lmdg::launch_sweep(h, LMDG_SCHEME_RLMDG, prec, nullptr, false, nullptr, st);
+    if (rc != LMDG_OK) return rc;
+    lmdg::launch_combine(h, LMDG_SCHEME_RLMDG, prec, lmdg::kRhs, nullptr, b, st);
+    return check_hip(h, hipGetLastError(), "rhs");
+  }
   rc = lmdg::launch_sweep(h, scheme, prec, nullptr, true, nullptr, st);
   if (rc != LMDG_OK) return rc;
   lmdg::launch_combine(h, scheme, prec, lmdg::kRhs, nullptr, b, st);
@@ -1052,6 +1068,13 @@ int lmdg_recover(lmdg_t* h, int scheme, int prec, const double* x, double* phi, 
   if (rc != LMDG_OK) return rc;
   if (!x || !phi) return set_error(h, LMDG_INVALID_ARG, "NULL vector");
   hipStream_t st = (hipStream_t)stream;
+  if (h->adj_rlm) {  // adjoint of RLMDG: mu = sweep of the full source; [P_0 mu ; -X'_1]
+    lmdg::launch_adj_rlm_source(h, x, h->adj_det, st);
+    rc = lmdg::launch_sweep(h, LMDG_SCHEME_RLMDG, prec, nullptr, false, psi, st);
+    if (rc != LMDG_OK) return rc;
+    lmdg::launch_combine(h, LMDG_SCHEME_RLMDG, prec, lmdg::kRecover, x, phi, st);
+    return check_hip(h, hipGetLastError(), "recover");
+  }
   rc = lmdg::launch_sweep(h, scheme, prec, x, true, psi, st);
   if (rc != LMDG_OK) return rc;
   lmdg::launch_combine(h, scheme, prec, lmdg::kRecover, x, phi, st);
@@ -1204,8 +1227,9 @@ int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, doubl
                        void* stream) {
   int rc = check_call(h, scheme, LMDG_PREC_FP64);
   if (rc != LMDG_OK) return rc;
-  if (scheme == LMDG_SCHEME_RLMDG)
-    return set_error(h, LMDG_UNSUPPORTED, "the adjoint covers the Galerkin schemes (standard, LMDG)");
+  const bool rlm = scheme == LMDG_SCHEME_RLMDG;
+  if (rlm && h->recon_flags != 0)
+    return set_error(h, LMDG_UNSUPPORTED, "the RLMDG adjoint covers the two-cell reconstruction only");
   if (h->dim != 2) return set_error(h, LMDG_UNSUPPORTED, "the adjoint solve is two-dimensional");
   if (h->slab) return set_error(h, LMDG_UNSUPPORTED, "adjoint of a slab handle");
   if (!det || !g_sigma_s || !g_sigma_a || !g_q || !J_out || !(tol > 0) || restart < 1 || restart > 250 ||
@@ -1233,6 +1257,10 @@ int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, doubl
     rc = check_hip(h, hipMalloc((void**)&h->d_cvec, (size_t)6 * N * sizeof(double)), "hipMalloc adjoint vectors");
     if (rc != LMDG_OK) return rc;
   }
+  if (rlm && !h->d_adjsrc) {  // per-direction source of the RLMDG adjoint sweeps
+    rc = check_hip(h, hipMalloc((void**)&h->d_adjsrc, (size_t)h->ndir * nc * sizeof(double)), "hipMalloc adjoint source");
+    if (rc != LMDG_OK) return rc;
+  }
   double* c = h->d_cvec;
   double* xf = h->d_cvec + N;
   double* phi = h->d_cvec + 2 * N;
@@ -1249,7 +1277,15 @@ int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, doubl
   // -Omega_l, so A^T lambda = j is the forward system with source moments d and the
   // direction blocks exchanged l <-> -l; the same sweeps solve it
   const double* xa_rec = xa;  // the adjoint solution as the recovery sweep takes it
-  if (rc == LMDG_OK) {
+  if (rc == LMDG_OK && rlm) {
+    // RLMDG (Petrov-Galerkin): the transposed system is a scheme of its own, solved by the
+    // same GMRES with the adjoint sweeps (adj_rlm_source_kernel); its solution X' gives the
+    // adjoint scalar flux [P_0 mu ; -X'_1]
+    h->adj_rlm = true;
+    h->adj_det = det;
+    rc = solve_impl(h, scheme, mode, tol, restart, max_iter, nullptr, xa, Lam, nullptr, &inf_a, st, nullptr, nullptr);
+    h->adj_rlm = false;
+  } else if (rc == LMDG_OK) {
     h->src0 = det;
     h->src1 = scheme == LMDG_SCHEME_STD ? det + nc : nullptr;
     const double* rhs_x = nullptr;
@@ -1282,6 +1318,16 @@ int lmdg_adjoint_solve(lmdg_t* h, int scheme, int mode, const double* det, doubl
     for (int q = 0; q < 4 && rc == LMDG_OK; ++q) {
       rc = lmdg::launch_sweep(h, scheme, LMDG_PREC_FP64, xf, true, h->d_psi_f, st, false, 1 << q, true);
       if (rc != LMDG_OK) break;
+      if (rlm) {
+        // adjoint cell constants mu of the opposite quadrant (the reflected directions)
+        h->adj_rlm = true;
+        h->adj_det = det;
+        lmdg::launch_adj_rlm_source(h, xa, det, st);
+        rc = lmdg::launch_sweep(h, scheme, LMDG_PREC_FP64, nullptr, false, h->d_psi_a, st, false, 1 << (q ^ 3), true);
+        h->adj_rlm = false;
+        if (rc == LMDG_OK) lmdg::launch_grad_accumulate(h, q, npsi, bil, st);
+        continue;
+      }
       h->src0 = det;
       h->src1 = scheme == LMDG_SCHEME_STD ? det + nc : nullptr;
       rc = lmdg::launch_sweep(h, scheme, LMDG_PREC_FP64, xa_rec, true, h->d_psi_a, st, false, 1 << (q ^ 3), true);

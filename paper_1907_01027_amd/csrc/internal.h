@@ -43,7 +43,8 @@ struct SweepParams {
   const double* qS;      // source slope moments (3 * ncell, standard scheme) or null
   const double* absA;    // eps sigma_a |K|
   const double* alpha;   // inflow data [n_dir][nfaces][3] (face average, linear coefficient, midpoint) or null
-  const double* qdir;    // direction-dependent source moments eps q_l |K| [n_dir][4][ncell] or null
+  const double* qdir;    // direction-dependent source moments eps q_l |K| [n_dir][qdir_nm][ncell] or null
+  int qdir_nm;           // moments per direction in qdir (4; 1 for the adjoint source)
   int nfaces;            // inflow faces per direction: n_y x faces, then n_x y faces
   int recon_y;           // 1: RLMDG reconstructs along y; 0 on slab handles
   int rflags;            // reconstruction variant: bit 0 three-cell, bit 1 suppression, bit 2 y axis
@@ -148,6 +149,11 @@ struct lmdg_handle {
   double* d_sqa = nullptr;
   int last_nsl = 4;                // partial slices written by the last sweep launch
   int recon_flags = 0;             // RLMDG reconstruction variant (lmdg_set_reconstruction)
+  // adjoint of RLMDG (inside lmdg_adjoint_solve): sweeps, right-hand sides, recovery and
+  // K x take the adjoint system; d_adjsrc holds its per-direction source [n_dir][ncell]
+  bool adj_rlm = false;
+  const double* adj_det = nullptr;
+  double* d_adjsrc = nullptr;
   // directions: index of -Omega_l; per quadrant and slot the weight and the slot of
   // -Omega_l in the opposite quadrant (adjoint gradients)
   std::vector<int> neg_dir;
@@ -212,6 +218,7 @@ void launch_combine3(lmdg_handle* h, int scheme, int prec, int mode, const doubl
 void launch_sum_octants(lmdg_handle* h, int scheme, int prec, double* out, hipStream_t st);
 void launch_b11_3d(lmdg_handle* h, const double* x, double* y, hipStream_t st);
 void launch_b11(lmdg_handle* h, const double* x, double* y, hipStream_t st);
+void launch_adj_rlm_source(lmdg_handle* h, const double* x, const double* det, hipStream_t st);
 void launch_grad_accumulate(lmdg_handle* h, int quadrant, int npsi, double* bil, hipStream_t st);
 void launch_gradients(lmdg_handle* h, int npsi, const double* bil, const double* phi, const double* Lam, double* gs,
                       double* ga, double* gq, hipStream_t st);

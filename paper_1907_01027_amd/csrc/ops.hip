@@ -300,6 +300,78 @@ __global__ void grad_final_kernel(long long nc, int npsi, const double* __restri
   }
 }
 
+// Source of the adjoint RLMDG sweep, per direction and cell (unweighted rows).
+//
+// The adjoint of the Petrov-Galerkin system A = T^T (L - M P) T_R (eq-rlmdg-vari) is
+// A^T lambda = j.  With the directions reflected (on a centrally symmetric set L_l^T is
+// L_{-l} and M P is symmetric), it becomes the Petrov-Galerkin system with trial space T
+// (cell constants per direction plus isotropic slopes) and test space T_R', R' the
+// downwind reconstruction (the upwind one of -Omega).  Testing with the slope part of
+// T_R' and using the isotropic slope rows to remove the P_1^T Sigma part, the constant
+// rows of direction l read
+//   (L_00 + R'^T L_10) mu_l = M_0 X_0 + L_01 X'_1 + R'^T ((L_11 - M_1) X'_1 + d_1) + d_0,
+// with X_0 = P_0 mu, X'_1 = -(the isotropic slopes), d = the detector moments, and the
+// slope rows give B_11 X'_1 - Sigma L_10 mu = -d_1.  L_00 + R'^T L_10 has the stencil of
+// the forward L~_00 with k = 1 in the outflow cell of a line and 1/2 elsewhere, so the
+// RLMDG sweep solves it with those rules; this kernel forms the right-hand side.
+// R'^T of a slope-row field rho: sum over axes a of s_a (-k_a(K) rho_a(K) +
+// k_a(U_a) rho_a(U_a)), U_a the upwind neighbour (k = 1/2 there: K is downwind of it);
+// rho_xi(J) = (eps sigma_a|J|/3 + ax + ay/3) a_J + ay s_y c_J / 3 + ax a_{U_x(J)}
+//             - ay (a_{U_y(J)} + s_y c_{U_y(J)}) / 3 + d_xi(J)   (and eta with x <-> y),
+// (a, b, c) the xi, eta, xi eta coefficients of X'_1, ax = |Ox| h_y, ay = |Oy| h_x; the
+// scattering parts of L_11 and M_1 cancel to eps sigma_a.
+__global__ void adj_rlm_source_kernel(int nx, int ny, double hx, double hy, int dslots, int recon_y,
+                                      const double* __restrict__ dirs, const double* __restrict__ x,
+                                      const double* __restrict__ det, const double* __restrict__ scatA,
+                                      const double* __restrict__ absA, double* __restrict__ out) {
+  const long long nc = (long long)nx * ny;
+  const long long total = 4LL * dslots * nc;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long p = e % nc;
+    const int qs = (int)(e / nc);  // quadrant * dslots + slot
+    const double* dr = dirs + (long long)qs * kDirStride;
+    const int l = (int)dr[3];
+    if (l < 0) continue;
+    const int q = qs / dslots;
+    const int sx = (q & 1) ? -1 : 1, sy = (q & 2) ? -1 : 1;
+    const double ox = dr[0], oy = dr[1];
+    const double ax = fabs(ox) * hy, ay = fabs(oy) * hx;
+    const int i = (int)(p % nx), j = (int)(p / nx);
+    // value of moment r of (x or det) at cell (ii, jj); zero outside
+    auto v = [&](const double* f, int r, int ii, int jj) -> double {
+      if (!f || ii < 0 || ii >= nx || jj < 0 || jj >= ny) return 0.0;
+      return f[(long long)r * nc + (long long)jj * nx + ii];
+    };
+    auto rho_xi = [&](int ii, int jj) -> double {
+      const double a = v(x, 1, ii, jj), c = v(x, 3, ii, jj);
+      const double aux = v(x, 1, ii - sx, jj);
+      const double auy = v(x, 1, ii, jj - sy), cuy = v(x, 3, ii, jj - sy);
+      const double aA = absA[(long long)jj * nx + ii];
+      return (aA / 3.0 + ax + ay / 3.0) * a + ay * sy * c / 3.0 + ax * aux - ay * (auy + sy * cuy) / 3.0 +
+             v(det, 1, ii, jj);
+    };
+    auto rho_eta = [&](int ii, int jj) -> double {
+      const double b = v(x, 2, ii, jj), c = v(x, 3, ii, jj);
+      const double buy = v(x, 2, ii, jj - sy);
+      const double bux = v(x, 2, ii - sx, jj), cux = v(x, 3, ii - sx, jj);
+      const double aA = absA[(long long)jj * nx + ii];
+      return (aA / 3.0 + ay + ax / 3.0) * b + ax * sx * c / 3.0 + ay * buy - ax * (bux + sx * cux) / 3.0 +
+             v(det, 2, ii, jj);
+    };
+    const bool upx = sx > 0 ? i > 0 : i < nx - 1, upy = sy > 0 ? j > 0 : j < ny - 1;
+    const bool outx = sx > 0 ? i == nx - 1 : i == 0, outy = sy > 0 ? j == ny - 1 : j == 0;
+    const double kx = outx ? 1.0 : 0.5, ky = outy ? 1.0 : 0.5;
+    double src = scatA[p] * v(x, 0, i, j) + v(det, 0, i, j);
+    // L_01 X'_1: outflow traces of the slopes minus the inflow ones
+    src += ox * hy * (v(x, 1, i, j) - v(x, 1, i - sx, j)) + oy * hx * (v(x, 2, i, j) - v(x, 2, i, j - sy));
+    // R'^T rho
+    double rt = sx * (-kx * rho_xi(i, j) + (upx ? 0.5 * rho_xi(i - sx, j) : 0.0));
+    if (recon_y) rt += sy * (-ky * rho_eta(i, j) + (upy ? 0.5 * rho_eta(i, j - sy) : 0.0));
+    out[(long long)l * nc + p] = src + rt;
+  }
+}
+
 // ---------------------------------------------------------------- GMRES vectors
 constexpr int kDotBlocks = 240;
 
@@ -413,6 +485,10 @@ void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double
   const bool own = mode == kRhs && !h->src0;
   const double* sq1 = own ? h->d_sq1 : nullptr;
   const double* sqa = (own && !rlm) ? h->d_sqa : nullptr;
+  if (h->adj_rlm) {  // adjoint of RLMDG: right-hand side minus the detector's slope moments
+    sq1 = mode == kRhs ? h->adj_det + nc : nullptr;
+    sqa = nullptr;
+  }
   if (prec == LMDG_PREC_FP64) {
     if (rlm) LMDG_COMBINE(double, true); else LMDG_COMBINE(double, false);
   } else {
@@ -435,6 +511,12 @@ void launch_sum_quadrants(lmdg_handle* h, int scheme, int prec, double* out, hip
   else
     hipLaunchKernelGGL(sum_quadrants_kernel<float>, dim3(g), dim3(kBlock), 0, st, nout, nout_abi, h->n_rhs,
                        h->last_nsl, h->ncell, (const float*)h->ws.part, out);
+}
+
+void launch_adj_rlm_source(lmdg_handle* h, const double* x, const double* det, hipStream_t st) {
+  const int g = std::min(grid_for(4LL * h->dslots * h->ncell), 8192);
+  hipLaunchKernelGGL(adj_rlm_source_kernel, dim3(g), dim3(kBlock), 0, st, (int)h->n[0], (int)h->n[1], h->h[0],
+                     h->h[1], h->dslots, h->slab ? 0 : 1, h->d_dirs, x, det, h->d_scatA, h->d_absA, h->d_adjsrc);
 }
 
 void launch_b11(lmdg_handle* h, const double* x, double* y, hipStream_t st) {

@@ -135,9 +135,12 @@ __device__ __forceinline__ void cell_rlmdg(const Dir<R>& d, R src, R aA3, R inv,
 // quadratic (3 psi - 4 psi_up + psi_upup) / 4, (0, 0) where the reconstruction is
 // suppressed.  Traces handed downwind: (outflow face average, linear coefficient along
 // the face, cell average, the cell's own upwind average along that axis).
+// adj: the adjoint sweep of the reconstructed scheme (rules k = 1 in the outflow cell,
+// 1/2 elsewhere; see adj_rlm_source_kernel), whose reductions are those of the
+// low-memory scheme, w psi and w Sigma L_10 psi (rows xi, eta), the other rows zero.
 template <typename R>
 __device__ __forceinline__ void cell_rlmdg_var(const Dir<R>& d, R src, R aA3, R inv, const R* ru, const R* xin,
-                                               const R* ydn, R* xo, R* yo, R* o, R& psi_out) {
+                                               const R* ydn, R* xo, R* yo, R* o, R& psi_out, bool adj) {
   const R third = R(1) / R(3);
   const R psi = (src + d.axhy * (xin[0] + ru[0] * xin[2] - ru[1] * xin[3]) +
                  d.ayhx * (ydn[0] + ru[2] * ydn[2] - ru[3] * ydn[3])) *
@@ -155,11 +158,17 @@ __device__ __forceinline__ void cell_rlmdg_var(const Dir<R>& d, R src, R aA3, R 
   yo[2] = psi;
   yo[3] = ydn[2];
   o[0] = d.w * psi;
-  o[1] = d.w * (d.oxhy * (xin[0] - psi) + (aA3 + d.axhy + d.ayhx * third) * cxi - d.ayhx * third * ydn[1]);
-  o[2] = d.w * (d.oyhx * (ydn[0] - psi) + (aA3 + d.ayhx + d.axhy * third) * ceta - d.axhy * third * xin[1]);
-  o[3] = d.w * third * (d.oxhy * (xin[1] - ceta) + d.oyhx * (ydn[1] - cxi));
-  o[4] = d.w * cxi;
-  o[5] = d.w * ceta;
+  if (adj) {
+    o[1] = d.w * d.oxhy * (xin[2] - psi);
+    o[2] = d.w * d.oyhx * (ydn[2] - psi);
+    o[3] = o[4] = o[5] = R(0);
+  } else {
+    o[1] = d.w * (d.oxhy * (xin[0] - psi) + (aA3 + d.axhy + d.ayhx * third) * cxi - d.ayhx * third * ydn[1]);
+    o[2] = d.w * (d.oyhx * (ydn[0] - psi) + (aA3 + d.ayhx + d.axhy * third) * ceta - d.axhy * third * xin[1]);
+    o[3] = d.w * third * (d.oxhy * (xin[1] - ceta) + d.oyhx * (ydn[1] - cxi));
+    o[4] = d.w * cxi;
+    o[5] = d.w * ceta;
+  }
   psi_out = psi;
 }
 
@@ -312,13 +321,15 @@ __device__ __forceinline__ void raw_load(const SweepParams<R>& P, const double* 
 }
 
 // Upwind rule (a_up, a_uu) along one axis of a cell with `pos` upwind cells inside the
-// mesh; same1: the cell and its upwind neighbour have the same cross sections, same2:
-// that neighbour and the next one do.  rflags: bit 0 three-cell stencil, bit 1
-// suppression at cross-section jumps.
-__device__ __forceinline__ void upwind_rule(int pos, bool same1, bool same2, int rflags, double& a_up,
+// mesh out of `len`; same1: the cell and its upwind neighbour have the same cross
+// sections, same2: that neighbour and the next one do.  rflags: bit 0 three-cell
+// stencil, bit 1 suppression at cross-section jumps, bit 3 the adjoint sweep (k = 1 in
+// the last cell of the line, 1/2 elsewhere).
+__device__ __forceinline__ void upwind_rule(int pos, int len, bool same1, bool same2, int rflags, double& a_up,
                                             double& a_uu) {
   const bool three = rflags & 1, suppress = rflags & 2;
-  if (pos == 0) { a_up = 1.0; a_uu = 0.0; }
+  if (rflags & 8) { a_up = (pos == len - 1) ? 1.0 : 0.5; a_uu = 0.0; }
+  else if (pos == 0) { a_up = 1.0; a_uu = 0.0; }
   else if (suppress && !same1) { a_up = 0.0; a_uu = 0.0; }
   else if (three && pos >= 2 && !(suppress && !same2)) { a_up = 1.0; a_uu = 0.25; }
   else { a_up = 0.5; a_uu = 0.0; }
@@ -345,7 +356,8 @@ __device__ __forceinline__ void upwind_rule(int pos, bool same1, bool same2, int
 // three stored coefficients per moment: src = a + |Ox| b + |Oy| c.
 template <typename R, int S, bool VAR = false>
 __device__ __forceinline__ void raw_coef(const double* raw, int c, int jr, int sxi, int syi, double hx,
-                                         double hy, bool defect, R* coef, int cstride, int rflags = 0) {
+                                         double hy, bool defect, R* coef, int cstride, int rflags = 0, int nx = 0,
+                                         int ny = 0) {
   if constexpr (S == LMDG_SCHEME_STD) {
     const double* p = raw;       // moments at the cell
     const double* u = raw + 4;   // x-upwind neighbour
@@ -425,8 +437,8 @@ __device__ __forceinline__ void raw_coef(const double* raw, int c, int jr, int s
       const bool same1y = raw[11] == raw[17] && raw[10] == raw[18];
       const bool same2y = raw[17] == raw[19] && raw[18] == raw[20];
       double axu, axuu, ayu, ayuu;
-      upwind_rule(c, same1x, same2x, rflags, axu, axuu);
-      upwind_rule(jr, same1y, same2y, rflags, ayu, ayuu);
+      upwind_rule(c, nx, same1x, same2x, rflags, axu, axuu);
+      upwind_rule(jr, ny, same1y, same2y, rflags, ayu, ayuu);
       if (!(rflags & 4)) ayu = ayuu = 0.0;
       coef[5 * cstride] = (R)axu;
       coef[6 * cstride] = (R)axuu;
@@ -551,7 +563,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
         if (e < ncells) {
           const int rr = e >> lcw, tt = e & (cw - 1);
           raw_coef<R, S, VAR>(raw[m], (k << lcw) + tt - rr, s * kRows + rr, sxi, syi, P.hx, P.hy, P.defect != 0,
-                              coef + (size_t)buf * NC * ncells + (tt << 4) + rr, ncells, P.rflags);
+                              coef + (size_t)buf * NC * ncells + (tt << 4) + rr, ncells, P.rflags, P.nx, P.ny);
         }
       }
     };
@@ -631,7 +643,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
             if (P.qdir && row_ok && d.idx >= 0 && c >= 0 && c < nx) {
               const long long cell = (long long)j * nx + (sxi > 0 ? c : nx - 1 - c);
 #pragma unroll
-              for (int m = 0; m < NS; ++m) src_g[u][m] += (R)P.qdir[((long long)d.idx * 4 + m) * nc + cell];
+              for (int m = 0; m < NS; ++m) src_g[u][m] += (R)P.qdir[((long long)d.idx * P.qdir_nm + m) * nc + cell];
             }
           }
           if constexpr (S == LMDG_SCHEME_LMDG) {
@@ -671,7 +683,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
             cell_lmdg<R>(d, src_g[u][0], inv, xin, ydn, xo, yo, o, psi_g[u][0]);
           } else if constexpr (VAR) {
             cell_rlmdg_var<R>(d, src_g[u][0], cbuf[((tt << 4) + r) + 4 * ncells], inv, ru_g[u], xin, ydn, xo, yo, o,
-                              psi_g[u][0]);
+                              psi_g[u][0], (P.rflags & 8) != 0);
           } else {
             const R kx = (c == 0) ? R(1) : R(0.5);
             cell_rlmdg<R>(d, src_g[u][0], cbuf[((tt << 4) + r) + 4 * ncells], inv, kx, ky, xin, ydn, xo, yo, o,
@@ -808,7 +820,8 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   const bool data = use_q && !h->src0 && (h->d_alpha || h->d_qdir);
   // reconstruction variants (RLMDG): their own kernel, always with the plain source
   constexpr bool kRlm = S == LMDG_SCHEME_RLMDG;
-  const bool var = kRlm && h->recon_flags != 0;
+  const bool adj = kRlm && h->adj_rlm;  // adjoint sweep of the reconstructed scheme
+  const bool var = kRlm && (h->recon_flags != 0 || adj);
   const bool direct = !data && !var && part_slices(h, S, sizeof(R) == 8 ? LMDG_PREC_FP64 : LMDG_PREC_FP32) > 4;
   h->last_nsl = direct ? 4 * W : 4;  // slices of the partials the combine adds
   auto lds_of = [&](int c) {
@@ -835,11 +848,12 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
   P.scatA = h->d_scatA;
   P.qA = use_q ? (h->src0 ? h->src0 : h->d_qA) : nullptr;
   P.qS = (use_q && S == LMDG_SCHEME_STD) ? (h->src0 ? h->src1 : h->d_qS) : nullptr;
-  P.alpha = data ? h->d_alpha : nullptr;
-  P.qdir = data ? h->d_qdir : nullptr;
+  P.alpha = (data && !adj) ? h->d_alpha : nullptr;
+  P.qdir = adj ? h->d_adjsrc : (data ? h->d_qdir : nullptr);
+  P.qdir_nm = adj ? 1 : 4;
   P.nfaces = (int)(h->n[0] + h->n[1]);
   P.recon_y = h->slab ? 0 : 1;
-  P.rflags = h->recon_flags | (h->slab ? 0 : 4);
+  P.rflags = (adj ? 8 : h->recon_flags) | (h->slab ? 0 : 4);
   P.absA = h->d_absA;
   P.defect = (defect && !var) ? 1 : 0;
   P.part = reinterpret_cast<R*>(h->ws.part);

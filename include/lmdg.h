@@ -226,6 +226,25 @@ int lmdg_sweep(lmdg_t* h, int scheme, int prec, const double* x, int use_q,
  * cell-direction-updates/s metric: one call = n_cells * n_dir updates. */
 int lmdg_apply(lmdg_t* h, int scheme, int prec, const double* x, double* y, void* stream);
 
+/*
+ * lmdg_apply for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same K x, with
+ * the sweep workspace (quadrant partials, strip-edge and z traces, progress words,
+ * ticket counter, wait flag) taken from a fixed array of 64 MiB that the library holds
+ * on each GPU it runs on until the process ends, instead of the handle's buffers.  The
+ * call allocates nothing (no hipMalloc, no event creation); the caller passes x and y
+ * as for lmdg_apply, and the handle's device must be the current device.  Every call on
+ * a GPU shares that GPU's array and starts by clearing its counters: calls that
+ * overlap on one GPU (several streams, threads or handles at once) race and must be
+ * serialised by the caller.  A failed bounded wait is carried over to the handle's own
+ * flag and reported by its next synchronising call, as for lmdg_apply.
+ * Errors: INVALID_ARG (as lmdg_apply; the handle's device not current; a workspace
+ * larger than the fixed array, e.g. the 2D S16 or several-source workloads on large
+ * meshes - lmdg_workspace_bytes does not apply, the message gives the size),
+ * HIP_ERROR.
+ */
+int lmdg_apply_noalloc(lmdg_t* h, int scheme, int prec, const double* x, double* y, void* stream);
+
 /* Right-hand side b of the reduced system (device moment vector). */
 int lmdg_rhs(lmdg_t* h, int scheme, int prec, double* b, void* stream);
 

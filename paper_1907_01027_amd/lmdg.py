@@ -30,7 +30,7 @@ EXPORTED = ["lmdg_status_string", "lmdg_last_error", "lmdg_quadrature_level_symm
             "lmdg_destroy", "lmdg_set_materials", "lmdg_set_sources", "lmdg_sweep", "lmdg_apply", "lmdg_rhs",
             "lmdg_recover", "lmdg_solve", "lmdg_set_augment", "lmdg_adjoint_solve", "lmdg_profile",
             "lmdg_sweep_kernel_time", "lmdg_synchronize", "lmdg_set_wait_limit", "lmdg_set_source_moments",
-            "lmdg_workspace_bytes", "lmdg_set_reconstruction"]
+            "lmdg_workspace_bytes", "lmdg_apply_noalloc", "lmdg_set_reconstruction"]
 
 
 class LmdgInfo(ctypes.Structure):
@@ -74,6 +74,7 @@ def _load():
         "lmdg_set_wait_limit": (I, [P, ctypes.c_longlong, I]),
         "lmdg_set_source_moments": (I, [P, I, P, P]),
         "lmdg_workspace_bytes": (I, [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+        "lmdg_apply_noalloc": (I, [P, I, I, P, P, P]),
         "lmdg_set_reconstruction": (I, [P, I, I]),
     }
     for name, (res, args) in sig.items():
@@ -188,6 +189,11 @@ def lmdg_sweep(h, scheme, prec, x, use_q, out, psi=None, stream=None):
 
 def lmdg_apply(h, scheme, prec, x, y, stream=None):
     _check(_lib.lmdg_apply(h, SCHEMES[scheme], PRECS[prec], _ptr(x), _ptr(y), _stream(stream)), h)
+
+
+def lmdg_apply_noalloc(h, scheme, prec, x, y, stream=None):
+    """K x with the library's fixed per-GPU workspace (no allocation)."""
+    _check(_lib.lmdg_apply_noalloc(h, SCHEMES[scheme], PRECS[prec], _ptr(x), _ptr(y), _stream(stream)), h)
 
 
 def lmdg_rhs(h, scheme, prec, b, stream=None):

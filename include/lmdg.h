@@ -208,12 +208,13 @@ int lmdg_set_sources(lmdg_t* h, int n_rhs, const double* q, void* stream);
  *          G = Sigma (L_10 + L_11 R) - Sigma M_1 P_1 R of Sec. 3.3.2 (the scattering
  *          part is taken per direction, where it cancels most of L_11 R)
  *   3D (rows of Sigma L_10 and G indexed by slope moment 1..7):
+ *   STD:   the 8 moments of P Psi (8 x 8 local solves of eq-Ljk)            8 rows
  *   LMDG:  [P_0 Psi ; Sigma L_10 Psi (7 rows)]                              8 rows
  *   RLMDG: [P_0 Psi ; G Psi (7 rows) ; P_1 R Psi (xi, eta, zeta)]           11 rows
  *   x        device moment vector or NULL (= 0)
  *   use_q    1 adds the source Q, 0 omits it
  *   out      device, n_out * n_cells doubles (n_out = 4, 4, 6 for STD, LMDG, RLMDG in
- *            2D; 8, 11 for LMDG, RLMDG in 3D)
+ *            2D; 8, 8, 11 in 3D)
  *   psi      optional device output of the angular flux (cell averages for
  *            LMDG/RLMDG, all n_P moments for STD), layout psi[(l*m + r)*n_cells + p]
  *            with l the caller's direction index, m = 1 (LMDG/RLMDG) or n_P (STD);
@@ -223,13 +224,16 @@ int lmdg_sweep(lmdg_t* h, int scheme, int prec, const double* x, int use_q,
                double* out, double* psi, void* stream);
 
 /* K x of the reduced system (device moment vectors).  Unit of the
- * cell-direction-updates/s metric: one call = n_cells * n_dir updates. */
+ * cell-direction-updates/s metric: one call = n_cells * n_dir updates.  The standard
+ * scheme on 3D handles applies the operator as printed, K Phi = Phi - P L^{-1} M Phi
+ * (eq-sndg-phi); the 2D standard and all low-memory operators use the defect form,
+ * the same operator with the sigma_s/eps parts cancelled before the sweep. */
 int lmdg_apply(lmdg_t* h, int scheme, int prec, const double* x, double* y, void* stream);
 
 /*
  * lmdg_apply for callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same K x, with
- * the sweep workspace (quadrant partials, strip-edge and z traces, progress words,
+ * the sweep workspace (quadrant partials, edge traces, 3D per-cell coefficients, progress words,
  * ticket counter, wait flag) taken from a fixed array of 64 MiB that the library holds
  * on each GPU it runs on until the process ends, instead of the handle's buffers.  The
  * call allocates nothing (no hipMalloc, no event creation); the caller passes x and y

@@ -207,7 +207,7 @@ int lmdg_quadrature_level_symmetric(int dim, int order, int capacity, int* n_dir
   return LMDG_OK;
 }
 
-// Grow the per-right-hand-side workspaces (partials, strip edges, z-trace ring,
+// Grow the per-right-hand-side workspaces (partials, strip edges, 3D coefficients,
 // progress words, scratch vectors, sources) to n_rhs right-hand sides.
 static int ensure_rhs_capacity(lmdg_t* h, int n_rhs) {
   using namespace lmdg;
@@ -359,9 +359,9 @@ static int create_impl(int dim, const int64_t* n, const double* length, int n_di
     h->ws.prog_words = (size_t)4 * h->nstrips;
   } else {
     h->ws.part_bytes = (size_t)8 * 10 * nc * sizeof(double);
-    h->ws.edge_bytes = (size_t)8 * n[2] * h->nstrips * n[0] * 4 * h->dslots * sizeof(double);
-    h->ws.zbuf_bytes = (size_t)8 * 2 * n[1] * n[0] * 4 * h->dslots * sizeof(double);
-    h->ws.prog_words = (size_t)8 * n[2] * h->nstrips;
+    h->ws.edge_bytes = lmdg::sweep3d_edge_bytes(h);
+    h->ws.zbuf_bytes = lmdg::sweep3d_coef_bytes(h);
+    h->ws.prog_words = lmdg::sweep3d_prog_words(h);
   }
   int dev = 0;
   hipGetDevice(&dev);
@@ -657,7 +657,8 @@ int apply_op(lmdg_t* h, int scheme, int prec, const double* x, double* y, hipStr
   }
   // the reconstruction variants of RLMDG use the plain form (eq-nonrec-block applied as
   // printed: K x = [x_0 - P_0 psi ; B_11 x_1 - G psi])
-  const bool defect = !(scheme == LMDG_SCHEME_RLMDG && h->recon_flags != 0);
+  // the 3D standard scheme has the plain form only
+  const bool defect = !(scheme == LMDG_SCHEME_RLMDG && h->recon_flags != 0) && !(h->dim == 3 && scheme == LMDG_SCHEME_STD);
   int rc = lmdg::launch_sweep(h, scheme, prec, x, false, nullptr, st, defect);
   if (rc != LMDG_OK) return rc;
   lmdg::launch_combine(h, scheme, prec, defect ? lmdg::kApplyDefect : lmdg::kApply, x, y, st);

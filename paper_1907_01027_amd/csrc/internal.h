@@ -61,26 +61,35 @@ struct SweepParams {
   unsigned int wait_bias;  // 0; 1 makes every wait target unreachable (failure-handling tests)
 };
 
-// Everything the 3D sweep kernel reads (LMDG, RLMDG); passed by value.
+// Per-cell source coefficients of the 3D sweeps (sweep3d.hip coef3_kernel); passed by value.
+struct Coef3Params {
+  int n[3];
+  int n_rhs;
+  int defect;            // 1: x enters through the defect source (low-memory schemes)
+  long long ncell;
+  double A[3];           // face measures h_y h_z, h_x h_z, h_x h_y
+  const double* x;       // moment vectors (n_rhs * 8 * ncell) or null
+  const double* qA;      // eps q V (n_rhs * ncell) or null
+  const double* sigtA;   // (sigma_s/eps + eps sigma_a) V
+  const double* scatA;   // (sigma_s/eps) V
+  const double* absA;    // eps sigma_a V
+};
+
+// Everything the 3D sweep kernel reads; passed by value.
 template <typename R>
 struct Sweep3Params {
-  int nx, ny, nz, nstrips, cw, lcw, nchunks, dslots, n_items, n_rhs;
+  int nx, ny, nz, nstrips, nblk, dslots, n_items, n_rhs;
   double h[3];
   long long ncell;
   const double* dirs;    // [8][dslots][kDirStride]: Ox, Oy, Oz, w, index
-  const double* x;       // moment vectors (n_rhs * 8 * ncell) or null
-  const double* sigtA;   // (sigma_s/eps + eps sigma_a) V
-  const double* scatA;   // (sigma_s/eps) V
-  const double* qA;      // eps q V (n_rhs * ncell) or null
-  const double* absA;    // eps sigma_a V
-  int defect;
+  const R* coef;         // per-cell coefficients (coef3_kernel layout)
   R* part;               // [n_rhs][8][NOUT][ncell]
-  R* yedge;              // [n_rhs][8][nz][nstrips][nx][NF][dslots]
-  R* zbuf;               // [n_rhs][8][2][ny][nx][NF][dslots] (two-plane ring)
-  long long yedge_ostride, zbuf_ostride;   // per (rhs, octant)
-  double* psi;           // optional angular flux [n_rhs][n_dir][ncell]
+  R* xedge;              // [n_rhs][8][nz][nstrips][nblk][16][dslots][NF] last-column traces
+  R* yedge;              // [n_rhs][8][nz][nstrips][nx][dslots][NF] top-row traces
+  long long xedge_ostride, yedge_ostride;   // per (rhs, octant)
+  double* psi;           // optional angular flux [n_rhs][n_dir][(8 moments, STD)][ncell]
   long long psi_rstride;
-  unsigned long long* prog;   // [n_rhs][8][nz][nstrips]
+  unsigned long long* prog;   // [n_rhs][8][nstrips][nblk] planes completed
   unsigned int* ticket;
   int* err;
   unsigned long long epoch;
@@ -93,7 +102,7 @@ struct Workspace {
   double* part = nullptr;       // 4 * 6 * ncell doubles (reused as floats)
   void* edge = nullptr;
   size_t edge_bytes = 0;
-  void* zbuf = nullptr;          // 3D: two-plane ring of z traces
+  void* zbuf = nullptr;          // 3D: per-cell sweep coefficients
   size_t zbuf_bytes = 0;          // per right-hand side
   size_t part_bytes = 0;          // per right-hand side
   size_t prog_words = 0;          // per right-hand side
@@ -210,6 +219,10 @@ int launch_sweep(lmdg_handle* h, int scheme, int prec, const double* x, bool use
                  bool psi_by_slot = false);
 int launch_sweep3d(lmdg_handle* h, int scheme, int prec, const double* x, bool use_q, double* psi,
                    hipStream_t st, bool defect);
+// workspace of the 3D sweeps per right-hand side (sweep3d.hip)
+size_t sweep3d_edge_bytes(const lmdg_handle* h);
+size_t sweep3d_coef_bytes(const lmdg_handle* h);
+size_t sweep3d_prog_words(const lmdg_handle* h);
 void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double* x,
                     double* out, hipStream_t st);
 void launch_sum_quadrants(lmdg_handle* h, int scheme, int prec, double* out, hipStream_t st);

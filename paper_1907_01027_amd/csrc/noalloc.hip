@@ -1,5 +1,5 @@
-// K x without allocation: the sweep workspace of lmdg_apply (quadrant partials, strip
-// edge traces, z-trace ring, progress words, ticket counter and error flag) taken from a
+// K x without allocation: the sweep workspace of lmdg_apply (quadrant partials, edge
+// traces, 3D per-cell coefficients, progress words, ticket counter and error flag) taken from a
 // fixed device array instead of the handle's buffers, for callers that cannot allocate.
 #include <mutex>
 
@@ -63,7 +63,7 @@ extern "C" int lmdg_apply_noalloc(lmdg_t* h, int scheme, int prec, const double*
   int rc = check_hip(h, hipGetDevice(&dev), "hipGetDevice");
   if (rc != LMDG_OK) return rc;
   if (dev != h->device) return set_error(h, LMDG_INVALID_ARG, "the handle's device is not the current device");
-  // layout: flags (ticket, error flag) | progress words | edge traces | z-trace ring | partials
+  // layout: flags (ticket, error flag) | progress words | edge traces | 3D coefficients | partials
   const size_t nr = (size_t)h->n_rhs;
   const size_t flags = 256;
   const size_t prog = round256(h->ws.prog_words * nr * sizeof(unsigned long long));

@@ -194,18 +194,17 @@ __global__ void combine_lm_kernel(int mode, int nr, int nsl, int nx, int ny, dou
 // Standard scheme: K Phi = Phi - P L^{-1} M Phi (eq-sndg-phi); right-hand side and
 // recovered scalar flux are the plain quadrant sums.
 template <typename R>
-__global__ void combine_std_kernel(int mode, int nr, int nsl, long long nc, const double* __restrict__ x_all,
+__global__ void combine_std_kernel(int mode, int nr, int nsl, int np, long long nc, const double* __restrict__ x_all,
                                    const R* __restrict__ part_all, double* __restrict__ out_all) {
   for (long long pr = blockIdx.x * (long long)blockDim.x + threadIdx.x; pr < nr * nc;
        pr += (long long)gridDim.x * blockDim.x) {
     const long long rh = pr / nc, p = pr - rh * nc;
-    const double* x = x_all ? x_all + rh * 4 * nc : nullptr;
-    const R* part = part_all + rh * nsl * 4 * nc;
-    double* out = out_all + rh * 4 * nc;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    const double* x = x_all ? x_all + rh * np * nc : nullptr;
+    const R* part = part_all + rh * nsl * np * nc;
+    double* out = out_all + rh * np * nc;
+    for (int m = 0; m < np; ++m) {
       double acc = 0;
-      for (int q = 0; q < nsl; ++q) acc += (double)part[((long long)q * 4 + m) * nc + p];
+      for (int q = 0; q < nsl; ++q) acc += (double)part[((long long)q * np + m) * nc + p];
       // kApplyDefect: the sweep already produced P L^{-1}(defect source) = K Phi
       out[m * nc + p] = (mode == kApply) ? x[m * nc + p] - acc : acc;
     }
@@ -451,7 +450,7 @@ int dots_partials() { return kDotBlocks; }
 
 void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double* x, double* out,
                     hipStream_t st) {
-  if (h->dim == 3) {
+  if (h->dim == 3 && scheme != LMDG_SCHEME_STD) {
     launch_combine3(h, scheme, prec, mode, x, out, st);
     return;
   }
@@ -460,11 +459,12 @@ void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double
   const int g = std::min(grid_for(nc * nr), 4096);
   const int nx = (int)h->n[0], ny = (int)h->n[1];
   if (scheme == LMDG_SCHEME_STD) {
+    // 3D: the plain form (one slice per octant of the eight moments)
     if (prec == LMDG_PREC_FP64)
-      hipLaunchKernelGGL(combine_std_kernel<double>, dim3(g), dim3(kBlock), 0, st, mode, nr, h->last_nsl, nc, x,
-                         (const double*)h->ws.part, out);
+      hipLaunchKernelGGL(combine_std_kernel<double>, dim3(g), dim3(kBlock), 0, st, mode, nr, h->last_nsl, h->np, nc,
+                         x, (const double*)h->ws.part, out);
     else
-      hipLaunchKernelGGL(combine_std_kernel<float>, dim3(g), dim3(kBlock), 0, st, mode, nr, h->last_nsl, nc, x,
+      hipLaunchKernelGGL(combine_std_kernel<float>, dim3(g), dim3(kBlock), 0, st, mode, nr, h->last_nsl, h->np, nc, x,
                          (const float*)h->ws.part, out);
     return;
   }
@@ -498,12 +498,12 @@ void launch_combine(lmdg_handle* h, int scheme, int prec, int mode, const double
 }
 
 void launch_sum_quadrants(lmdg_handle* h, int scheme, int prec, double* out, hipStream_t st) {
-  if (h->dim == 3) {
+  if (h->dim == 3 && scheme != LMDG_SCHEME_STD) {
     launch_sum_octants(h, scheme, prec, out, st);
     return;
   }
-  const int nout = scheme == LMDG_SCHEME_STD ? 4 : (scheme == LMDG_SCHEME_LMDG ? 3 : 6);
-  const int nout_abi = scheme == LMDG_SCHEME_RLMDG ? 6 : 4;
+  const int nout = scheme == LMDG_SCHEME_STD ? h->np : (scheme == LMDG_SCHEME_LMDG ? 3 : 6);
+  const int nout_abi = scheme == LMDG_SCHEME_RLMDG ? 6 : h->np;
   const int g = std::min(grid_for(h->ncell * h->n_rhs), 4096);
   if (prec == LMDG_PREC_FP64)
     hipLaunchKernelGGL(sum_quadrants_kernel<double>, dim3(g), dim3(kBlock), 0, st, nout, nout_abi, h->n_rhs,

@@ -1,34 +1,47 @@
-// Transport sweeps of the low-memory schemes on a uniform 3D Cartesian mesh (gfx950).
+// Transport sweeps on a uniform 3D Cartesian mesh (gfx950): the standard Q^1 scheme
+// (eq-Ljk with trilinear elements) and the low-memory schemes LMDG and RLMDG.
 //
-// The 2D decomposition (sweep2d.hip) extended by one axis: a work item is
-// (octant o, plane kz in sweep order, strip s of 16 y-rows, right-hand side); the
-// workgroup holds every direction slot of the octant, lanes = 16 rows x 4 slots, and
-// the x axis is walked in skewed steps (row r handles column t - r at step t).
-// Upwind values arrive from three sides:
-//   x  the lane's own previous cell (registers);
-//   y  the lane below through one DPP row shift, row 0 from the strip-edge buffer
-//      written by strip s - 1 of the same plane;
-//   z  the plane below: every cell writes its z-outflow traces to a two-plane ring
-//      buffer; plane kz stages the traces of plane kz - 1 for a chunk in LDS.
-// An item waits for (kz, s - 1) and (kz - 1, s) to have finished the columns of the
-// chunk (epoch-tagged progress words, bounded spin).  The ring buffer is safe with two
-// planes: plane kz overwrites the slot that plane kz - 1 reads only at columns that
-// plane kz - 1 has already published, i.e. finished reading.
+// Work decomposition.  A work item is (octant o, strip s of 16 rows along y, block b of
+// CB columns along x, right-hand side).  It carries its 16 x CB column of cells through
+// every plane along z in sweep order, so that the z-inflow of a cell is the z-outflow the
+// same lane produced one plane earlier and never leaves the registers.  The workgroup
+// holds every direction slot of the octant: lanes are 16 rows x 4 slots per wave, W waves.
+// Inside an item the cells are visited in skewed order: at step tau, row r handles the
+// cell with index lambda = tau - r in the sequence (plane, column) of the block, lambda =
+// plane * CB + column.  Then
+//   x-inflow  the lane's previous cell (registers), or in the block's first column the
+//             x-outflow of block b - 1 at the same plane and row (x-edge buffer);
+//   y-inflow  the lane of the row below, whose previous step handled the same cell (DPP
+//             row shift); row 0 takes the y-outflow of strip s - 1 (y-edge buffer);
+//   z-inflow  the lane's own outflow CB steps earlier: the steps are unrolled in periods
+//             of CB, and step u of a period reads and rewrites register slot u.
+// Row r trails row 0 by r steps, so in period p the rows cover planes p - L .. p with
+// L = ceil(15 / CB); plane q is complete after period q + L.  Per period the item stages
+// the coefficients of plane p + 1 in LDS (a ring of L + 2 plane buffers), sums its outputs
+// over the slots and waves of the octant, and publishes how many planes it has completed;
+// it waits for (s, b - 1) and (s - 1, b) to have completed plane p before period p.
 //
-// Local solves follow Sec. 3.2 (L_00, scalar per cell and direction) and Sec. 3.3
-// (L~_00 = L_00 + L_01 R with the upwind slopes c_a = s_a k_a (psi - psi_up,a),
+// Exchange through global memory uses agent-scope atomic loads and stores only (edge
+// traces and progress words), so no cache maintenance is needed: a wave waits for its own
+// trace stores to complete before the workgroup barrier that precedes the progress store,
+// and a consumer issues its trace loads after the barrier that follows its wait.
+//
+// Local solves.  LMDG and RLMDG follow Sec. 3.2 (L_00, scalar per cell and direction) and
+// Sec. 3.3 (L~_00 = L_00 + L_01 R with the upwind slopes c_a = s_a k_a (psi - psi_up,a),
 // k_a = 1 in the inflow cell of the line and 1/2 elsewhere).  With face measures
 // A_x = h_y h_z, A_y = h_x h_z, A_z = h_x h_y and V = h_x h_y h_z:
 //   psi (sigma_t V + sum_a |O_a| A_a (1 + k_a)) = src + sum_a |O_a| A_a (T_a + k_a psi_a)
 // where T_a is the upwind cell's outflow face value and psi_a its average (LMDG:
-// k_a = 0, T_a = psi_a).  Per direction the sweep accumulates the weighted rows of
-// the second block row of the reduced system: for a slope test function b_m,
-//   xi_a      : O_a A_a (T_a - psi) + (sigma_t V / 3 + |O_a| A_a) c_a
+// k_a = 0, T_a = psi_a).  Per direction the sweep accumulates the weighted rows of the
+// second block row of the reduced system: for a slope test function b_m,
+//   xi_a      : O_a A_a (T_a - psi) + (eps sigma_a V / 3 + |O_a| A_a) c_a
 //               + sum_{b != a} |O_b| A_b (c_a - c_a of the b-upwind cell) / 3
 //   xi_a xi_b : (O_a A_a (c_b of the a-upwind cell - c_b) + O_b A_b (c_a of the
 //               b-upwind cell - c_a)) / 3
 //   xi eta zeta: 0
 // (LMDG keeps only O_a A_a (psi_a - psi) on xi_a), plus w c_a for P_1 R (RLMDG).
+// The standard scheme solves the 8 x 8 block of eq-Ljk for the trilinear moments c_m
+// (m = b_x + 2 b_y + 4 b_z, basis prod_a xi_a^{b_a}), see cell_std3.
 #include "internal.h"
 #include "sweep_common.h"
 
@@ -36,15 +49,18 @@ namespace lmdg {
 namespace {
 
 template <int S> struct Traits3;
-// NOUT: per-cell outputs [P_0, xi, eta, zeta rows (, xi eta, xi zeta, eta zeta rows,
-// P_1 R xi, eta, zeta)]; NF: values handed downwind per axis; NRAW: FP64 inputs per cell
-// NC: staged values per cell: sigma_t V, the source coefficients a, b_x, b_y, b_z, and for
-// RLMDG eps sigma_a V / 3 (the slope mass term of the second block row)
-template <> struct Traits3<LMDG_SCHEME_LMDG> { static constexpr int NOUT = 4, NF = 1, NC = 5; };
-template <> struct Traits3<LMDG_SCHEME_RLMDG> { static constexpr int NOUT = 10, NF = 4, NC = 6; };
-constexpr int kNRAW3 = 17;
-constexpr int kMAXC3 = 2;   // staged cells per thread
-constexpr int kStepGroup3 = 2;  // steps per unrolled group (measured best on gfx950)
+// NOUT: per-cell outputs; NF: values handed downwind per axis; NK: staged coefficients
+// per cell; NA: per-source coefficient arrays of coef3_kernel.
+//   STD   outputs w c_m (m = 0..7); traces: the four face moments of the outflow trace;
+//         coefficients sigma_t V, a_0..a_7.
+//   LMDG  outputs [P_0, xi, eta, zeta rows]; trace psi; coefficients sigma_t V, a, b_x,
+//         b_y, b_z (src = a + |Ox| b_x + |Oy| b_y + |Oz| b_z).
+//   RLMDG outputs [P_0, xi, eta, zeta, xi eta, xi zeta, eta zeta rows, P_1 R xi, eta,
+//         zeta]; traces [outflow face value, two tangential slopes, cell value];
+//         coefficients as LMDG plus eps sigma_a V / 3.
+template <> struct Traits3<LMDG_SCHEME_STD> { static constexpr int NOUT = 8, NF = 4, NK = 9, NA = 8; };
+template <> struct Traits3<LMDG_SCHEME_LMDG> { static constexpr int NOUT = 4, NF = 1, NK = 5, NA = 7; };
+template <> struct Traits3<LMDG_SCHEME_RLMDG> { static constexpr int NOUT = 10, NF = 4, NK = 6, NA = 7; };
 
 template <typename R>
 struct Dir3 {
@@ -55,85 +71,185 @@ struct Dir3 {
   int idx;
 };
 
-// Raw FP64 inputs of one cell: x_0 at the cell and at its upwind and second-upwind
-// neighbours along x, y, z; the slope moments xi, eta, zeta of x_1 at the cell and
-// the upwind neighbour along the same axis; the four material values.  Zero outside.
+__host__ __device__ constexpr int popc3(int m) { return (m & 1) + ((m >> 1) & 1) + ((m >> 2) & 1); }
+// (1/3)^(number of linear factors of mode m): the L2 norm squared of b_m on [-1,1]^3 / 8
 template <typename R>
-__device__ __forceinline__ void raw_load3_impl(const Sweep3Params<R>& P, const double* x, const double* qA,
-                                               const int si[3], int c, int jr, int kz, double* raw) {
-#pragma unroll
-  for (int k = 0; k < kNRAW3; ++k) raw[k] = 0.0;
-  if (c < 0 || c >= P.nx || jr >= P.ny) return;
-  const long long nx = P.nx, nxy = (long long)P.nx * P.ny, nc = P.ncell;
-  const int i = si[0] > 0 ? c : P.nx - 1 - c;
-  const int j = si[1] > 0 ? jr : P.ny - 1 - jr;
-  const int k = si[2] > 0 ? kz : P.nz - 1 - kz;
-  const long long cell = (long long)k * nxy + (long long)j * nx + i;
-  const long long dx = si[0], dy = si[1] * nx, dz = si[2] * nxy;  // cell - d: upwind
-  if (x) {
-    raw[0] = x[cell];
-    if (c > 0) raw[1] = x[cell - dx];
-    if (c > 1) raw[2] = x[cell - 2 * dx];
-    if (jr > 0) raw[3] = x[cell - dy];
-    if (jr > 1) raw[4] = x[cell - 2 * dy];
-    if (kz > 0) raw[5] = x[cell - dz];
-    if (kz > 1) raw[6] = x[cell - 2 * dz];
-    raw[7] = x[1 * nc + cell];
-    if (c > 0) raw[8] = x[1 * nc + cell - dx];
-    raw[9] = x[2 * nc + cell];
-    if (jr > 0) raw[10] = x[2 * nc + cell - dy];
-    raw[11] = x[4 * nc + cell];
-    if (kz > 0) raw[12] = x[4 * nc + cell - dz];
-  }
-  raw[13] = P.sigtA[cell];
-  raw[14] = P.absA[cell];
-  raw[15] = P.scatA[cell];
-  raw[16] = qA ? qA[cell] : 0.0;
+__device__ __forceinline__ constexpr R mass3(int m) {
+  return popc3(m) == 0 ? R(1) : (popc3(m) == 1 ? R(1) / R(3) : (popc3(m) == 2 ? R(1) / R(9) : R(1) / R(27)));
+}
+// Index of a cell mode t without axis a among the four modes of a face normal to a:
+// bit 0 the lower remaining axis, bit 1 the upper one.
+__device__ __forceinline__ constexpr int face_idx(int a, int t) {
+  return a == 0 ? (t >> 1) : (a == 1 ? ((t & 1) | ((t >> 1) & 2)) : (t & 3));
+}
+// The cell mode without axis a whose face index is f (inverse of face_idx).
+__device__ __forceinline__ constexpr int face_mode(int a, int f) {
+  return a == 0 ? (f << 1) : (a == 1 ? ((f & 1) | ((f & 2) << 1)) : f);
 }
 
-// Source coefficients of one cell (FP64), src = a + |Ox| b_x + |Oy| b_y + |Oz| b_z.
-// Plain form M_0 x_0 + L_01 Sigma^T x_1 (+ Q~_0):
-//   a = (sigma_s/eps) V x_0 + eps q V,  b_a = s_a A_a (slope_a(K) - slope_a(upwind)).
-// Defect form (L~_00 Sigma_0^T - M_0) x_0 - L_01 Sigma^T x_1 (the same operator with
-// the sigma_s/eps parts cancelled; see the 2D kernel):
-//   a = eps sigma_a V x_0 + eps q V,
-//   b_a = -s_a A_a (slope_a(K) - slope_a(upwind)) + A_a (T_a(K) - T_a(upwind))
-// with T the outflow face value of x_0 along a (x_0 itself for LMDG; x_0 + k (x_0 -
-// x_0,up) for RLMDG; zero outside the mesh).
+// Per-cell source coefficients shared by the eight octants, computed once per launch in
+// FP64 and stored in the sweep precision R, so that the sweep stages six (nine) values
+// per cell and octant instead of gathering the neighbourhood of every cell.
+//
+// LMDG/RLMDG, out [n_rhs][7][ncell]: a, then b_a for s_a = +1 and s_a = -1 per axis a
+// (array 1 + 2 a + (s_a < 0)); then [2][ncell]: sigma_t V and eps sigma_a V / 3.
+//   Plain form  M_0 x_0 + L_01 Sigma^T x_1 (+ Q~_0):
+//     a = (sigma_s/eps) V x_0 + eps q V,  b_a = s_a A_a (slope_a(K) - slope_a(upwind)).
+//   Defect form (L~_00 Sigma_0^T - M_0) x_0 - L_01 Sigma^T x_1 (the same operator with the
+//   sigma_s/eps parts cancelled, as in the 2D kernel):
+//     a = eps sigma_a V x_0 + eps q V,
+//     b_a = -s_a A_a (slope_a(K) - slope_a(upwind)) + A_a (T_a(K) - T_a(upwind))
+//   with T the outflow face value of x_0 along a (x_0 itself for LMDG; x_0 + k (x_0 -
+//   x_0,up) for RLMDG; zero outside the mesh).  The upwind neighbour along a is the cell
+//   at -s_a e_a; its distance from the inflow boundary decides k.
+// STD, out [n_rhs][8][ncell]: a_m = (sigma_s/eps) V mass_m x_m (+ eps q V for m = 0),
+// the plain form M Phi (+ Q) of eq-sndg-phi; then [1][ncell]: sigma_t V.
 template <typename R, int S>
-__device__ __forceinline__ void raw_coef3(const double* raw, const int pos[3], const int si[3], const double A[3],
-                                          bool defect, R* coef, int cstride) {
-  const double x0 = raw[0];
-  const double up[3] = {raw[1], raw[3], raw[5]}, upup[3] = {raw[2], raw[4], raw[6]};
-  const double sl[3] = {raw[7], raw[9], raw[11]}, slu[3] = {raw[8], raw[10], raw[12]};
-  const double sigtA = raw[13], absA = raw[14], scatA = raw[15], qA = raw[16];
-  coef[0] = (R)sigtA;
-  coef[cstride] = (R)((defect ? absA : scatA) * x0 + qA);
+__global__ void coef3_kernel(Coef3Params P, R* __restrict__ out) {
+  constexpr int NA = Traits3<S>::NA;
+  const long long nc = P.ncell;
+  const long long stride[3] = {1, P.n[0], (long long)P.n[0] * P.n[1]};
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < P.n_rhs * nc;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int rh = (int)(e / nc);
+    const long long cell = e - rh * nc;
+    const double* x = P.x ? P.x + (long long)rh * 8 * nc : nullptr;
+    const double qA = P.qA ? P.qA[(long long)rh * nc + cell] : 0.0;
+    R* o = out + (long long)rh * NA * nc + cell;
+    if constexpr (S == LMDG_SCHEME_STD) {
+      const double scat = P.scatA[cell];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const double v = x ? scat * mass3<double>(m) * x[m * nc + cell] : 0.0;
+        o[m * nc] = (R)(m == 0 ? v + qA : v);
+      }
+      if (rh == 0) out[(long long)P.n_rhs * NA * nc + cell] = (R)P.sigtA[cell];
+    } else {
+      const int idx[3] = {(int)(cell % P.n[0]), (int)((cell / P.n[0]) % P.n[1]),
+                          (int)(cell / ((long long)P.n[0] * P.n[1]))};
+      const double x0 = x ? x[cell] : 0.0;
+      o[0] = (R)((P.defect ? P.absA[cell] : P.scatA[cell]) * x0 + qA);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int sm = 1 << a;  // slope moment of axis a
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg) {
+          const int sgn = sg ? -1 : 1;
+          const int pos = sgn > 0 ? idx[a] : P.n[a] - 1 - idx[a];  // upwind cells inside the mesh
+          double b = 0.0;
+          if (x) {
+            const long long up = cell - sgn * stride[a];
+            const double u1 = pos >= 1 ? x[up] : 0.0;
+            const double u2 = pos >= 2 ? x[up - sgn * stride[a]] : 0.0;
+            const double sl = x[sm * nc + cell], slu = pos >= 1 ? x[sm * nc + up] : 0.0;
+            const double ds = sgn * P.A[a] * (sl - slu);
+            b = ds;
+            if (P.defect) {
+              double t = x0, tu = u1;
+              if (S == LMDG_SCHEME_RLMDG) {
+                t = x0 + (pos == 0 ? 1.0 : 0.5) * (x0 - u1);
+                tu = pos > 0 ? u1 + (pos == 1 ? 1.0 : 0.5) * (u1 - u2) : 0.0;
+              }
+              b = -ds + P.A[a] * (t - tu);
+            }
+          }
+          o[(1 + 2 * a + sg) * nc] = (R)b;
+        }
+      }
+      if (rh == 0) {
+        out[(long long)P.n_rhs * NA * nc + cell] = (R)P.sigtA[cell];
+        out[((long long)P.n_rhs * NA + 1) * nc + cell] = (R)(P.absA[cell] * (1.0 / 3.0));
+      }
+    }
+  }
+}
+
+// Standard Q^1 cell (eq-Ljk in 3D): the 8 x 8 block sigma_t V M + streaming + outflow
+// faces for the trilinear moments c, right-hand side a (8 source moments) plus the
+// inflow traces.  With mass_m = (1/3)^{#linear factors of m} and for each axis a:
+//   streaming  -int u Omega.grad b_n:  row n with bit a, column n - a: -2 O_a A_a mass_{n-a}
+//   outflow    int_{xi_a = s_a} |O_a| u b_n:  rows and columns n, m that differ at most in
+//              bit a: |O_a| A_a s_a^{b_a(n) + b_a(m)} mass_{n-a}
+//   inflow     the upwind cell's outflow trace T (face moments over the other two axes)
+//              enters row n as |O_a| A_a (-s_a)^{b_a(n)} mass_{n-a} T_{n-a}.
+// The symmetric part of the block is positive definite, so elimination needs no pivoting.
+// Outflow traces handed downwind along a: T_t = c_t + s_a c_{t+a} for the modes t without a.
+template <typename R>
+__device__ __forceinline__ void cell_std3(const Dir3<R>& d, const int si[3], const R* src, R sigV, const R* xin,
+                                          const R* yin, const R* zin, R* xo, R* yo, R* zo, R* o, R* c) {
+  R m[8][8], b[8];
+#pragma unroll
+  for (int n = 0; n < 8; ++n) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m[n][k] = R(0);
+    m[n][n] = sigV * mass3<R>(n);
+    b[n] = src[n];
+  }
+  const R* tin[3] = {xin, yin, zin};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double ds = si[a] * A[a] * (sl[a] - slu[a]);
-    double b = ds;
-    if (defect) {
-      double t = x0, tu = up[a];
-      if (S == LMDG_SCHEME_RLMDG) {
-        t = x0 + (pos[a] == 0 ? 1.0 : 0.5) * (x0 - up[a]);
-        tu = pos[a] > 0 ? up[a] + (pos[a] == 1 ? 1.0 : 0.5) * (up[a] - upup[a]) : 0.0;
-      }
-      b = -ds + A[a] * (t - tu);
+    const int bit = 1 << a;
+    const R sg = R(si[a]);
+#pragma unroll
+    for (int n = 0; n < 8; ++n) {
+      const int t = n & ~bit;
+      const R fm = mass3<R>(t);
+      if (n & bit) m[n][t] += R(-2) * d.oA[a] * fm;
+      // outflow: columns t and t + a
+      const R sn = (n & bit) ? sg : R(1);
+      m[n][t] += d.aA[a] * sn * fm;
+      m[n][t | bit] += d.aA[a] * sn * sg * fm;
+      // inflow
+      b[n] += d.aA[a] * ((n & bit) ? -sg : R(1)) * fm * tin[a][face_idx(a, t)];
     }
-    coef[(2 + a) * cstride] = (R)b;
   }
-  if (S == LMDG_SCHEME_RLMDG) coef[5 * cstride] = (R)(absA * (1.0 / 3.0));
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const R inv = R(1) / m[k][k];
+#pragma unroll
+    for (int i = k + 1; i < 8; ++i) {
+      const R f = m[i][k] * inv;
+#pragma unroll
+      for (int j = k + 1; j < 8; ++j) m[i][j] -= f * m[k][j];
+      b[i] -= f * b[k];
+    }
+  }
+#pragma unroll
+  for (int k = 7; k >= 0; --k) {
+    R acc = b[k];
+#pragma unroll
+    for (int j = k + 1; j < 8; ++j) acc -= m[k][j] * c[j];
+    c[k] = acc / m[k][k];
+  }
+  R* tout[3] = {xo, yo, zo};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int bit = 1 << a;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const int t = face_mode(a, f);
+      tout[a][f] = c[t] + R(si[a]) * c[t | bit];
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < 8; ++n) o[n] = d.w * c[n];
 }
 
-template <typename R, int S, int MAXW>
+template <typename R, int S, int MAXW, int CB>
 __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
   constexpr int NOUT = Traits3<S>::NOUT;
   constexpr int NOUTP = (NOUT + 3) & ~3;  // rows of red, padded to whole lane groups
   constexpr int NF = Traits3<S>::NF;
-  constexpr int NC = Traits3<S>::NC;
-  constexpr int MAXC = MAXW > 4 ? 1 : kMAXC3;
+  constexpr int NK = Traits3<S>::NK;
+  constexpr int NA = Traits3<S>::NA;
+  constexpr int LCB = CB == 4 ? 2 : (CB == 8 ? 3 : 4);
+  static_assert((1 << LCB) == CB, "CB is 4, 8 or 16");
+  constexpr int CB16 = CB * kRows;
+  constexpr int L = (kRows - 1 + CB - 1) / CB;  // periods by which row 15 trails row 0
+  constexpr int NBUF = L + 2;                   // staged planes: p - L .. p and p + 1
+  constexpr int MAXC = (CB16 + 63) / 64;        // staged cells per thread (one wave at least)
   constexpr bool RLM = S == LMDG_SCHEME_RLMDG;
+  constexpr bool STDS = S == LMDG_SCHEME_STD;
   extern __shared__ unsigned char smem_raw[];
   __shared__ int s_item;
 
@@ -144,46 +260,42 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
   const int r = lane & 15;
   const int slot = wv * 4 + (lane >> 4);
   const long long nc = P.ncell;
-  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int nx = P.nx, ny = P.ny, nz = P.nz, nstrips = P.nstrips, nblk = P.nblk;
   const long long nxy = (long long)nx * ny;
-  const int lcw = P.lcw;
-  const int cw = 1 << lcw;
-  const int ncells = kRows << lcw;
   const int ds = P.dslots;
   const double A[3] = {P.h[1] * P.h[2], P.h[0] * P.h[2], P.h[0] * P.h[1]};
-  // LDS: red [cw][W][NOUTP][16] | coef [2][NC][cw][16] | eds [cw][NF][ds] | zds [cw][16][NF][ds]
+  // LDS: red [CB][W][NOUTP][16] (+1 pad per step) | cbuf [NBUF][NK][CB][16] | eds [CB][ds][NF]
   R* red = reinterpret_cast<R*>(smem_raw);
-  // one column's block of red holds W x NOUTP x 16 values plus one pad, so that the
-  // reduction's reads of consecutive columns fall in different banks
+  // one step's block of red holds W x NOUTP x 16 values plus one pad, so that the
+  // reduction's reads of consecutive steps fall in different banks
   const int red_tt = W * NOUTP * kRows + 1;
-  R* coef = red + (size_t)cw * red_tt;
-  R* eds = coef + (size_t)2 * ncells * NC;
-  R* zds = eds + (size_t)cw * NF * ds;
+  R* cbuf = red + (size_t)CB * red_tt;
+  R* eds = cbuf + (size_t)NBUF * NK * CB16;
 
   for (;;) {
     if (tid == 0) s_item = (int)(atomicAdd(P.ticket, 1u) - P.ticket_base);
     __syncthreads();
     const int item = s_item;
     if (item >= P.n_items) break;
-    // item = ((kz * nstrips + s) * n_rhs + rhs) * 8 + octant: both items it waits for,
-    // (kz, s - 1) and (kz - 1, s), come earlier
+    // item = ((s * nblk + b) * n_rhs + rhs) * 8 + octant: both items it waits for,
+    // (s, b - 1) and (s - 1, b), come earlier
     const int o = item & 7;
     int rest = item >> 3;
     const int rh = rest % P.n_rhs;
     rest /= P.n_rhs;
-    const int s = rest % P.nstrips;
-    const int kz = rest / P.nstrips;
+    const int b = rest % nblk;
+    const int s = rest / nblk;
     int si[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) si[a] = ((o >> a) & 1) ? -1 : 1;
-    const double* xr = P.x ? P.x + (long long)rh * 8 * nc : nullptr;
-    const double* qAr = P.qA ? P.qA + (long long)rh * nc : nullptr;
-    R* const partr = P.part + (long long)rh * 8 * NOUT * nc;
     const long long ro = (long long)rh * 8 + o;
-    R* const yedge = P.yedge + ro * P.yedge_ostride;                    // [nz][nstrips][nx][NF][ds]
-    R* const zring = P.zbuf + ro * P.zbuf_ostride;                      // [2][ny][nx][NF][ds]
-    unsigned long long* const progr = P.prog + ro * (long long)nz * P.nstrips;
+    R* const partr = P.part + ro * NOUT * nc;
+    R* const xeb = P.xedge + ro * P.xedge_ostride;   // [nz][nstrips][nblk][16][ds][NF]
+    R* const yeb = P.yedge + ro * P.yedge_ostride;   // [nz][nstrips][nx][ds][NF]
+    unsigned long long* const progr = P.prog + ro * (long long)nstrips * nblk;
     double* const psir = P.psi ? P.psi + rh * P.psi_rstride : nullptr;
+    const R* const cf_rh = P.coef + (long long)rh * NA * nc;
+    const R* const cf_sh = P.coef + (long long)P.n_rhs * NA * nc;  // shared: sigma_t V (, eps sigma_a V / 3)
 
     Dir3<R> d;
     {
@@ -200,322 +312,368 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
     const int jr = s * kRows + r;
     const bool row_ok = jr < ny;
     const int j = si[1] > 0 ? jr : ny - 1 - jr;
-    const int kk = si[2] > 0 ? kz : nz - 1 - kz;
+    const int c0 = b * CB;  // first column of the block (sweep order)
     const R ky = (jr == 0) ? R(1) : R(0.5);
-    const R kzf = (kz == 0) ? R(1) : R(0.5);
-    const R* zin_ring = zring + (long long)((kz + 1) & 1) * nxy * NF * ds;  // plane kz - 1
-    R* const zout_ring = zring + (long long)(kz & 1) * nxy * NF * ds;
 
-    double raw[MAXC][kNRAW3];
-    auto stage_load = [&](int k) {
+    // coefficients of the cells of plane q of the block: loaded to registers (stage_load)
+    // and stored to plane buffer q % NBUF (stage_store); cells outside the mesh get
+    // sigma_t V = 1 and zero sources, so that every lane computes finite values
+    R stg[MAXC][NK];
+    auto stage_load = [&](int q) {
 #pragma unroll
-      for (int m = 0; m < MAXC; ++m) {
-        const int e = tid + m * blockDim.x;
-        const int rr = e >> lcw, tt = e & (cw - 1);
-        const int c = (e < ncells) ? (k << lcw) + tt - rr : -1;
-        raw_load3_impl<R>(P, xr, qAr, si, c, s * kRows + rr, kz, raw[m]);
+      for (int mc = 0; mc < MAXC; ++mc) {
+        const int e = tid + mc * (int)blockDim.x;
+        const int cl = e & (CB - 1), rr = e >> LCB;
+        const int c = c0 + cl, jr2 = s * kRows + rr;
+        const bool in = e < CB16 && c < nx && jr2 < ny && q < nz;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) stg[mc][k] = (k == 0) ? R(1) : R(0);
+        if (in) {
+          const int i2 = si[0] > 0 ? c : nx - 1 - c;
+          const int j2 = si[1] > 0 ? jr2 : ny - 1 - jr2;
+          const int k2 = si[2] > 0 ? q : nz - 1 - q;
+          const long long cell = (long long)k2 * nxy + (long long)j2 * nx + i2;
+          stg[mc][0] = cf_sh[cell];
+          if constexpr (STDS) {
+#pragma unroll
+            for (int m = 0; m < 8; ++m) stg[mc][1 + m] = cf_rh[m * nc + cell];
+          } else {
+            stg[mc][1] = cf_rh[cell];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) stg[mc][2 + a] = cf_rh[(1 + 2 * a + (si[a] < 0)) * nc + cell];
+            if constexpr (RLM) stg[mc][5] = cf_sh[nc + cell];
+          }
+        }
       }
     };
-    auto stage_store = [&](int k, int buf) {
+    auto stage_store = [&](int buf) {
 #pragma unroll
-      for (int m = 0; m < MAXC; ++m) {
-        const int e = tid + m * blockDim.x;
-        if (e < ncells) {
-          const int rr = e >> lcw, tt = e & (cw - 1);
-          const int pos[3] = {(k << lcw) + tt - rr, s * kRows + rr, kz};
-          raw_coef3<R, S>(raw[m], pos, si, A, P.defect != 0, coef + (size_t)buf * NC * ncells + (tt << 4) + rr,
-                          ncells);
+      for (int mc = 0; mc < MAXC; ++mc) {
+        const int e = tid + mc * (int)blockDim.x;
+        if (e < CB16) {
+          const int cl = e & (CB - 1), rr = e >> LCB;
+          R* dst = cbuf + (size_t)buf * NK * CB16 + cl * kRows + rr;
+#pragma unroll
+          for (int k = 0; k < NK; ++k) dst[k * CB16] = stg[mc][k];
         }
       }
     };
 
-    R xin[NF], yprev[NF];
+    R zreg[CB][NF], xin[NF], yprev[NF], xe[NF], xsave[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) { xin[f] = 0; yprev[f] = 0; }
-
+    for (int f = 0; f < NF; ++f) {
+      xin[f] = yprev[f] = xsave[f] = R(0);
+#pragma unroll
+      for (int u = 0; u < CB; ++u) zreg[u][f] = R(0);
+    }
+    // plane buffers other than the first hold neutral values until staged (rows that
+    // trail into planes before the first read them)
+    for (int e = CB16 * NK + tid; e < NBUF * NK * CB16; e += blockDim.x)
+      cbuf[e] = ((e / CB16) % NK == 0) ? R(1) : R(0);
     stage_load(0);
-    stage_store(0, 0);
-    for (int k = 0; k < P.nchunks; ++k) {
-      const int t0 = k << lcw;
-      const int buf = k & 1;
-      if (tid == 0 && (s > 0 || kz > 0)) {
-        const int need = min(nx, t0 + cw);
+    stage_store(0);
+    int pb = 0;  // p % NBUF
+    for (int p = 0; p < nz + L; ++p) {
+      if (tid == 0 && (s > 0 || b > 0)) {
+        const int need = min(p + 1, nz);
         const unsigned long long target = ((P.epoch + P.wait_bias) << 32) | (unsigned long long)need;
         long long spins = 0;
+        if (b > 0) {
+          const unsigned long long* flag = progr + (long long)s * nblk + (b - 1);
+          while (load_agent(flag) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > P.spin_limit) { atomicOr(P.err, 1); break; }
+          }
+        }
         if (s > 0) {
-          const unsigned long long* flag = progr + (long long)kz * P.nstrips + (s - 1);
+          const unsigned long long* flag = progr + (long long)(s - 1) * nblk + b;
           while (load_agent(flag) < target) {
             __builtin_amdgcn_s_sleep(2);
             if (++spins > P.spin_limit) { atomicOr(P.err, 1); break; }
           }
         }
-        if (kz > 0) {
-          const unsigned long long* flag = progr + (long long)(kz - 1) * P.nstrips + s;
-          while (load_agent(flag) < target) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > P.spin_limit) { atomicOr(P.err, 1); break; }
-          }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       __syncthreads();
-      {
-        // y traces of strip s - 1 (same plane) for the chunk's columns
-        const int ne = cw * NF * ds;
-        const R* src = yedge + (((long long)kz * P.nstrips + (s - 1)) * nx + t0) * NF * ds;
+      // y traces of strip s - 1 at plane p for the block's columns (row 0's inflow)
+      if (p < nz) {
+        const int ne = CB * ds * NF;
+        const R* src = yeb + (((long long)p * nstrips + (s - 1)) * nx + c0) * ds * NF;
         for (int e = tid; e < ne; e += blockDim.x) {
-          const int c = t0 + e / (NF * ds);
+          const int c = c0 + e / (ds * NF);
           eds[e] = (s > 0 && c < nx) ? load_agent(src + e) : R(0);
         }
-        // z traces of plane kz - 1 for every cell of the chunk, in batches of kZB values
-        // per thread whose loads are all issued before the first is stored to LDS (one
-        // load's latency per batch instead of per value)
-        const int nz_e = cw * kRows * NF * ds;
-        constexpr int kZB = 16;
-        for (int base = 0; base < nz_e; base += kZB * (int)blockDim.x) {
-          R v[kZB];
-#pragma unroll
-          for (int m = 0; m < kZB; ++m) {
-            const int e = base + tid + m * (int)blockDim.x;
-            const int fs = e % (NF * ds);
-            const int cellc = e / (NF * ds);
-            const int rr = cellc & 15, tt = cellc >> 4;
-            const int c = t0 + tt - rr;
-            const int jr2 = s * kRows + rr;
-            v[m] = R(0);
-            if (e < nz_e && kz > 0 && c >= 0 && c < nx && jr2 < ny) {
-              const int i2 = si[0] > 0 ? c : nx - 1 - c;
-              const int j2 = si[1] > 0 ? jr2 : ny - 1 - jr2;
-              v[m] = load_agent(zin_ring + ((long long)j2 * nx + i2) * NF * ds + fs);
-            }
-          }
-#pragma unroll
-          for (int m = 0; m < kZB; ++m) {
-            const int e = base + tid + m * (int)blockDim.x;
-            if (e < nz_e) zds[e] = v[m];
-          }
-        }
       }
-      if (k + 1 < P.nchunks) stage_load(k + 1);  // overlaps the step loop below
-      lds_barrier();  // staged traces and coefficients visible; the prefetch stays in flight
+      // x traces of block b - 1 for this row, at the plane where the row enters the block
+      {
+        const int qx = p - (r >> LCB);
+        const bool ok = b > 0 && row_ok && qx >= 0 && qx < nz;
+        const R* src = xeb + ((((long long)qx * nstrips + s) * nblk + (b - 1)) * kRows + r) * ds * NF + slot * NF;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) xe[f] = ok ? load_agent(src + f) : R(0);
+      }
+      if (p + 1 < nz) stage_load(p + 1);  // stays in flight through the steps
+      lds_barrier();  // staged y traces visible; the loads above stay in flight
 
-      const R* cbuf = coef + (size_t)buf * NC * ncells;
-      constexpr int U = kStepGroup3;
-      for (int tg = 0; tg < cw; tg += U) {
-        R src_g[U], sig_g[U], inv_g[U], edn_g[U][NF], zin_g[U][NF];
+      // the row index passes through an empty asm once per period, so that the per-step
+      // offsets derived from it are recomputed here instead of being held in registers
+      // across the whole item
+      int rp = r;
+      asm volatile("" : "+v"(rp));
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int tt = tg + u;
-          const R* cf = cbuf + (tt << 4) + r;
-          sig_g[u] = cf[0];
-          src_g[u] = cf[ncells] + d.ao[0] * cf[2 * ncells] + d.ao[1] * cf[3 * ncells] + d.ao[2] * cf[4 * ncells];
-          if constexpr (RLM) {
-            const R kx = (t0 + tt - r == 0) ? R(1) : R(0.5);
-            inv_g[u] = recip(sig_g[u] + d.aA[0] * (R(1) + kx) + d.aA[1] * (R(1) + ky) + d.aA[2] * (R(1) + kzf));
-          } else {
-            inv_g[u] = recip(sig_g[u] + d.aA[0] + d.aA[1] + d.aA[2]);
-          }
+      for (int u = 0; u < CB; ++u) {
+        const int dd = u - rp;
+        const int qo = dd >> LCB;  // 0, -1, .. -L: the plane relative to p
+        const int cl = dd & (CB - 1);
+        const int q = p + qo;
+        const int c = c0 + cl;
+        const bool act = row_ok && q >= 0 && q < nz && c < nx;
+        int qb = pb + qo;
+        if (qb < 0) qb += NBUF;
+        const R* cf = cbuf + (size_t)qb * NK * CB16 + cl * kRows + r;
+        R xi[NF], yd[NF], zi[NF];
 #pragma unroll
-          for (int f = 0; f < NF; ++f) {
-            edn_g[u][f] = eds[((tt * NF) + f) * ds + slot];
-            zin_g[u][f] = zds[(((tt << 4) + r) * NF + f) * ds + slot];
-          }
+        for (int f = 0; f < NF; ++f) {
+          xi[f] = (cl == 0) ? xe[f] : xin[f];
+          const R v = shr1(yprev[f]);
+          yd[f] = (r == 0) ? eds[(u * ds + slot) * NF + f] : v;
+          zi[f] = (q <= 0) ? R(0) : zreg[u][f];
         }
-        R yo_g[U][NF], zo_g[U][NF], psi_g[U];
+        R o[NOUT], xo[NF], yo[NF], zo[NF];
+        if constexpr (STDS) {
+          R src[8], cm[8];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int tt = tg + u;
-          const int c = t0 + tt - r;
-          const bool act = row_ok && c >= 0 && c < nx;
-          R ydn[NF];
+          for (int m = 0; m < 8; ++m) src[m] = cf[(1 + m) * CB16];
+          cell_std3<R>(d, si, src, cf[0], xi, yd, zi, xo, yo, zo, o, cm);
+          if (psir && act && d.idx >= 0) {
+            const int i = si[0] > 0 ? c : nx - 1 - c;
+            const int kk = si[2] > 0 ? q : nz - 1 - q;
+            const long long cell = (long long)kk * nxy + (long long)j * nx + i;
 #pragma unroll
-          for (int f = 0; f < NF; ++f) {
-            const R v = shr1(yprev[f]);
-            ydn[f] = (r == 0) ? edn_g[u][f] : v;
-            xin[f] = (c == 0) ? R(0) : xin[f];
+            for (int m = 0; m < 8; ++m) psir[((long long)d.idx * 8 + m) * nc + cell] = (double)cm[m];
           }
-          const R* zin = zin_g[u];
-          R o[NOUT], xo[NF], yo[NF], zo[NF];
+        } else {
+          const R sig = cf[0];
+          const R src = cf[CB16] + d.ao[0] * cf[2 * CB16] + d.ao[1] * cf[3 * CB16] + d.ao[2] * cf[4 * CB16];
           R psi;
           if constexpr (!RLM) {
-            psi = (src_g[u] + d.aA[0] * xin[0] + d.aA[1] * ydn[0] + d.aA[2] * zin[0]) * inv_g[u];
+            const R inv = recip(sig + d.aA[0] + d.aA[1] + d.aA[2]);
+            psi = (src + d.aA[0] * xi[0] + d.aA[1] * yd[0] + d.aA[2] * zi[0]) * inv;
             xo[0] = yo[0] = zo[0] = psi;
             o[0] = d.w * psi;
-            o[1] = d.w * d.oA[0] * (xin[0] - psi);
-            o[2] = d.w * d.oA[1] * (ydn[0] - psi);
-            o[3] = d.w * d.oA[2] * (zin[0] - psi);
+            o[1] = d.w * d.oA[0] * (xi[0] - psi);
+            o[2] = d.w * d.oA[1] * (yd[0] - psi);
+            o[3] = d.w * d.oA[2] * (zi[0] - psi);
           } else {
             // traces per axis: [outflow face value, two tangential slopes, cell value];
             // tangential slopes in axis order: x carries (c_y, c_z), y (c_x, c_z), z (c_x, c_y)
             const R kx = (c == 0) ? R(1) : R(0.5);
+            const R kz = (q == 0) ? R(1) : R(0.5);
             const R third = R(1) / R(3);
-            psi = (src_g[u] + d.aA[0] * (xin[0] + kx * xin[3]) + d.aA[1] * (ydn[0] + ky * ydn[3]) +
-                   d.aA[2] * (zin[0] + kzf * zin[3])) *
-                  inv_g[u];
-            const R cx = R(si[0]) * kx * (psi - xin[3]);
-            const R cy = R(si[1]) * ky * (psi - ydn[3]);
-            const R cz = R(si[2]) * kzf * (psi - zin[3]);
-            xo[0] = psi + kx * (psi - xin[3]);
+            const R inv = recip(sig + d.aA[0] * (R(1) + kx) + d.aA[1] * (R(1) + ky) + d.aA[2] * (R(1) + kz));
+            psi = (src + d.aA[0] * (xi[0] + kx * xi[3]) + d.aA[1] * (yd[0] + ky * yd[3]) +
+                   d.aA[2] * (zi[0] + kz * zi[3])) *
+                  inv;
+            const R cx = R(si[0]) * kx * (psi - xi[3]);
+            const R cy = R(si[1]) * ky * (psi - yd[3]);
+            const R cz = R(si[2]) * kz * (psi - zi[3]);
+            xo[0] = psi + kx * (psi - xi[3]);
             xo[1] = cy;
             xo[2] = cz;
             xo[3] = psi;
-            yo[0] = psi + ky * (psi - ydn[3]);
+            yo[0] = psi + ky * (psi - yd[3]);
             yo[1] = cx;
             yo[2] = cz;
             yo[3] = psi;
-            zo[0] = psi + kzf * (psi - zin[3]);
+            zo[0] = psi + kz * (psi - zi[3]);
             zo[1] = cx;
             zo[2] = cy;
             zo[3] = psi;
             // eps sigma_a V / 3: sigma_t V / 3 of L_11 R minus (sigma_s/eps) V / 3 of M_1 P_1 R
-            const R sV3 = cbuf[((tt << 4) + r) + 5 * ncells];
+            const R sV3 = cf[5 * CB16];
             o[0] = d.w * psi;
-            o[1] = d.w * (d.oA[0] * (xin[0] - psi) + (sV3 + d.aA[0]) * cx +
-                          third * (d.aA[1] * (cx - ydn[1]) + d.aA[2] * (cx - zin[1])));
-            o[2] = d.w * (d.oA[1] * (ydn[0] - psi) + (sV3 + d.aA[1]) * cy +
-                          third * (d.aA[0] * (cy - xin[1]) + d.aA[2] * (cy - zin[2])));
-            o[3] = d.w * (d.oA[2] * (zin[0] - psi) + (sV3 + d.aA[2]) * cz +
-                          third * (d.aA[0] * (cz - xin[2]) + d.aA[1] * (cz - ydn[2])));
-            o[4] = d.w * third * (d.oA[0] * (xin[1] - cy) + d.oA[1] * (ydn[1] - cx));
-            o[5] = d.w * third * (d.oA[0] * (xin[2] - cz) + d.oA[2] * (zin[1] - cx));
-            o[6] = d.w * third * (d.oA[1] * (ydn[2] - cz) + d.oA[2] * (zin[2] - cy));
+            o[1] = d.w * (d.oA[0] * (xi[0] - psi) + (sV3 + d.aA[0]) * cx +
+                          third * (d.aA[1] * (cx - yd[1]) + d.aA[2] * (cx - zi[1])));
+            o[2] = d.w * (d.oA[1] * (yd[0] - psi) + (sV3 + d.aA[1]) * cy +
+                          third * (d.aA[0] * (cy - xi[1]) + d.aA[2] * (cy - zi[2])));
+            o[3] = d.w * (d.oA[2] * (zi[0] - psi) + (sV3 + d.aA[2]) * cz +
+                          third * (d.aA[0] * (cz - xi[2]) + d.aA[1] * (cz - yd[2])));
+            o[4] = d.w * third * (d.oA[0] * (xi[1] - cy) + d.oA[1] * (yd[1] - cx));
+            o[5] = d.w * third * (d.oA[0] * (xi[2] - cz) + d.oA[2] * (zi[1] - cx));
+            o[6] = d.w * third * (d.oA[1] * (yd[2] - cz) + d.oA[2] * (zi[2] - cy));
             o[7] = d.w * cx;
             o[8] = d.w * cy;
             o[9] = d.w * cz;
           }
-          psi_g[u] = psi;
-#pragma unroll
-          for (int f = 0; f < NF; ++f) {
-            xin[f] = xo[f];
-            yprev[f] = yo[f];
-            yo_g[u][f] = yo[f];
-            zo_g[u][f] = zo[f];
-          }
-          // sums over the four direction slots of the wave, four rows at a time: lane
-          // group g receives row m0 + g (no branch, so the steps of a group stay one
-          // scheduling region)
-          R om[NOUTP];
-#pragma unroll
-          for (int m = 0; m < NOUTP; ++m) om[m] = (m < NOUT && act) ? o[m < NOUT ? m : 0] : R(0);
-#pragma unroll
-          for (int m0 = 0; m0 < NOUTP; m0 += 4) {
-            const R v = quad_sum4(om[m0], om[m0 + 1], om[m0 + 2], om[m0 + 3]);
-            red[tt * red_tt + (wv * NOUTP + m0 + (lane >> 4)) * kRows + r] = v;
+          if (psir && act && d.idx >= 0) {
+            const int i = si[0] > 0 ? c : nx - 1 - c;
+            const int kk = si[2] > 0 ? q : nz - 1 - q;
+            psir[(long long)d.idx * nc + (long long)kk * nxy + (long long)j * nx + i] = (double)psi;
           }
         }
-        // deferred stores of the group: y traces (top row), z traces (every cell), psi
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int c = t0 + tg + u - r;
-          if (row_ok && c >= 0 && c < nx) {
-            const int i = si[0] > 0 ? c : nx - 1 - c;
-            if (r == kRows - 1 && s + 1 < P.nstrips) {
-              R* e = yedge + ((((long long)kz * P.nstrips + s) * nx + c) * NF) * ds + slot;
+        for (int f = 0; f < NF; ++f) {
+          xin[f] = xo[f];
+          yprev[f] = yo[f];
+          zreg[u][f] = zo[f];
+          xsave[f] = (cl == CB - 1) ? xo[f] : xsave[f];
+        }
+        // top row: y traces for strip s + 1
+        if (r == kRows - 1 && act && s + 1 < nstrips) {
+          R* dst = yeb + (((long long)q * nstrips + s) * nx + c) * ds * NF + slot * NF;
 #pragma unroll
-              for (int f = 0; f < NF; ++f) store_agent(e + (long long)f * ds, yo_g[u][f]);
-            }
-            if (kz + 1 < nz) {
-              R* e = zout_ring + (((long long)j * nx + i) * NF) * ds + slot;
+          for (int f = 0; f < NF; ++f) store_agent(dst + f, yo[f]);
+        }
+        // sums over the four direction slots of the wave, four rows at a time: lane group
+        // g receives row m0 + g
+        R om[NOUTP];
 #pragma unroll
-              for (int f = 0; f < NF; ++f) store_agent(e + (long long)f * ds, zo_g[u][f]);
-            }
-            if (psir && d.idx >= 0) {
-              const long long cell = (long long)kk * nxy + (long long)j * nx + i;
-              psir[(long long)d.idx * nc + cell] = (double)psi_g[u];
-            }
-          }
+        for (int m = 0; m < NOUTP; ++m) om[m] = (m < NOUT && act) ? o[m < NOUT ? m : 0] : R(0);
+#pragma unroll
+        for (int m0 = 0; m0 < NOUTP; m0 += 4) {
+          const R v = quad_sum4(om[m0], om[m0 + 1], om[m0 + 2], om[m0 + 3]);
+          red[u * red_tt + (wv * NOUTP + m0 + (lane >> 4)) * kRows + r] = v;
+        }
+        // keep each step's loads next to its arithmetic (bounds the registers held)
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // x traces for block b + 1: the period's cell in the block's last column
+      {
+        const int qx = p - ((r + CB - 1) >> LCB);
+        if (b + 1 < nblk && row_ok && qx >= 0 && qx < nz) {
+          R* dst = xeb + ((((long long)qx * nstrips + s) * nblk + b) * kRows + r) * ds * NF + slot * NF;
+#pragma unroll
+          for (int f = 0; f < NF; ++f) store_agent(dst + f, xsave[f]);
         }
       }
-      // publish: columns below `done` are finished by every row of this strip (also
-      // their z traces, which plane kz + 1 reads, and their reads of plane kz - 1).
-      // Raised before the staging and reduction below, which no other item waits for:
-      // every wave waits for its own trace stores to complete before the barrier.
-      const bool publish = s + 1 < P.nstrips || kz + 1 < nz;
+      // publish: planes below `done` are finished by every row of the block (their trace
+      // stores included); waves wait for their own stores before the barrier
+      const int done = min(p + 1 - L, nz);
+      const bool publish = done > 0 && (s + 1 < nstrips || b + 1 < nblk);
       if (publish) __builtin_amdgcn_s_waitcnt(kWaitVmem);
       __syncthreads();
-      if (tid == 0 && publish) {
-        const int done = (k + 1 == P.nchunks) ? nx : min(nx, t0 + cw - (kRows - 1));
-        if (done > 0) {
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          store_agent(progr + (long long)kz * P.nstrips + s, (P.epoch << 32) | (unsigned long long)done);
-        }
-      }
-      if (k + 1 < P.nchunks) stage_store(k + 1, buf ^ 1);
-      const int nred = (NOUT * kRows) << lcw;
-      for (int e = tid; e < nred; e += blockDim.x) {
-        const int tt = e & (cw - 1);
-        const int m = (e >> lcw) % NOUT;
-        const int rr = (e >> lcw) / NOUT;
-        const int c = t0 + tt - rr;
+      if (tid == 0 && publish) store_agent(progr + (long long)s * nblk + b, (P.epoch << 32) | (unsigned long long)done);
+      const int pb1 = (pb + 1 == NBUF) ? 0 : pb + 1;
+      if (p + 1 < nz) stage_store(pb1);
+      // the period's outputs: one cell per (row, column of the block)
+      for (int e = tid; e < NOUT * CB16; e += blockDim.x) {
+        const int cl = e & (CB - 1);
+        const int rr = (e >> LCB) & (kRows - 1);
+        const int m = e >> (LCB + 4);
+        const int u = (rr + cl) & (CB - 1);
+        const int q = p + ((u - rr) >> LCB);
+        const int c = c0 + cl;
         const int jr2 = s * kRows + rr;
-        if (jr2 < ny && c >= 0 && c < nx) {
+        if (q >= 0 && q < nz && c < nx && jr2 < ny) {
           R acc = 0;
 #pragma unroll
           for (int w2 = 0; w2 < MAXW; ++w2)
-            if (w2 < W) acc += red[tt * red_tt + (w2 * NOUTP + m) * kRows + rr];
+            if (w2 < W) acc += red[u * red_tt + (w2 * NOUTP + m) * kRows + rr];
           const int i = si[0] > 0 ? c : nx - 1 - c;
           const int jj = si[1] > 0 ? jr2 : ny - 1 - jr2;
-          partr[((long long)o * NOUT + m) * nc + (long long)kk * nxy + (long long)jj * nx + i] = acc;
+          const int kk = si[2] > 0 ? q : nz - 1 - q;
+          partr[(long long)m * nc + (long long)kk * nxy + (long long)jj * nx + i] = acc;
         }
       }
+      pb = pb1;
     }
     __syncthreads();
   }
 }
 
 template <typename R, int S>
-size_t lds_bytes3(int cw, int W, int dslots) {
+size_t lds_bytes3(int cb, int W, int dslots) {
   constexpr int NOUT = Traits3<S>::NOUT;
-  constexpr int NF = Traits3<S>::NF;
   constexpr int NOUTP = (NOUT + 3) & ~3;
-  return ((size_t)cw * (W * NOUTP * kRows + 1) + (size_t)2 * cw * kRows * Traits3<S>::NC + (size_t)cw * NF * dslots +
-          (size_t)cw * kRows * NF * dslots) *
+  const int L = (kRows - 1 + cb - 1) / cb;
+  return ((size_t)cb * (W * NOUTP * kRows + 1) + (size_t)(L + 2) * Traits3<S>::NK * cb * kRows +
+          (size_t)cb * dslots * Traits3<S>::NF) *
          sizeof(R);
 }
 
+// Work items the GPU holds at once for one instantiation (occupancy query, cached).
+template <typename R, int S, int MAXW, int CB>
+int resident_blocks(int threads, size_t lds) {
+  static int per_cu = -1;
+  static size_t per_cu_lds = 0;
+  if (per_cu < 0 || per_cu_lds != lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep3d_kernel<R, S, MAXW, CB>, threads, lds) !=
+            hipSuccess ||
+        nb < 1)
+      nb = 1;
+    per_cu = nb;
+    per_cu_lds = lds;
+  }
+  return per_cu;
+}
+
+template <typename R, int S, int MAXW, int CB>
+int launch_kernel3(lmdg_handle* h, const Sweep3Params<R>& P, int W, hipStream_t st) {
+  const size_t lds = lds_bytes3<R, S>(CB, W, h->dslots);
+  if (lds > 160 * 1024)
+    return set_error(h, LMDG_UNSUPPORTED, "direction set too large for the 3D sweep's LDS staging");
+  const int per_cu = resident_blocks<R, S, MAXW, CB>(64 * W, lds);
+  const int grid = (int)std::min<long long>(P.n_items, (long long)per_cu * h->n_cu);
+  hipLaunchKernelGGL((sweep3d_kernel<R, S, MAXW, CB>), dim3(grid), dim3(64 * W), lds, st, P);
+  h->ticket_base += (unsigned)(P.n_items + grid);
+  return LMDG_OK;
+}
+
+// Column block width: 8 for FP32 sweeps, 4 for FP64 (the register ring holds CB x NF
+// values; wider blocks raise the register count past three waves per SIMD).
+constexpr int kMinBlockCols3 = 4;
+template <typename R>
+constexpr int block_cols3() { return sizeof(R) == 4 ? 8 : 4; }
+static_assert(block_cols3<float>() >= kMinBlockCols3 && block_cols3<double>() >= kMinBlockCols3, "workspace sizing");
+
 template <typename R, int S>
 int launch3_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipStream_t st, bool defect) {
+  constexpr int CB = block_cols3<R>();
+  constexpr int NF = Traits3<S>::NF;
+  constexpr int NA = Traits3<S>::NA;
+  const int W = h->waves;
   Sweep3Params<R> P;
   P.nx = (int)h->n[0];
   P.ny = (int)h->n[1];
   P.nz = (int)h->n[2];
   P.nstrips = h->nstrips;
+  P.nblk = (P.nx + CB - 1) / CB;
   P.dslots = h->dslots;
-  const int W = h->waves;
-  // LDS per workgroup (gfx950 gives a workgroup up to 160 KB): FP64 sweeps take the
-  // widest chunks that fit one workgroup per compute unit; FP32 sweeps are held to 64 KB,
-  // so that two or three workgroups share a compute unit (measured faster, 128^3 S8)
-  constexpr size_t kLdsBudget = sizeof(R) == 8 ? 144 * 1024 : 64 * 1024;
-  int cw = 16;
-  const int maxc = W > 4 ? 1 : kMAXC3;
-  while (cw > kStepGroup3 && (kRows * cw > maxc * 64 * W || lds_bytes3<R, S>(cw, W, h->dslots) > kLdsBudget))
-    cw >>= 1;
-  if (lds_bytes3<R, S>(cw, W, h->dslots) > kLdsBudget)
-    return set_error(h, LMDG_UNSUPPORTED, "direction set too large for the 3D sweep's LDS staging");
-  P.cw = cw;
-  P.lcw = 0;
-  while ((1 << P.lcw) < cw) ++P.lcw;
-  P.nchunks = (P.nx + kRows - 1 + cw - 1) / cw;
   P.n_rhs = h->n_rhs;
-  P.n_items = 8 * h->nstrips * P.nz * h->n_rhs;
+  P.n_items = 8 * P.nstrips * P.nblk * h->n_rhs;
   for (int a = 0; a < 3; ++a) P.h[a] = h->h[a];
   P.ncell = h->ncell;
   P.dirs = h->d_dirs;
-  P.x = x;
-  P.sigtA = h->d_sigtA;
-  P.scatA = h->d_scatA;
-  P.qA = use_q ? (h->src0 ? h->src0 : h->d_qA) : nullptr;
-  P.absA = h->d_absA;
-  P.defect = defect ? 1 : 0;
+  // coefficients of every source in the sweep precision
+  R* coef = reinterpret_cast<R*>(h->ws.zbuf);
+  {
+    Coef3Params C;
+    for (int a = 0; a < 3; ++a) C.n[a] = (int)h->n[a];
+    C.n_rhs = h->n_rhs;
+    C.defect = defect ? 1 : 0;
+    C.ncell = h->ncell;
+    C.A[0] = h->h[1] * h->h[2];
+    C.A[1] = h->h[0] * h->h[2];
+    C.A[2] = h->h[0] * h->h[1];
+    C.x = x;
+    C.qA = use_q ? (h->src0 ? h->src0 : h->d_qA) : nullptr;
+    C.sigtA = h->d_sigtA;
+    C.scatA = h->d_scatA;
+    C.absA = h->d_absA;
+    const long long n = h->ncell * h->n_rhs;
+    const int g = (int)std::min<long long>(std::max<long long>((n + 255) / 256, 1), 8192);
+    hipLaunchKernelGGL((coef3_kernel<R, S>), dim3(g), dim3(256), 0, st, C, coef);
+    (void)NA;
+  }
+  P.coef = coef;
   P.part = reinterpret_cast<R*>(h->ws.part);
   h->last_nsl = 8;
-  P.yedge = reinterpret_cast<R*>(h->ws.edge);
-  P.zbuf = reinterpret_cast<R*>(h->ws.zbuf);
-  constexpr int NF = Traits3<S>::NF;
-  P.yedge_ostride = (long long)P.nz * h->nstrips * P.nx * NF * h->dslots;
-  P.zbuf_ostride = (long long)2 * P.nx * P.ny * NF * h->dslots;
+  P.xedge = reinterpret_cast<R*>(h->ws.edge);
+  P.xedge_ostride = (long long)P.nz * P.nstrips * P.nblk * kRows * h->dslots * NF;
+  P.yedge = P.xedge + 8LL * h->n_rhs * P.xedge_ostride;
+  P.yedge_ostride = (long long)P.nz * P.nstrips * P.nx * h->dslots * NF;
   P.psi = psi;
-  P.psi_rstride = (long long)h->ndir * h->ncell;
+  P.psi_rstride = (long long)h->ndir * (S == LMDG_SCHEME_STD ? 8 : 1) * h->ncell;
   P.prog = h->ws.prog;
   P.ticket = h->ws.ticket;
   P.err = h->ws.err;
@@ -523,8 +681,6 @@ int launch3_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipS
   P.ticket_base = h->ticket_base;
   P.spin_limit = h->spin_limit;
   P.wait_bias = h->wait_bias;
-  const int grid = std::min(P.n_items, 4 * h->n_cu);
-  const size_t lds = lds_bytes3<R, S>(cw, W, h->dslots);
   hipEvent_t ev_end = nullptr;
   if (h->profiling) {
     if (h->ev_used + 2 > h->ev_pool.size()) {
@@ -538,21 +694,34 @@ int launch3_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipS
     ev_end = h->ev_pool[h->ev_used + 1];
     h->ev_used += 2;
   }
-  if (W <= 4)
-    hipLaunchKernelGGL((sweep3d_kernel<R, S, 4>), dim3(grid), dim3(64 * W), lds, st, P);
-  else
-    hipLaunchKernelGGL((sweep3d_kernel<R, S, kMaxWaves>), dim3(grid), dim3(64 * W), lds, st, P);
+  const int rc = W <= 4 ? launch_kernel3<R, S, 4, CB>(h, P, W, st) : launch_kernel3<R, S, kMaxWaves, CB>(h, P, W, st);
+  if (rc != LMDG_OK) return rc;
   if (ev_end) hipEventRecord(ev_end, st);
   h->epoch += 1;
-  h->ticket_base += (unsigned)(P.n_items + grid);
   return check_hip(h, hipGetLastError(), "sweep launch");
 }
 
 }  // namespace
 
+// Workspace of the 3D sweeps per right-hand side (the handle sizes it for the narrowest
+// column blocks, FP64 values and four trace values): edge traces (x then y), per-cell
+// coefficients, progress words.
+size_t sweep3d_edge_bytes(const lmdg_handle* h) {
+  const long long nblk = (h->n[0] + kMinBlockCols3 - 1) / kMinBlockCols3;
+  return (size_t)8 * h->n[2] * h->nstrips * (nblk * kRows + h->n[0]) * h->dslots * 4 * sizeof(double);
+}
+size_t sweep3d_coef_bytes(const lmdg_handle* h) { return (size_t)9 * h->ncell * sizeof(double); }
+size_t sweep3d_prog_words(const lmdg_handle* h) {
+  return (size_t)8 * h->nstrips * ((h->n[0] + kMinBlockCols3 - 1) / kMinBlockCols3);
+}
+
 int launch_sweep3d(lmdg_handle* h, int scheme, int prec, const double* x, bool use_q, double* psi, hipStream_t st,
                    bool defect) {
-  if (scheme == LMDG_SCHEME_STD) return set_error(h, LMDG_UNSUPPORTED, "the 3D path covers LMDG and RLMDG");
+  if (scheme == LMDG_SCHEME_STD) {
+    // the standard scheme takes the plain form M Phi (+ Q) of eq-sndg-phi
+    return prec == LMDG_PREC_FP64 ? launch3_typed<double, LMDG_SCHEME_STD>(h, x, use_q, psi, st, false)
+                                  : launch3_typed<float, LMDG_SCHEME_STD>(h, x, use_q, psi, st, false);
+  }
   if (prec == LMDG_PREC_FP64)
     return scheme == LMDG_SCHEME_LMDG ? launch3_typed<double, LMDG_SCHEME_LMDG>(h, x, use_q, psi, st, defect)
                                       : launch3_typed<double, LMDG_SCHEME_RLMDG>(h, x, use_q, psi, st, defect);

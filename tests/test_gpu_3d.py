@@ -161,3 +161,105 @@ def test_multi_source_3d_equals_single():
         assert torch.equal(b[k * 8 * nc:(k + 1) * 8 * nc], singles[k][0])
         assert torch.equal(y[k * 8 * nc:(k + 1) * 8 * nc], singles[k][1])
     s.close()
+
+
+# ------------------------------------------------------------------ standard Q1 in 3D
+def std_abi(v, nc):
+    """cell-major (nc, 8) oracle moments -> moment-major ABI layout."""
+    return np.asarray(v).reshape(nc, 8).T.ravel()
+
+
+def std_oracle(v, nc):
+    return np.asarray(v).reshape(8, nc).T.ravel()
+
+
+# 3D standard scheme (8 x 8 local solves, plain form M Phi of eq-sndg-phi).  FP64 bar
+# 1e-12; FP32 sweeps are compared with the magnitude of the swept term P L^{-1} M x,
+# which the plain form subtracts from x (2e-5 of it, the FP32 sweep bar).
+@pytest.mark.parametrize("shape,order", SHAPES)
+def test_sweep3d_std_parity(shape, order):
+    print(f"case 3d std sweep {shape} S{order}", flush=True)
+    case = Case3(shape, order, eps=0.3)
+    s = case.solver()
+    nc = case.ncell
+    nd = case.prob.n_dir
+    st = S.StdReduced(case.prob)
+    x = np.random.default_rng(3).normal(size=8 * nc)
+    mphi = case.prob.Mu @ std_oracle(x, nc)
+    for use_q in (False, True):
+        rhs = np.broadcast_to(mphi, (nd, mphi.size)) + (case.prob.Qu if use_q else 0.0)
+        lpsi = st.Linv(rhs)                                          # (nd, nc*8)
+        ref = std_abi(case.prob.w @ lpsi, nc)
+        ref_psi = np.concatenate([std_abi(lpsi[l], nc) for l in range(nd)])
+        out = torch.zeros(8 * nc, dtype=torch.float64, device=DEV)
+        psi = torch.zeros(nd * 8 * nc, dtype=torch.float64, device=DEV)
+        lmdg.lmdg_sweep(s.h, "std", "fp64", T(x), use_q, out, psi)
+        assert rel_err(N(out), ref) < 1e-12
+        assert rel_err(N(psi), ref_psi) < 1e-12
+        lmdg.lmdg_sweep(s.h, "std", "fp32", T(x), use_q, out, None)
+        assert rel_err(N(out), ref) < 2e-5
+    s.close()
+
+
+@pytest.mark.parametrize("shape,order", SHAPES)
+def test_apply_and_rhs_std_3d(shape, order):
+    print(f"case 3d std apply {shape} S{order}", flush=True)
+    case = Case3(shape, order, eps=0.1)
+    s = case.solver()
+    nc = case.ncell
+    st = S.StdReduced(case.prob)
+    x = np.random.default_rng(2).normal(size=8 * nc)
+    ref_y = std_abi(st.apply(std_oracle(x, nc)), nc)
+    ref_b = std_abi(st.rhs(), nc)
+    swept = np.abs(x - ref_y).max()   # max |P L^{-1} M x|
+    y = torch.zeros(8 * nc, dtype=torch.float64, device=DEV)
+    b = torch.zeros_like(y)
+    lmdg.lmdg_apply(s.h, "std", "fp64", T(x), y)
+    lmdg.lmdg_rhs(s.h, "std", "fp64", b)
+    assert rel_err(N(y), ref_y) < 1e-12
+    assert rel_err(N(b), ref_b) < 1e-12
+    lmdg.lmdg_apply(s.h, "std", "fp32", T(x), y)
+    assert np.abs(N(y) - ref_y).max() < 2e-5 * swept
+    s.close()
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_solve_std_3d_against_direct(mode):
+    print(f"case 3d std solve {mode}", flush=True)
+    case = Case3((6, 7, 5), 4, eps=0.1)
+    s = case.solver()
+    nc = case.ncell
+    x = torch.zeros(8 * nc, dtype=torch.float64, device=DEV)
+    phi = torch.zeros_like(x)
+    info = lmdg.lmdg_solve(s.h, "std", mode, 1e-12, 40, 4000, x, phi)
+    assert info["converged"] == 1
+    psi = S.solve_std_direct(case.prob)                    # (n_dir, nc, 8)
+    ref = np.einsum("l,lcm->cm", case.w, psi)              # scalar flux moments, cell-major
+    assert rel_err(N(phi).reshape(8, nc).T, ref) < 1e-9
+    s.close()
+
+
+def test_std_3d_several_sources_equal_single():
+    case = Case3((5, 18, 4), 4, eps=0.2)
+    nc = case.ncell
+    q = np.random.default_rng(8).uniform(0, 1, size=(2, nc))
+    s = case.solver()
+    x = T(np.random.default_rng(9).normal(size=(2, 8 * nc)))
+    singles = []
+    for k in range(2):
+        lmdg.lmdg_set_materials(s.h, T(case.sigma_s), T(case.sigma_a), T(case.eps), T(q[k]))
+        b = torch.zeros(8 * nc, dtype=torch.float64, device=DEV)
+        y = torch.zeros_like(b)
+        lmdg.lmdg_rhs(s.h, "std", "fp64", b)
+        lmdg.lmdg_apply(s.h, "std", "fp32", x[k].contiguous(), y)
+        singles.append((b, y))
+    lmdg.lmdg_set_sources(s.h, T(q))
+    b = torch.zeros(2 * 8 * nc, dtype=torch.float64, device=DEV)
+    y = torch.zeros_like(b)
+    lmdg.lmdg_rhs(s.h, "std", "fp64", b)
+    lmdg.lmdg_apply(s.h, "std", "fp32", x.reshape(-1), y)
+    torch.cuda.synchronize()
+    for k in range(2):
+        assert torch.equal(b[k * 8 * nc:(k + 1) * 8 * nc], singles[k][0])
+        assert torch.equal(y[k * 8 * nc:(k + 1) * 8 * nc], singles[k][1])
+    s.close()

@@ -17,6 +17,8 @@ schemes     standard, low-memory (LMDG) and reconstructed (RLMDG) systems, direc
             solves, the reduced Krylov route of Secs. 2.1.1, 3.2, 3.3.2, scalar flux
 diffusion   the eps -> 0 limit schemes of Sec. 3.1 (Q^1 CG and the Pi_0 form)
 adjoint     adjoint solves and gradients of a detector functional
+precond     two-level preconditioner of the reduced systems (cell blocks + the Pi_0
+            diffusion limit of Sec. 3.1)
 
 Every function states the passage of the paper it follows.  Readings of passages
 that are silent, ambiguous or misprinted are listed in the module docstrings.

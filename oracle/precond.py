@@ -32,9 +32,12 @@ Parts (each one a plain definition):
   (sigma_t = sigma_s/eps + eps sigma_a, the total cross section of the scaled equation,
   which tends to sigma_s/eps as eps -> 0) and absorption eps sigma_a, plus a vacuum
   (Marshak) term 1/2 int_{dD} u v on the boundary of D.  Reading (not in the paper): the
-  absorption and boundary matrices are lumped (row sums on the diagonal).  On square
-  cells the cell-averaged gradient energy is D |K| ((u_NE - u_SW)^2 + (u_SE - u_NW)^2) /
-  (2 h^2), so B couples only nodes of equal parity of i + j: two independent systems.
+  absorption and boundary matrices are lumped (row sums on the diagonal).  With
+  a = u_NE - u_SW and b = u_SE - u_NW the cell-averaged gradient energy of a cell is
+  D |K| [(a^2 + b^2)(1/(4 h_x^2) + 1/(4 h_y^2)) + 2 a b (1/(4 h_x^2) - 1/(4 h_y^2))];
+  the second term (zero on square cells) couples nodes of unlike parity of i + j and is
+  left out of B (reading, not in the paper), so B is two independent systems, one per
+  parity class.
 * Z: nodal u -> its cell Legendre moments (exact L^2 projection), mapped to reduced
   unknowns [m_0 ; -m_slopes]; for RLMDG the angular average of the reconstructed slopes of
   the isotropic cell averages, P_1 R (1 (x) m_0), is added to the slope part (the reduced
@@ -86,7 +89,8 @@ def cell_blocks(red: LowMemoryReduced):
 
 def diffusion_matrix(mesh: Mesh, d_coef, absorb, lumped=True):
     """B on all (n_x+1)(n_y+1) nodes: int D Pi_0 grad u . Pi_0 grad v (eq-difflimPF with the
-    per-cell coefficient D), int absorb u v and 1/2 int_{dD} u v, the last two lumped.
+    per-cell coefficient D) without its couplings between nodes of unlike i + j parity,
+    int absorb u v and 1/2 int_{dD} u v, the last two lumped.
     Returns (B, node index of the 4 corners of every cell)."""
     d = mesh.dim
     pts, wts = tensor_rule(d, 3)
@@ -101,10 +105,13 @@ def diffusion_matrix(mesh: Mesh, d_coef, absorb, lumped=True):
     absorb = np.broadcast_to(np.asarray(absorb, float), (mesh.n_cells,))
     rows = np.repeat(idx, 4, axis=1).ravel()
     cols = np.tile(idx, (1, 4)).ravel()
-    S = sp.csr_matrix(((d_coef[:, None, None] * stiff[None]).ravel(), (rows, cols)), shape=(nn, nn))
+    S = sp.csr_matrix(((d_coef[:, None, None] * stiff[None]).ravel(), (rows, cols)), shape=(nn, nn)).tocoo()
+    nnx = mesh.n[0] + 1
+    parity = (np.arange(nn) % nnx + np.arange(nn) // nnx) % 2
+    keep = parity[S.row] == parity[S.col]
+    S = sp.csr_matrix((S.data[keep], (S.row[keep], S.col[keep])), shape=(nn, nn))
     Mm = sp.csr_matrix(((absorb[:, None, None] * mass[None]).ravel(), (rows, cols)), shape=(nn, nn))
     # boundary term: 1/2 int over boundary edges of u v (two-point Gauss on each edge)
-    nnx = mesh.n[0] + 1
     ge, gw = np.polynomial.legendre.leggauss(2)
     phi = np.stack([(1 - ge) / 2, (1 + ge) / 2], axis=1)             # end-point hat functions
     edge = np.einsum("q,qa,qb->ab", gw / 2, phi, phi)                  # on a unit-length edge

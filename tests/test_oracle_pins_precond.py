@@ -86,6 +86,29 @@ def test_diffusion_matrix_stiffness_is_the_pi0_form():
     assert np.abs(B.toarray()[cross]).max() < 1e-15
 
 
+def test_diffusion_matrix_drops_only_the_cross_parity_term():
+    """On rectangular cells B's couplings are those of eq-difflimPF between nodes of equal
+    parity of i + j; what is dropped is the 2 a b term of the cell energy (it vanishes for
+    a field constant on one parity class)."""
+    n = (5, 4)
+    mesh = Mesh(n)                                      # h_x = 1/5, h_y = 1/4
+    sig = 0.8
+    B, _ = PC.diffusion_matrix(mesh, 1.0 / (3.0 * sig), 0.0)
+    ref = DIF.assembled_matrix(mesh, sig, 0.0, projected=True).toarray()
+    nnx, nn = n[0] + 1, B.shape[0]
+    par = (np.arange(nn) % nnx + np.arange(nn) // nnx) % 2
+    same = par[:, None] == par[None, :]
+    Bd = B.toarray() - np.diag(B.diagonal())
+    refd = ref - np.diag(ref.diagonal())
+    assert np.abs(Bd[same] - refd[same]).max() < 1e-14
+    assert np.abs(Bd[~same]).max() == 0.0 and np.abs(refd[~same]).max() > 0.01
+    assert np.abs(B.diagonal() - ref.diagonal()).max() > 0       # boundary term present
+    u = np.where(par == 0, np.random.default_rng(4).normal(size=nn), 0.0)   # b = 0 or a = 0 in every cell
+    lump = B.diagonal() - ref.diagonal()
+    e = u @ ref @ u
+    assert e > 1.0 and abs(u @ (B.toarray() - np.diag(lump)) @ u - e) < 1e-13 * e
+
+
 def test_diffusion_matrix_lumping_invariants():
     """1^T B 1 = int absorb + (1/2) |dD| (lumping keeps row sums; Pi_0 grad of a constant is 0),
     and B is symmetric positive definite."""

@@ -84,6 +84,11 @@ extern "C" {
 #define LMDG_MODE_FP64 0   /* FP64 sweeps inside FP64 GMRES */
 #define LMDG_MODE_MIXED 1  /* FP32 sweeps inside FP64 GMRES, FP64 iterative refinement */
 
+/* preconditioners of the reduced system (lmdg_set_preconditioner) */
+#define LMDG_PRECOND_NONE 0
+#define LMDG_PRECOND_CELL 1       /* cell blocks of K only */
+#define LMDG_PRECOND_TWO_LEVEL 2  /* cell blocks + the diffusion-limit correction */
+
 typedef struct lmdg_handle lmdg_t;
 
 typedef struct lmdg_info {
@@ -309,6 +314,47 @@ int lmdg_set_reconstruction(lmdg_t* h, int stencil, int suppress);
  * Errors: INVALID_ARG (k < 0 or k > 249).
  */
 int lmdg_set_augment(lmdg_t* h, int k);
+
+/*
+ * Preconditioner of the handle's GMRES solves of the reduced LMDG and RLMDG systems
+ * (lmdg_solve, the LMDG adjoint solve and the inner solves of mode MIXED), applied on
+ * the right: GMRES works on K M^{-1} u = b and the iterate is X = M^{-1} u, so the
+ * solution and the stopping test on ||b - K X|| are those of the unpreconditioned
+ * solve.  The paper leaves preconditioning of the dimension-reduced system to future
+ * work (Sec. 5, item (ii)); this one is built on its eps -> 0 limit of the low-memory
+ * scheme (Sec. 3.1, eq-difflimPF):
+ *     M^{-1} r = K_loc^{-1} r + Z B^{-1} W r.
+ * K_loc is, per cell, the 4 x 4 diagonal block of K (rows and columns X_0, X_1 of the
+ * cell).  W turns the residual into the source it stands for in the full scheme (cell
+ * moments (sigma_s/eps) r_0 and -r_m / (|K| n_m), n = 1/3, 1/3, 1/9) loaded onto nodal
+ * Q^1 functions.  B is the eq-difflimPF form with coefficient 1/(3 sigma_t) and
+ * absorption eps sigma_a plus 1/2 of the boundary mass (vacuum), absorption and boundary
+ * terms lumped, keeping the couplings of nodes of equal parity of i + j (all of them on
+ * square cells).  Z maps nodal values to [cell average ; minus the slope moments], for
+ * RLMDG plus the angular average of the reconstructed slopes of the cell averages.  B^{-1}
+ * is applied by `cycles` multigrid V-cycles (one per parity class; Galerkin coarse
+ * operators, Gauss-Seidel smoothing, dense coarsest solve), a fixed linear map.
+ *   kind    LMDG_PRECOND_NONE (default), LMDG_PRECOND_CELL (K_loc^{-1} only) or
+ *           LMDG_PRECOND_TWO_LEVEL.
+ *   cycles  1 .. 50 V-cycles per application (kind TWO_LEVEL; one is usually enough).
+ * The setup (cell blocks for the scheme of the solve, multigrid hierarchy) runs at the
+ * first use after lmdg_set_materials; its memory (16 doubles per cell, about 5 per node
+ * of the multigrid) is counted by lmdg_workspace_bytes, and a preconditioned solve holds
+ * two further vectors of the solve's length.  Solves of STD, of an RLMDG reconstruction
+ * variant and of the RLMDG adjoint system run without it.
+ * Errors: INVALID_ARG (kind or cycles out of range), UNSUPPORTED (a 3D or slab handle
+ * with kind != NONE).
+ */
+int lmdg_set_preconditioner(lmdg_t* h, int kind, int cycles);
+
+/*
+ * z = M^{-1} r for every right-hand side of the handle (device moment vectors of the
+ * reduced system; see lmdg_set_preconditioner) with the handle's kind and cycles; kind
+ * NONE copies r.  Enqueues on `stream`; builds the preconditioner first if needed.
+ * Errors: INVALID_ARG (NULL vectors, materials not set), UNSUPPORTED (a scheme or handle
+ * the preconditioner does not cover), HIP_ERROR.
+ */
+int lmdg_precond_apply(lmdg_t* h, int scheme, const double* r, double* z, void* stream);
 
 /*
  * Detector response and its gradients (2D, all three schemes).

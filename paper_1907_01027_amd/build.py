@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblmdg.so")
-SOURCES = ["api.cpp", "sweep2d.hip", "sweep3d.hip", "ops.hip", "ops3d.hip", "noalloc.hip"]
+SOURCES = ["api.cpp", "sweep2d.hip", "sweep3d.hip", "ops.hip", "ops3d.hip", "noalloc.hip", "precond.hip"]
 
 
 def hipcc() -> str:

@@ -439,6 +439,7 @@ void lmdg_destroy(lmdg_t* h) {
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (h->h_small) hipHostFree(h->h_small);
+  lmdg::pc_free(h);
   for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
   delete h;
 }
@@ -554,6 +555,7 @@ int lmdg_set_materials(lmdg_t* h, const double* sigma_s, const double* sigma_a, 
   if (rc == LMDG_OK) rc = check_hip(h, hipStreamSynchronize(st), "write materials");
   if (rc == LMDG_OK) {
     h->have_mat = true;
+    h->mat_version += 1;
     h->n_rhs = 1;
     h->h_eps = ep;
     clear_source_data(h, false);
@@ -784,9 +786,13 @@ int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, doubl
   const int ka_max = std::max(0, std::min(h->augment, kMaxRestart - m));
   const int mt = m + ka_max;                          // steps per cycle at most
   const SmallLayout L = small_layout(nr);
-  // V (mt + 1), r; with augmentation also Z, K Z (ka_max each), the correction and its image
+  // right preconditioning (lmdg_set_preconditioner) where it covers the system
+  const bool pc = h->pc_kind != LMDG_PRECOND_NONE && lmdg::pc_supported(h, scheme, nullptr);
+  // V (mt + 1), r; with augmentation also Z, K Z (ka_max each), the correction and its image;
+  // with the preconditioner two more (M^{-1} of a basis vector, of the cycle's combination)
+  const size_t base_vecs = (size_t)(mt + 2 + (ka_max > 0 ? 2 * ka_max + 2 : 0));
   const double* prev_krylov = h->d_krylov;
-  int rc = ensure_krylov(h, (size_t)(mt + 2 + (ka_max > 0 ? 2 * ka_max + 2 : 0)) * NT);
+  int rc = ensure_krylov(h, (base_vecs + (pc ? 2 : 0)) * NT);
   if (h->d_krylov != prev_krylov) stats.n_aug = stats.aug_next = 0;  // store lost with the old buffer
   if (rc == LMDG_OK) rc = ensure_small(h, L.total);
   if (rc != LMDG_OK) return rc;
@@ -796,6 +802,8 @@ int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, doubl
   double* AZ = Z + (size_t)ka_max * NT;    // their images
   double* dz = ka_max > 0 ? AZ + (size_t)ka_max * NT : x;  // this cycle's correction (x itself
   double* adz = dz + NT;                                     // without augmentation), its image
+  double* pt = h->d_krylov + base_vecs * NT;                 // preconditioner input / output
+  double* pz = pt + NT;
   double* dcoef = h->d_small + L.coef;
   double* dscal = h->d_small + L.scal;
   double* part = h->d_small + L.part;
@@ -876,7 +884,11 @@ int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, doubl
       if (krylov && stats.iterations >= max_iter) break;
       double* w = V + (size_t)(j + 1) * NT;
       if (krylov) {
-        rc = timed_apply(prec, V + (size_t)j * NT, w);
+        if (pc) {  // w = K M^{-1} v_j
+          rc = lmdg::pc_apply(h, scheme, V + (size_t)j * NT, pz, st);
+          if (rc != LMDG_OK) break;
+        }
+        rc = timed_apply(prec, pc ? pz : V + (size_t)j * NT, w);
         if (rc != LMDG_OK) break;
         stats.iterations += 1;
       } else {
@@ -964,8 +976,18 @@ int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, doubl
       for (int i = 0; i < nkry; ++i) hc[(size_t)i * nr + k] = ys[k][i];
     rc = check_hip(h, hipMemcpyAsync(dcoef, hc, (size_t)nkry * nr * sizeof(double), hipMemcpyHostToDevice, st), "y");
     if (rc != LMDG_OK) break;
-    if (ka_max > 0) lmdg::vec_fill(dz, 0.0, NT, st);
-    lmdg::vec_axpy_multi(dz, V, NT, nkry, dcoef, 1.0, N, st, nr);
+    if (pc) {
+      // Krylov part of the correction: M^{-1} (sum_j y_j V_j)
+      lmdg::vec_fill(pt, 0.0, NT, st);
+      lmdg::vec_axpy_multi(pt, V, NT, nkry, dcoef, 1.0, N, st, nr);
+      rc = lmdg::pc_apply(h, scheme, pt, pz, st);
+      if (rc != LMDG_OK) break;
+      if (ka_max > 0) lmdg::vec_copy(dz, pz, NT, st);
+      else lmdg::vec_axpby(x, 1.0, pz, 1.0, NT, st);
+    } else {
+      if (ka_max > 0) lmdg::vec_fill(dz, 0.0, NT, st);
+      lmdg::vec_axpy_multi(dz, V, NT, nkry, dcoef, 1.0, N, st, nr);
+    }
     if (kmax > m) {
       // stored corrections: coefficients by ring slot (step m + l used slot aug_next - 1 - l)
       double* hz = hc + (size_t)(mt + 1) * nr;
@@ -1374,10 +1396,12 @@ int lmdg_workspace_bytes(const lmdg_t* h, int restart, int64_t* held, int64_t* s
   if (h->d_sqa) b += 3 * (size_t)nc * d;
   b += h->krylov_doubles * d + h->small_doubles * d + 2 * h->psi_doubles * d;
   if (h->d_cvec) b += 6 * (size_t)h->np * nc * d;
+  b += lmdg::pc_bytes(h);
   *held = (int64_t)b;
   // what a solve with this restart (and the handle's augmentation) allocates beyond that
   const int ka = std::max(0, std::min(h->augment, kMaxRestart - restart));
-  const size_t kry = (size_t)(restart + ka + 2 + (ka > 0 ? 2 * ka + 2 : 0)) * h->np * nc * h->n_rhs;
+  const size_t kry = (size_t)(restart + ka + 2 + (ka > 0 ? 2 * ka + 2 : 0) + (h->pc_kind ? 2 : 0)) * h->np * nc *
+                     h->n_rhs;
   const size_t small = small_layout(h->n_rhs).total;
   *solve = (int64_t)((kry > h->krylov_doubles ? kry : 0) + (small > h->small_doubles ? small : 0)) * (int64_t)d;
   return LMDG_OK;
@@ -1415,6 +1439,29 @@ int lmdg_set_augment(lmdg_t* h, int k) {
   if (k < 0 || k > kMaxRestart - 1) return set_error(h, LMDG_INVALID_ARG, "augmentation count out of range");
   h->augment = k;
   return LMDG_OK;
+}
+
+int lmdg_set_preconditioner(lmdg_t* h, int kind, int cycles) {
+  if (!h) return LMDG_INVALID_ARG;
+  if (kind < LMDG_PRECOND_NONE || kind > LMDG_PRECOND_TWO_LEVEL || cycles < 1 || cycles > 50)
+    return set_error(h, LMDG_INVALID_ARG, "preconditioner kind or cycles out of range");
+  if (kind != LMDG_PRECOND_NONE && (h->dim != 2 || h->slab))
+    return set_error(h, LMDG_UNSUPPORTED, "the preconditioner is built for 2D handles");
+  h->pc_kind = kind;
+  h->pc_cycles = cycles;
+  return LMDG_OK;
+}
+
+int lmdg_precond_apply(lmdg_t* h, int scheme, const double* r, double* z, void* stream) {
+  int rc = check_call(h, scheme, LMDG_PREC_FP64);
+  if (rc != LMDG_OK) return rc;
+  if (!r || !z) return set_error(h, LMDG_INVALID_ARG, "NULL vector");
+  hipStream_t st = (hipStream_t)stream;
+  if (h->pc_kind == LMDG_PRECOND_NONE) {
+    lmdg::vec_copy(z, r, (long long)h->np * h->ncell * h->n_rhs, st);
+    return check_hip(h, hipGetLastError(), "copy");
+  }
+  return lmdg::pc_apply(h, scheme, r, z, st);
 }
 
 int lmdg_profile(lmdg_t* h, int enable) {

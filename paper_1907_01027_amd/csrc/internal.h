@@ -112,6 +112,31 @@ struct Workspace {
   double* vec = nullptr;        // scratch moment vectors (kScratchVecs * 4 * ncell)
 };
 
+// Two-level preconditioner (precond.hip): cell blocks K_loc^{-1}, level-0 node arrays of
+// the eq-difflimPF operator, and the Cartesian multigrid levels of both parity classes.
+struct PcLevel {
+  int mx = 0, my = 0;
+  double* S = nullptr;   // [2][9][mx my] stencils, entry (dy + 1) * 3 + dx + 1
+  double* u = nullptr;   // [2][mx my]
+  double* f = nullptr;
+  double* r = nullptr;
+};
+struct Precond {
+  int NX = 0, NY = 0;                      // nodes of level 0
+  int kloc_scheme = -1;                    // scheme kinv was formed for
+  unsigned long long kloc_mat = 0, mg_mat = 0;   // material versions they were built from
+  double* kinv = nullptr;                  // [16][n_cells] row-major 4 x 4 inverses
+  double* wcell = nullptr;                 // [n_cells] weights of the diagonal node pairs
+  double* d0 = nullptr;                    // [NX NY] level-0 diagonal
+  double* u0 = nullptr;
+  double* f0 = nullptr;
+  std::vector<PcLevel> lev;                // levels 1.. (last: coarsest, dense inverse)
+  double* cinv = nullptr;                  // [2][m][m]
+  double* cwork = nullptr;                 // [2][m][2m]
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+};
+
 }  // namespace lmdg
 
 struct lmdg_handle {
@@ -190,6 +215,10 @@ struct lmdg_handle {
   double* h_small = nullptr;       // pinned host mirror
   size_t small_doubles = 0;
   int augment = 0;                 // LGMRES: stored corrections searched per restart cycle
+  unsigned long long mat_version = 0;   // bumped by lmdg_set_materials
+  int pc_kind = 0;                 // LMDG_PRECOND_* used by the solves
+  int pc_cycles = 1;               // V-cycles per application of the two-level preconditioner
+  lmdg::Precond* pc = nullptr;
 };
 
 namespace lmdg {
@@ -250,6 +279,13 @@ void vec_axpby(double* y, double a, const double* x, double b, long long n, hipS
 void vec_copy(double* y, const double* x, long long n, hipStream_t st);
 void vec_fill(double* y, double v, long long n, hipStream_t st);
 int dots_partials();
+
+// two-level preconditioner (precond.hip)
+bool pc_supported(const lmdg_handle* h, int scheme, std::string* why);
+int pc_prepare(lmdg_handle* h, int scheme, hipStream_t st);
+int pc_apply(lmdg_handle* h, int scheme, const double* r, double* z, hipStream_t st);
+void pc_free(lmdg_handle* h);
+size_t pc_bytes(const lmdg_handle* h);
 
 int set_error(lmdg_handle* h, int status, const std::string& msg);
 int check_hip(lmdg_handle* h, hipError_t e, const char* what);

@@ -25,12 +25,14 @@ LMDG_UNSUPPORTED = 5
 SCHEMES = {"std": 0, "lmdg": 1, "rlmdg": 2}
 PRECS = {"fp64": 0, "fp32": 1}
 MODES = {"fp64": 0, "mixed": 1}
+PRECONDS = {"none": 0, "cell": 1, "two-level": 2}
 
 EXPORTED = ["lmdg_status_string", "lmdg_last_error", "lmdg_quadrature_level_symmetric", "lmdg_create",
             "lmdg_destroy", "lmdg_set_materials", "lmdg_set_sources", "lmdg_sweep", "lmdg_apply", "lmdg_rhs",
             "lmdg_recover", "lmdg_solve", "lmdg_set_augment", "lmdg_adjoint_solve", "lmdg_profile",
             "lmdg_sweep_kernel_time", "lmdg_synchronize", "lmdg_set_wait_limit", "lmdg_set_source_moments",
-            "lmdg_workspace_bytes", "lmdg_apply_noalloc", "lmdg_set_reconstruction"]
+            "lmdg_workspace_bytes", "lmdg_apply_noalloc", "lmdg_set_reconstruction", "lmdg_set_preconditioner",
+            "lmdg_precond_apply"]
 
 
 class LmdgInfo(ctypes.Structure):
@@ -76,6 +78,8 @@ def _load():
         "lmdg_workspace_bytes": (I, [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
         "lmdg_apply_noalloc": (I, [P, I, I, P, P, P]),
         "lmdg_set_reconstruction": (I, [P, I, I]),
+        "lmdg_set_preconditioner": (I, [P, I, I]),
+        "lmdg_precond_apply": (I, [P, I, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -228,6 +232,14 @@ def lmdg_adjoint_solve(h, scheme, mode, det, tol, restart, max_iter, g_sigma_s, 
 def lmdg_set_reconstruction(h, stencil=2, suppress=False):
     """RLMDG reconstruction variant: stencil 2 (default) or 3 (RLMDG*), suppression at jumps."""
     _check(_lib.lmdg_set_reconstruction(h, int(stencil), int(bool(suppress))), h)
+
+
+def lmdg_set_preconditioner(h, kind="two-level", cycles=1):
+    _check(_lib.lmdg_set_preconditioner(h, PRECONDS[kind], int(cycles)), h)
+
+
+def lmdg_precond_apply(h, scheme, r, z, stream=None):
+    _check(_lib.lmdg_precond_apply(h, SCHEMES[scheme], _ptr(r), _ptr(z), _stream(stream)), h)
 
 
 def lmdg_set_augment(h, k):

@@ -16,7 +16,9 @@ Afterwards: the same workload solved to a true FP64 relative residual of 1e-8 in
 and mixed mode; the other workloads as secondary figures (256^2 S8 eps = 1e-3 FP64 with
 its own roofline, the 1024^2 S16 multiscale workload with FP64 and mixed solves, the
 512^2 S12 detector gradients, a slab, the 20^2 S4 solves); and the CPU oracle timed on
-bounded samples (see cpu_baseline.sample).
+bounded samples (see cpu_baseline.sample).  The 2D low-memory solves use the two-level
+preconditioner (lmdg_set_preconditioner; --precond none for plain LGMRES); the 3D and
+slab solves and the 20^2 S4 solves run without it.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-solve] [--no-extra]
 """
@@ -58,6 +60,9 @@ def parse():
     ap.add_argument("--profile-workload", type=int, default=0,
                     help="only time K x on workload 3, 4 or 5 (all its sources) for a profiler run")
     ap.add_argument("--prec", default="fp64", choices=("fp64", "fp32"))
+    ap.add_argument("--precond", default="two-level", choices=("none", "cell", "two-level"),
+                    help="preconditioner of the 2D low-memory solves (256^2, 1024^2, 512^2 adjoint)")
+    ap.add_argument("--pc-cycles", type=int, default=1, help="V-cycles per preconditioner application")
     return ap.parse_args()
 
 
@@ -144,10 +149,8 @@ def cpu_baseline(seconds):
 
     value: its reduced-operator rate (updates/s) on a 12^3 sample of the headline recipe
     (3D S8, RLMDG, one source at a time: the oracle has no multi-source path).  Beside
-    it: the oracle's full solves of the 20^2 S4 workload (to 1e-10, both schemes), and
-    for the 256^2 S8 workload its operator time on a 128^2 sample scaled to 256^2 by the
-    cell count (an extrapolation, labelled as such; the solve time is that times the
-    applications the GPU's FP64 solve needed)."""
+    it: the oracle's full solves of the 20^2 S4 workload (to 1e-10, both schemes), and its
+    preconditioned solve of the 256^2 S8 recipe on a 128^2 sample (to 1e-8)."""
     from oracle import schemes as S
     from oracle.dg import Mesh
     from oracle.quadrature import level_symmetric
@@ -179,27 +182,32 @@ def cpu_baseline(seconds):
         t0 = time.perf_counter()
         _, its = make().solve(tol=1e-10, restart=30)
         solves[f"20x20_S4_{name}_tol1e-10"] = {"wall_s": time.perf_counter() - t0, "iterations": its}
-    # 256^2, S8: operator time on a 128^2 sample of the same recipe, scaled by the cell count
+    # 256^2 recipe on a 128^2 sample: the oracle's own preconditioned solve (its direct
+    # solve of the diffusion operator) to 1e-8, set-up included
+    from oracle import precond as PC
     n2 = (128, 128)
     ss2, sa2, ep2, q2 = materials(2, n=n2)
     om8, w8 = level_symmetric(8, 2)
     t0 = time.perf_counter()
     red2 = S.LowMemoryReduced(S.Problem(Mesh(n2), om8, w8, ss2, sa2, ep2, q=q2[0]), reconstructed=True)
     setup2 = time.perf_counter() - t0
-    x2 = np.random.default_rng(1).normal(size=4 * n2[0] * n2[1])
     t0 = time.perf_counter()
-    for _ in range(3):
-        red2.apply(x2)
-    apply128 = (time.perf_counter() - t0) / 3
+    x2 = np.random.default_rng(1).normal(size=4 * n2[0] * n2[1])
+    red2.apply(x2)
+    apply128 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, its2 = PC.solve(red2, tol=1e-8, restart=30)
+    solve128 = time.perf_counter() - t0
     return {"value": ups, "unit": "cell-direction updates/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle RLMDG reduced operator K x (sparse LU of each direction's sweep block, FP64, "
                       f"one source) on a 12^3 mesh with the 3D S8 set and the headline recipe: {k} applications "
                       f"in {el:.1f} s after {setup:.1f} s of assembly and factorisation; single-threaded "
                       f"SciPy/NumPy (host has {os.cpu_count()} logical CPUs; thread settings {threads})",
             "solves": solves,
-            "256x256_S8_rlmdg_apply_s_extrapolated": {
-                "value": apply128 * 4.0, "from": f"128^2 sample: {apply128:.3f} s per K x after {setup2:.1f} s of "
-                                                  f"set-up, times 4 for the cell count (extrapolated)"}}
+            "128x128_S8_eps1e-3_rlmdg_preconditioned_solve": {
+                "wall_s": solve128, "setup_s": setup2, "iterations": its2, "apply_s": apply128,
+                "note": "oracle two-level preconditioner with a direct solve of its diffusion operator, "
+                        "GMRES(30) to 1e-8; the 256^2 recipe on a 128^2 mesh (sample)"}}
 
 
 def _apply_rate(torch, lmdg, h, scheme, prec, x, y, ncell, ndir, n_rhs=1, reps=5):
@@ -274,9 +282,17 @@ def extra_measurements(torch, lmdg, WORKLOADS, materials, args):
                            "bytes_per_launch": nbytes, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(2)}
     if not args.no_solve:
-        lmdg.lmdg_set_augment(s.h, args.augment)
-        e2["solve_tol1e-8"] = _solve_pair(torch, lmdg, s.h, "rlmdg", 4 * nc, 1e-8, 60, args.solve_max_iter, dev,
+        lmdg.lmdg_set_preconditioner(s.h, args.precond, args.pc_cycles)
+        e2["solve_tol1e-8"] = _solve_pair(torch, lmdg, s.h, "rlmdg", 4 * nc, 1e-8, 30, args.solve_max_iter, dev,
                                           "256^2")
+        e2["solve_tol1e-8"].update({"restart": 30, "precond": args.precond, "pc_cycles": args.pc_cycles})
+        if args.precond != "none":
+            # the same solves without the preconditioner: LGMRES(60 + 10)
+            lmdg.lmdg_set_preconditioner(s.h, "none", 1)
+            lmdg.lmdg_set_augment(s.h, args.augment)
+            e2["solve_tol1e-8_unpreconditioned"] = _solve_pair(torch, lmdg, s.h, "rlmdg", 4 * nc, 1e-8, 60,
+                                                               args.solve_max_iter, dev, "256^2 unpreconditioned")
+            e2["solve_tol1e-8_unpreconditioned"].update({"restart": 60, "augment": args.augment})
     res["256x256_S8_eps1e-3_rlmdg"] = e2
     s.close()
     del x, y
@@ -292,10 +308,14 @@ def extra_measurements(torch, lmdg, WORKLOADS, materials, args):
     e3 = {p: _apply_rate(torch, lmdg, s.h, "rlmdg", p, x, y, nc, len(w)) for p in ("fp64", "fp32")}
     del x, y
     if not args.no_solve:
-        lmdg.lmdg_set_augment(s.h, args.augment)
-        e3["solve_tol1e-8"] = _solve_pair(torch, lmdg, s.h, "rlmdg", 4 * nc, 1e-8, 60, args.cfg3_max_iter, dev,
-                                          "1024^2")
-        e3["solve_tol1e-8"]["max_iter"] = args.cfg3_max_iter
+        lmdg.lmdg_set_preconditioner(s.h, args.precond, args.pc_cycles)
+        if args.precond == "none":
+            lmdg.lmdg_set_augment(s.h, args.augment)
+        restart = 30 if args.precond != "none" else 60
+        e3["solve_tol1e-8"] = _solve_pair(torch, lmdg, s.h, "rlmdg", 4 * nc, 1e-8, restart, args.cfg3_max_iter,
+                                          dev, "1024^2")
+        e3["solve_tol1e-8"].update({"max_iter": args.cfg3_max_iter, "restart": restart, "precond": args.precond,
+                                    "pc_cycles": args.pc_cycles})
     res["1024x1024_S16_multiscale_rlmdg"] = e3
     s.close()
     _progress("1024^2 workload done")
@@ -306,7 +326,10 @@ def extra_measurements(torch, lmdg, WORKLOADS, materials, args):
     om, w = lmdg.lmdg_quadrature_level_symmetric(2, wl.order)
     s = lmdg.Solver(wl.n, (1.0, 1.0), om, w)
     lmdg.lmdg_set_materials(s.h, T(ss), T(sa), T(ep), T(q[0]))
-    lmdg.lmdg_set_augment(s.h, 10)
+    lmdg.lmdg_set_preconditioner(s.h, args.precond, args.pc_cycles)
+    adj_restart = 30 if args.precond != "none" else 60
+    if args.precond == "none":
+        lmdg.lmdg_set_augment(s.h, 10)
     nc = wl.n[0] * wl.n[1]
     x = T(np.random.default_rng(1).normal(size=4 * nc))
     y = torch.empty_like(x)
@@ -320,13 +343,13 @@ def extra_measurements(torch, lmdg, WORKLOADS, materials, args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
-            J, info = lmdg.lmdg_adjoint_solve(s.h, "lmdg", mode, det, 1e-8, 60, 30000, *g)
+            J, info = lmdg.lmdg_adjoint_solve(s.h, "lmdg", mode, det, 1e-8, adj_restart, 30000, *g)
             ok = True
         except lmdg.LmdgError as e:
             J, info, ok = float("nan"), {"error": str(e)}, False
         torch.cuda.synchronize()
-        e = {"wall_s": time.perf_counter() - t0, "J": J, "converged": ok,
-             "iterations": info.get("iterations"), "rel_residual": info.get("rel_residual")}
+        e = {"wall_s": time.perf_counter() - t0, "J": J, "converged": ok, "precond": args.precond,
+             "restart": adj_restart, "iterations": info.get("iterations"), "rel_residual": info.get("rel_residual")}
         if mode == "fp64":
             g64, J64 = g, J
         elif ok and g64 is not None:

@@ -661,7 +661,7 @@ int apply_op(lmdg_t* h, int scheme, int prec, const double* x, double* y, hipStr
   // printed: K x = [x_0 - P_0 psi ; B_11 x_1 - G psi])
   // the 3D standard scheme has the plain form only
   const bool defect = !(scheme == LMDG_SCHEME_RLMDG && h->recon_flags != 0) && !(h->dim == 3 && scheme == LMDG_SCHEME_STD);
-  int rc = lmdg::launch_sweep(h, scheme, prec, x, false, nullptr, st, defect);
+  int rc = lmdg::launch_sweep(h, scheme, prec, x, false, nullptr, st, defect, 0xF, false, false);
   if (rc != LMDG_OK) return rc;
   lmdg::launch_combine(h, scheme, prec, defect ? lmdg::kApplyDefect : lmdg::kApply, x, y, st);
   return check_hip(h, hipGetLastError(), "combine");
@@ -1080,7 +1080,7 @@ int lmdg_rhs(lmdg_t* h, int scheme, int prec, double* b, void* stream) {
     lmdg::launch_combine(h, LMDG_SCHEME_RLMDG, prec, lmdg::kRhs, nullptr, b, st);
     return check_hip(h, hipGetLastError(), "rhs");
   }
-  rc = lmdg::launch_sweep(h, scheme, prec, nullptr, true, nullptr, st);
+  rc = lmdg::launch_sweep(h, scheme, prec, nullptr, true, nullptr, st, false, 0xF, false, false);
   if (rc != LMDG_OK) return rc;
   lmdg::launch_combine(h, scheme, prec, lmdg::kRhs, nullptr, b, st);
   return check_hip(h, hipGetLastError(), "rhs");
@@ -1123,7 +1123,7 @@ static int solve_impl(lmdg_t* h, int scheme, int mode, double tol, int restart, 
   if (!rhs_x) {
     rc = lmdg_rhs(h, scheme, LMDG_PREC_FP64, b, st);
   } else {
-    rc = lmdg::launch_sweep(h, scheme, LMDG_PREC_FP64, rhs_x, true, nullptr, st);
+    rc = lmdg::launch_sweep(h, scheme, LMDG_PREC_FP64, rhs_x, true, nullptr, st, false, 0xF, false, false);
     if (rc == LMDG_OK) lmdg::launch_combine(h, scheme, LMDG_PREC_FP64, lmdg::kRhs, nullptr, b, st);
   }
   if (rc != LMDG_OK) return rc;

@@ -243,11 +243,13 @@ inline int part_slices(const lmdg_handle* h, int scheme, int prec) {
 }
 
 // launchers (sweep2d.hip / ops.hip)
+// p1r: the sweep also produces the P_1 R rows of RLMDG (false when the combine that
+// follows reads only the operator rows: operator applications and right-hand sides)
 int launch_sweep(lmdg_handle* h, int scheme, int prec, const double* x, bool use_q,
                  double* psi, hipStream_t st, bool defect = false, int qmask = 0xF,
-                 bool psi_by_slot = false);
+                 bool psi_by_slot = false, bool p1r = true);
 int launch_sweep3d(lmdg_handle* h, int scheme, int prec, const double* x, bool use_q, double* psi,
-                   hipStream_t st, bool defect);
+                   hipStream_t st, bool defect, bool p1r);
 // workspace of the 3D sweeps per right-hand side (sweep3d.hip)
 size_t sweep3d_edge_bytes(const lmdg_handle* h);
 size_t sweep3d_coef_bytes(const lmdg_handle* h);

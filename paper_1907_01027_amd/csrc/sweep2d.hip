@@ -923,10 +923,10 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
 }  // namespace
 
 int launch_sweep(lmdg_handle* h, int scheme, int prec, const double* x, bool use_q, double* psi,
-                 hipStream_t st, bool defect, int qmask, bool psi_by_slot) {
+                 hipStream_t st, bool defect, int qmask, bool psi_by_slot, bool p1r) {
   if (h->dim == 3) {
     if (qmask != 0xF || psi_by_slot) return set_error(h, LMDG_UNSUPPORTED, "quadrant-restricted 3D sweep");
-    return launch_sweep3d(h, scheme, prec, x, use_q, psi, st, defect);
+    return launch_sweep3d(h, scheme, prec, x, use_q, psi, st, defect, p1r);
   }
   if ((qmask & 0xF) == 0) return set_error(h, LMDG_INVALID_ARG, "empty quadrant mask");
   if (prec == LMDG_PREC_FP64) {

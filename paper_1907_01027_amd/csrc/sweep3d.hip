@@ -175,7 +175,7 @@ __global__ void coef3_kernel(Coef3Params P, R* __restrict__ out) {
 // The symmetric part of the block is positive definite, so elimination needs no pivoting.
 // Outflow traces handed downwind along a: T_t = c_t + s_a c_{t+a} for the modes t without a.
 template <typename R>
-__device__ __forceinline__ void cell_std3(const Dir3<R>& d, const int si[3], const R* src, R sigV, const R* xin,
+__device__ __forceinline__ void cell_std3(const Dir3<R>& d, R wa, const int si[3], const R* src, R sigV, const R* xin,
                                           const R* yin, const R* zin, R* xo, R* yo, R* zo, R* o, R* c) {
   R m[8][8], b[8];
 #pragma unroll
@@ -232,12 +232,15 @@ __device__ __forceinline__ void cell_std3(const Dir3<R>& d, const int si[3], con
     }
   }
 #pragma unroll
-  for (int n = 0; n < 8; ++n) o[n] = d.w * c[n];
+  for (int n = 0; n < 8; ++n) o[n] = wa * c[n];
 }
 
-template <typename R, int S, int MAXW, int CB>
+// P1R: also the P_1 R rows of RLMDG (read by the recovery and by lmdg_sweep's output;
+// operator applications and right-hand sides skip them).  PSI: angular fluxes stored.
+template <typename R, int S, int MAXW, int CB, bool P1R, bool PSI>
 __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
-  constexpr int NOUT = Traits3<S>::NOUT;
+  constexpr int NOUT_ALL = Traits3<S>::NOUT;       // partial rows per cell (layout stride)
+  constexpr int NOUT = (S == LMDG_SCHEME_RLMDG && !P1R) ? 7 : NOUT_ALL;  // rows produced
   constexpr int NOUTP = (NOUT + 3) & ~3;  // rows of red, padded to whole lane groups
   constexpr int NF = Traits3<S>::NF;
   constexpr int NK = Traits3<S>::NK;
@@ -265,12 +268,14 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
   const int ds = P.dslots;
   const double A[3] = {P.h[1] * P.h[2], P.h[0] * P.h[2], P.h[0] * P.h[1]};
   // LDS: red [CB][W][NOUTP][16] (+1 pad per step) | cbuf [NBUF][NK][CB][16] | eds [CB][ds][NF]
+  //      | ybuf [CB][ds][NF] (the top row's y traces of the period, written out after the steps)
   R* red = reinterpret_cast<R*>(smem_raw);
   // one step's block of red holds W x NOUTP x 16 values plus one pad, so that the
   // reduction's reads of consecutive steps fall in different banks
   const int red_tt = W * NOUTP * kRows + 1;
   R* cbuf = red + (size_t)CB * red_tt;
   R* eds = cbuf + (size_t)NBUF * NK * CB16;
+  R* ybuf = eds + (size_t)CB * ds * NF;
 
   for (;;) {
     if (tid == 0) s_item = (int)(atomicAdd(P.ticket, 1u) - P.ticket_base);
@@ -289,11 +294,11 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) si[a] = ((o >> a) & 1) ? -1 : 1;
     const long long ro = (long long)rh * 8 + o;
-    R* const partr = P.part + ro * NOUT * nc;
+    R* const partr = P.part + ro * NOUT_ALL * nc;
     R* const xeb = P.xedge + ro * P.xedge_ostride;   // [nz][nstrips][nblk][16][ds][NF]
     R* const yeb = P.yedge + ro * P.yedge_ostride;   // [nz][nstrips][nx][ds][NF]
     unsigned long long* const progr = P.prog + ro * (long long)nstrips * nblk;
-    double* const psir = P.psi ? P.psi + rh * P.psi_rstride : nullptr;
+    double* const psir = PSI ? P.psi + rh * P.psi_rstride : nullptr;
     const R* const cf_rh = P.coef + (long long)rh * NA * nc;
     const R* const cf_sh = P.coef + (long long)P.n_rhs * NA * nc;  // shared: sigma_t V (, eps sigma_a V / 3)
 
@@ -438,13 +443,15 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
           yd[f] = (r == 0) ? eds[(u * ds + slot) * NF + f] : v;
           zi[f] = (q <= 0) ? R(0) : zreg[u][f];
         }
-        R o[NOUT], xo[NF], yo[NF], zo[NF];
+        R o[NOUT_ALL], xo[NF], yo[NF], zo[NF];
+        // the weight of an inactive lane-step is zero, so its (finite) values add nothing
+        const R wa = act ? d.w : R(0);
         if constexpr (STDS) {
           R src[8], cm[8];
 #pragma unroll
           for (int m = 0; m < 8; ++m) src[m] = cf[(1 + m) * CB16];
-          cell_std3<R>(d, si, src, cf[0], xi, yd, zi, xo, yo, zo, o, cm);
-          if (psir && act && d.idx >= 0) {
+          cell_std3<R>(d, wa, si, src, cf[0], xi, yd, zi, xo, yo, zo, o, cm);
+          if (PSI && act && d.idx >= 0) {
             const int i = si[0] > 0 ? c : nx - 1 - c;
             const int kk = si[2] > 0 ? q : nz - 1 - q;
             const long long cell = (long long)kk * nxy + (long long)j * nx + i;
@@ -459,10 +466,10 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
             const R inv = recip(sig + d.aA[0] + d.aA[1] + d.aA[2]);
             psi = (src + d.aA[0] * xi[0] + d.aA[1] * yd[0] + d.aA[2] * zi[0]) * inv;
             xo[0] = yo[0] = zo[0] = psi;
-            o[0] = d.w * psi;
-            o[1] = d.w * d.oA[0] * (xi[0] - psi);
-            o[2] = d.w * d.oA[1] * (yd[0] - psi);
-            o[3] = d.w * d.oA[2] * (zi[0] - psi);
+            o[0] = wa * psi;
+            o[1] = wa * d.oA[0] * (xi[0] - psi);
+            o[2] = wa * d.oA[1] * (yd[0] - psi);
+            o[3] = wa * d.oA[2] * (zi[0] - psi);
           } else {
             // traces per axis: [outflow face value, two tangential slopes, cell value];
             // tangential slopes in axis order: x carries (c_y, c_z), y (c_x, c_z), z (c_x, c_y)
@@ -490,21 +497,23 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
             zo[3] = psi;
             // eps sigma_a V / 3: sigma_t V / 3 of L_11 R minus (sigma_s/eps) V / 3 of M_1 P_1 R
             const R sV3 = cf[5 * CB16];
-            o[0] = d.w * psi;
-            o[1] = d.w * (d.oA[0] * (xi[0] - psi) + (sV3 + d.aA[0]) * cx +
-                          third * (d.aA[1] * (cx - yd[1]) + d.aA[2] * (cx - zi[1])));
-            o[2] = d.w * (d.oA[1] * (yd[0] - psi) + (sV3 + d.aA[1]) * cy +
-                          third * (d.aA[0] * (cy - xi[1]) + d.aA[2] * (cy - zi[2])));
-            o[3] = d.w * (d.oA[2] * (zi[0] - psi) + (sV3 + d.aA[2]) * cz +
-                          third * (d.aA[0] * (cz - xi[2]) + d.aA[1] * (cz - yd[2])));
-            o[4] = d.w * third * (d.oA[0] * (xi[1] - cy) + d.oA[1] * (yd[1] - cx));
-            o[5] = d.w * third * (d.oA[0] * (xi[2] - cz) + d.oA[2] * (zi[1] - cx));
-            o[6] = d.w * third * (d.oA[1] * (yd[2] - cz) + d.oA[2] * (zi[2] - cy));
-            o[7] = d.w * cx;
-            o[8] = d.w * cy;
-            o[9] = d.w * cz;
+            o[0] = wa * psi;
+            o[1] = wa * (d.oA[0] * (xi[0] - psi) + (sV3 + d.aA[0]) * cx +
+                         third * (d.aA[1] * (cx - yd[1]) + d.aA[2] * (cx - zi[1])));
+            o[2] = wa * (d.oA[1] * (yd[0] - psi) + (sV3 + d.aA[1]) * cy +
+                         third * (d.aA[0] * (cy - xi[1]) + d.aA[2] * (cy - zi[2])));
+            o[3] = wa * (d.oA[2] * (zi[0] - psi) + (sV3 + d.aA[2]) * cz +
+                         third * (d.aA[0] * (cz - xi[2]) + d.aA[1] * (cz - yd[2])));
+            o[4] = wa * third * (d.oA[0] * (xi[1] - cy) + d.oA[1] * (yd[1] - cx));
+            o[5] = wa * third * (d.oA[0] * (xi[2] - cz) + d.oA[2] * (zi[1] - cx));
+            o[6] = wa * third * (d.oA[1] * (yd[2] - cz) + d.oA[2] * (zi[2] - cy));
+            if constexpr (P1R) {
+              o[7] = wa * cx;
+              o[8] = wa * cy;
+              o[9] = wa * cz;
+            }
           }
-          if (psir && act && d.idx >= 0) {
+          if (PSI && act && d.idx >= 0) {
             const int i = si[0] > 0 ? c : nx - 1 - c;
             const int kk = si[2] > 0 ? q : nz - 1 - q;
             psir[(long long)d.idx * nc + (long long)kk * nxy + (long long)j * nx + i] = (double)psi;
@@ -517,17 +526,16 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
           zreg[u][f] = zo[f];
           xsave[f] = (cl == CB - 1) ? xo[f] : xsave[f];
         }
-        // top row: y traces for strip s + 1
-        if (r == kRows - 1 && act && s + 1 < nstrips) {
-          R* dst = yeb + (((long long)q * nstrips + s) * nx + c) * ds * NF + slot * NF;
+        // top row: y traces for strip s + 1, staged in LDS for one store pass per period
+        if (r == kRows - 1) {
 #pragma unroll
-          for (int f = 0; f < NF; ++f) store_agent(dst + f, yo[f]);
+          for (int f = 0; f < NF; ++f) ybuf[(u * ds + slot) * NF + f] = yo[f];
         }
         // sums over the four direction slots of the wave, four rows at a time: lane group
         // g receives row m0 + g
         R om[NOUTP];
 #pragma unroll
-        for (int m = 0; m < NOUTP; ++m) om[m] = (m < NOUT && act) ? o[m < NOUT ? m : 0] : R(0);
+        for (int m = 0; m < NOUTP; ++m) om[m] = m < NOUT ? o[m < NOUT ? m : 0] : R(0);
 #pragma unroll
         for (int m0 = 0; m0 < NOUTP; m0 += 4) {
           const R v = quad_sum4(om[m0], om[m0 + 1], om[m0 + 2], om[m0 + 3]);
@@ -535,6 +543,20 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
         }
         // keep each step's loads next to its arithmetic (bounds the registers held)
         __builtin_amdgcn_sched_barrier(0);
+      }
+      // y traces of the period's top-row cells for strip s + 1 (row 15 handled the cell
+      // lambda = u - 15 at step u)
+      lds_barrier();
+      if (s + 1 < nstrips) {
+        const int ne = CB * ds * NF;
+        for (int e = tid; e < ne; e += blockDim.x) {
+          const int u = e / (ds * NF);
+          const int dd = u - (kRows - 1);
+          const int q = p + (dd >> LCB);
+          const int c = c0 + (dd & (CB - 1));
+          if (q >= 0 && q < nz && c < nx)
+            store_agent(yeb + (((long long)q * nstrips + s) * nx + c) * ds * NF + (e - u * ds * NF), ybuf[e]);
+        }
       }
       // x traces for block b + 1: the period's cell in the block's last column
       {
@@ -580,24 +602,24 @@ __global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
   }
 }
 
-template <typename R, int S>
+template <typename R, int S, bool P1R>
 size_t lds_bytes3(int cb, int W, int dslots) {
-  constexpr int NOUT = Traits3<S>::NOUT;
+  constexpr int NOUT = (S == LMDG_SCHEME_RLMDG && !P1R) ? 7 : Traits3<S>::NOUT;
   constexpr int NOUTP = (NOUT + 3) & ~3;
   const int L = (kRows - 1 + cb - 1) / cb;
   return ((size_t)cb * (W * NOUTP * kRows + 1) + (size_t)(L + 2) * Traits3<S>::NK * cb * kRows +
-          (size_t)cb * dslots * Traits3<S>::NF) *
+          (size_t)2 * cb * dslots * Traits3<S>::NF) *
          sizeof(R);
 }
 
 // Work items the GPU holds at once for one instantiation (occupancy query, cached).
-template <typename R, int S, int MAXW, int CB>
+template <typename R, int S, int MAXW, int CB, bool P1R, bool PSI>
 int resident_blocks(int threads, size_t lds) {
   static int per_cu = -1;
   static size_t per_cu_lds = 0;
   if (per_cu < 0 || per_cu_lds != lds) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep3d_kernel<R, S, MAXW, CB>, threads, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sweep3d_kernel<R, S, MAXW, CB, P1R, PSI>, threads, lds) !=
             hipSuccess ||
         nb < 1)
       nb = 1;
@@ -607,14 +629,14 @@ int resident_blocks(int threads, size_t lds) {
   return per_cu;
 }
 
-template <typename R, int S, int MAXW, int CB>
+template <typename R, int S, int MAXW, int CB, bool P1R, bool PSI>
 int launch_kernel3(lmdg_handle* h, const Sweep3Params<R>& P, int W, hipStream_t st) {
-  const size_t lds = lds_bytes3<R, S>(CB, W, h->dslots);
+  const size_t lds = lds_bytes3<R, S, P1R>(CB, W, h->dslots);
   if (lds > 160 * 1024)
     return set_error(h, LMDG_UNSUPPORTED, "direction set too large for the 3D sweep's LDS staging");
-  const int per_cu = resident_blocks<R, S, MAXW, CB>(64 * W, lds);
+  const int per_cu = resident_blocks<R, S, MAXW, CB, P1R, PSI>(64 * W, lds);
   const int grid = (int)std::min<long long>(P.n_items, (long long)per_cu * h->n_cu);
-  hipLaunchKernelGGL((sweep3d_kernel<R, S, MAXW, CB>), dim3(grid), dim3(64 * W), lds, st, P);
+  hipLaunchKernelGGL((sweep3d_kernel<R, S, MAXW, CB, P1R, PSI>), dim3(grid), dim3(64 * W), lds, st, P);
   h->ticket_base += (unsigned)(P.n_items + grid);
   return LMDG_OK;
 }
@@ -626,8 +648,15 @@ template <typename R>
 constexpr int block_cols3() { return sizeof(R) == 4 ? 8 : 4; }
 static_assert(block_cols3<float>() >= kMinBlockCols3 && block_cols3<double>() >= kMinBlockCols3, "workspace sizing");
 
+template <typename R, int S, int MAXW, int CB>
+int launch_kernel3_sel(lmdg_handle* h, const Sweep3Params<R>& P, int W, bool p1r, hipStream_t st) {
+  if (P.psi) return launch_kernel3<R, S, MAXW, CB, true, true>(h, P, W, st);
+  if (p1r || S != LMDG_SCHEME_RLMDG) return launch_kernel3<R, S, MAXW, CB, true, false>(h, P, W, st);
+  return launch_kernel3<R, S, MAXW, CB, false, false>(h, P, W, st);
+}
+
 template <typename R, int S>
-int launch3_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipStream_t st, bool defect) {
+int launch3_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipStream_t st, bool defect, bool p1r) {
   constexpr int CB = block_cols3<R>();
   constexpr int NF = Traits3<S>::NF;
   constexpr int NA = Traits3<S>::NA;
@@ -694,7 +723,8 @@ int launch3_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipS
     ev_end = h->ev_pool[h->ev_used + 1];
     h->ev_used += 2;
   }
-  const int rc = W <= 4 ? launch_kernel3<R, S, 4, CB>(h, P, W, st) : launch_kernel3<R, S, kMaxWaves, CB>(h, P, W, st);
+  const int rc = W <= 4 ? launch_kernel3_sel<R, S, 4, CB>(h, P, W, p1r, st)
+                        : launch_kernel3_sel<R, S, kMaxWaves, CB>(h, P, W, p1r, st);
   if (rc != LMDG_OK) return rc;
   if (ev_end) hipEventRecord(ev_end, st);
   h->epoch += 1;
@@ -716,17 +746,17 @@ size_t sweep3d_prog_words(const lmdg_handle* h) {
 }
 
 int launch_sweep3d(lmdg_handle* h, int scheme, int prec, const double* x, bool use_q, double* psi, hipStream_t st,
-                   bool defect) {
+                   bool defect, bool p1r) {
   if (scheme == LMDG_SCHEME_STD) {
     // the standard scheme takes the plain form M Phi (+ Q) of eq-sndg-phi
-    return prec == LMDG_PREC_FP64 ? launch3_typed<double, LMDG_SCHEME_STD>(h, x, use_q, psi, st, false)
-                                  : launch3_typed<float, LMDG_SCHEME_STD>(h, x, use_q, psi, st, false);
+    return prec == LMDG_PREC_FP64 ? launch3_typed<double, LMDG_SCHEME_STD>(h, x, use_q, psi, st, false, true)
+                                  : launch3_typed<float, LMDG_SCHEME_STD>(h, x, use_q, psi, st, false, true);
   }
   if (prec == LMDG_PREC_FP64)
-    return scheme == LMDG_SCHEME_LMDG ? launch3_typed<double, LMDG_SCHEME_LMDG>(h, x, use_q, psi, st, defect)
-                                      : launch3_typed<double, LMDG_SCHEME_RLMDG>(h, x, use_q, psi, st, defect);
-  return scheme == LMDG_SCHEME_LMDG ? launch3_typed<float, LMDG_SCHEME_LMDG>(h, x, use_q, psi, st, defect)
-                                    : launch3_typed<float, LMDG_SCHEME_RLMDG>(h, x, use_q, psi, st, defect);
+    return scheme == LMDG_SCHEME_LMDG ? launch3_typed<double, LMDG_SCHEME_LMDG>(h, x, use_q, psi, st, defect, p1r)
+                                      : launch3_typed<double, LMDG_SCHEME_RLMDG>(h, x, use_q, psi, st, defect, p1r);
+  return scheme == LMDG_SCHEME_LMDG ? launch3_typed<float, LMDG_SCHEME_LMDG>(h, x, use_q, psi, st, defect, p1r)
+                                    : launch3_typed<float, LMDG_SCHEME_RLMDG>(h, x, use_q, psi, st, defect, p1r);
 }
 
 }  // namespace lmdg

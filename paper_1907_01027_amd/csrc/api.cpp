@@ -761,10 +761,12 @@ struct GmresStats {
   // slot.  It persists across the gmres calls that share one GmresStats, so the inner
   // solves of iterative refinement (same FP32 operator) keep the earlier passes' pairs.
   int n_aug = 0, aug_next = 0;
+  int reorth = 0;  // Arnoldi steps that took a second Gram-Schmidt pass
 };
 
-// Restarted GMRES(m) with classical Gram-Schmidt applied twice, FP64 vectors, for the
-// handle's nr right-hand sides at once: nr independent GMRES instances (own Hessenberg
+// Restarted GMRES(m) with classical Gram-Schmidt (a second pass where the first
+// cancelled), FP64 vectors, for the handle's nr right-hand sides at once: nr
+// independent GMRES instances (own Hessenberg
 // matrices, rotations and stopping tests) share every operator application.  Solves
 // K_prec x = b from x (in/out); stops when every true FP64-operator residual
 // ||b - K x|| <= rtol ||b|| (true_prec) or after max_iter applications.  relres is
@@ -896,19 +898,36 @@ int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, doubl
         const int slot = ((aug_next - 1 - (j - m)) % ka_max + ka_max) % ka_max;
         lmdg::vec_copy(w, AZ + (size_t)slot * NT, NT, st);
       }
-      // two passes of classical Gram-Schmidt, coefficients kept on the device
+      // classical Gram-Schmidt, coefficients kept on the device; a second pass only where
+      // the first cancelled: ||w'|| < ||w|| / sqrt(2), i.e. ||w'||^2 < sum_i h_i^2 with
+      // w' = w - V h (Daniel, Gragg, Kaufman and Stewart 1976)
       lmdg::vec_dots(V, NT, j + 1, w, N, part, dcoef, st, nr);
       lmdg::vec_axpy_multi(w, V, NT, j + 1, dcoef, -1.0, N, st, nr);
       rc = check_hip(h, hipMemcpyAsync(hc, dcoef, (j + 1) * nr * sizeof(double), hipMemcpyDeviceToHost, st), "h");
       if (rc != LMDG_OK) break;
-      lmdg::vec_dots(V, NT, j + 1, w, N, part, dcoef, st, nr);
-      lmdg::vec_axpy_multi(w, V, NT, j + 1, dcoef, -1.0, N, st, nr);
-      rc = check_hip(h, hipMemcpyAsync(hc + (size_t)(mt + 1) * nr, dcoef, (j + 1) * nr * sizeof(double),
-                                       hipMemcpyDeviceToHost, st), "h2");
-      if (rc != LMDG_OK) break;
       rc = seg_norms(h, w, N, nr, hn.data(), st);  // synchronises: hc is valid afterwards
-      if (krylov) add_time();
       if (rc != LMDG_OK) break;
+      bool second = false;
+      for (int k = 0; k < nr && !second; ++k) {
+        if (done[k]) continue;
+        double hh = 0.0;
+        for (int i = 0; i <= j; ++i) hh += hc[(size_t)i * nr + k] * hc[(size_t)i * nr + k];
+        second = !(hn[k] * hn[k] >= hh);
+      }
+      double* hc2 = hc + (size_t)(mt + 1) * nr;
+      if (second) {
+        lmdg::vec_dots(V, NT, j + 1, w, N, part, dcoef, st, nr);
+        lmdg::vec_axpy_multi(w, V, NT, j + 1, dcoef, -1.0, N, st, nr);
+        rc = check_hip(h, hipMemcpyAsync(hc2, dcoef, (j + 1) * nr * sizeof(double), hipMemcpyDeviceToHost, st),
+                       "h2");
+        if (rc != LMDG_OK) break;
+        rc = seg_norms(h, w, N, nr, hn.data(), st);
+        if (rc != LMDG_OK) break;
+        stats.reorth += 1;
+      } else {
+        std::fill(hc2, hc2 + (size_t)(j + 1) * nr, 0.0);
+      }
+      if (krylov) add_time();
       bool all_done = true;
       for (int k = 0; k < nr; ++k) {
         if (done[k]) {  // finished at an earlier step: its segments stay zero

@@ -147,11 +147,13 @@ __global__ void combine_lm_kernel(int mode, int nr, int nsl, int nx, int ny, dou
     const double* x = x_all ? x_all + rh * 4 * nc : nullptr;
     const R* part = part_all + rh * nsl * NOUT * nc;
     double* out = out_all + rh * 4 * nc;
+    // rows the mode reads (RLMDG sweeps produce the P_1 R rows for the recovery only)
     double s[NOUT];
 #pragma unroll
     for (int m = 0; m < NOUT; ++m) {
       double acc = 0;
-      for (int q = 0; q < nsl; ++q) acc += (double)part[((long long)q * NOUT + m) * nc + p];
+      if (!RLM || m < 4 || mode == kRecover)
+        for (int q = 0; q < nsl; ++q) acc += (double)part[((long long)q * NOUT + m) * nc + p];
       s[m] = acc;
     }
     // the sweep's slope rows already hold G Psi (with Sigma M_1 P_1 R taken per direction)
@@ -374,27 +376,39 @@ __global__ void adj_rlm_source_kernel(int nx, int ny, double hx, double hy, int 
 // ---------------------------------------------------------------- GMRES vectors
 constexpr int kDotBlocks = 240;
 
-// Vectors of nr right-hand sides are stacked (segments of length n).  For basis
-// vector v (blockIdx.y) and segment rz (blockIdx.z):
-// partial[(v * nr + rz) * kDotBlocks + b] = block b's share of V_v[rz] . w[rz]
-__global__ void dots_partial_kernel(const double* __restrict__ V, long long ld, const double* __restrict__ w_all,
-                                    long long n, double* __restrict__ partial) {
-  const int v = blockIdx.y;
+// Vectors of nr right-hand sides are stacked (segments of length n).  For the group of
+// up to kDotGroup basis vectors v0 + 0.. (blockIdx.y) and segment rz (blockIdx.z):
+// partial[(v * nr + rz) * kDotBlocks + b] = block b's share of V_v[rz] . w[rz]; each
+// element of w is read once per group.
+constexpr int kDotGroup = 8;
+__global__ void dots_partial_kernel(const double* __restrict__ V, long long ld, int nvec,
+                                    const double* __restrict__ w_all, long long n, double* __restrict__ partial) {
+  const int v0 = blockIdx.y * kDotGroup;
+  const int nv = min(kDotGroup, nvec - v0);
   const int rz = blockIdx.z;
-  const double* vv = V + v * ld + rz * n;
   const double* w = w_all + rz * n;
-  double acc = 0;
+  double acc[kDotGroup];
+#pragma unroll
+  for (int k = 0; k < kDotGroup; ++k) acc[k] = 0.0;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
-       e += (long long)gridDim.x * blockDim.x)
-    acc += vv[e] * w[e];
-  __shared__ double sh[kBlock];
-  sh[threadIdx.x] = acc;
+       e += (long long)gridDim.x * blockDim.x) {
+    const double we = w[e];
+#pragma unroll
+    for (int k = 0; k < kDotGroup; ++k)
+      if (k < nv) acc[k] += V[(v0 + k) * ld + rz * n + e] * we;
+  }
+  __shared__ double sh[kDotGroup][kBlock];
+#pragma unroll
+  for (int k = 0; k < kDotGroup; ++k) sh[k][threadIdx.x] = acc[k];
   __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+  for (int s2 = kBlock / 2; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2)
+#pragma unroll
+      for (int k = 0; k < kDotGroup; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s2];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[((long long)v * gridDim.z + rz) * gridDim.x + blockIdx.x] = sh[0];
+  if (threadIdx.x < nv)
+    partial[((long long)(v0 + threadIdx.x) * gridDim.z + rz) * gridDim.x + blockIdx.x] = sh[threadIdx.x][0];
 }
 
 __global__ void dots_final_kernel(const double* __restrict__ partial, int nparts, double* __restrict__ out) {
@@ -544,7 +558,8 @@ void launch_gradients(lmdg_handle* h, int npsi, const double* bil, const double*
 
 void vec_dots(const double* V, long long ld, int nvec, const double* w, long long n, double* partial,
               double* out, hipStream_t st, int nr) {
-  hipLaunchKernelGGL(dots_partial_kernel, dim3(kDotBlocks, nvec, nr), dim3(kBlock), 0, st, V, ld, w, n, partial);
+  hipLaunchKernelGGL(dots_partial_kernel, dim3(kDotBlocks, (nvec + kDotGroup - 1) / kDotGroup, nr), dim3(kBlock), 0,
+                     st, V, ld, nvec, w, n, partial);
   hipLaunchKernelGGL(dots_final_kernel, dim3(nvec * nr), dim3(kBlock), 0, st, partial, kDotBlocks, out);
 }
 

@@ -465,10 +465,13 @@ __device__ __forceinline__ void raw_coef(const double* raw, int c, int jr, int s
 // cell).  Per-direction source moments are added to the staged isotropic source.
 // VAR (RLMDG): the reconstruction variants, with a per-cell upwind rule staged beside
 // the source coefficients (cell_rlmdg_var); used with the plain form of the source.
-template <typename R, int S, int MAXW, bool DIRECT, bool DATA = false, bool VAR = false>
+// P1R: also the P_1 R rows of RLMDG (read by the recovery and by lmdg_sweep's output;
+// operator applications and right-hand sides skip them).
+template <typename R, int S, int MAXW, bool DIRECT, bool DATA = false, bool VAR = false, bool P1R = true>
 __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
   static_assert(!VAR || S == LMDG_SCHEME_RLMDG, "reconstruction variants are RLMDG sweeps");
-  constexpr int NOUT = SchemeTraits<S>::NOUT;
+  constexpr int NOUT_ALL = SchemeTraits<S>::NOUT;   // partial rows per cell (layout stride)
+  constexpr int NOUT = (S == LMDG_SCHEME_RLMDG && !P1R) ? 4 : NOUT_ALL;  // rows produced
   constexpr int NOUTP = (NOUT + 3) & ~3;  // rows of red, padded to whole lane groups
   constexpr int NF = SrcTraitsV<S, VAR>::NF;
   constexpr int NS = SrcTraits<S>::NS;
@@ -514,7 +517,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
     const int rh = (item / P.nq) - s * P.n_rhs;
     const double* xr = P.x ? P.x + (long long)rh * 4 * nc : nullptr;
     const double* qAr = P.qA ? P.qA + (long long)rh * nc : nullptr;
-    R* const partr = P.part + (long long)rh * nsl * NOUT * nc;
+    R* const partr = P.part + (long long)rh * nsl * NOUT_ALL * nc;
     R* const edger = P.edge + rh * P.edge_rstride;
     unsigned long long* const progr = P.prog + (long long)rh * 4 * P.nstrips;
     double* const psir = P.psi ? P.psi + rh * P.psi_rstride : nullptr;
@@ -676,7 +679,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
             ydn[f] = (r == 0) ? edn_g[u][f] : v;
             xin[f] = (c == 0) ? gx[f] : xin[f];
           }
-          R o[NOUT], xo[NF], yo[NF];
+          R o[NOUT_ALL], xo[NF], yo[NF];
           if constexpr (S == LMDG_SCHEME_STD) {
             cell_std<R>(d, src_g[u], sig_g[u], xin, ydn, xo, yo, o, psi_g[u]);
           } else if constexpr (S == LMDG_SCHEME_LMDG) {
@@ -713,7 +716,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
         if constexpr (DIRECT) {
           // this wave's sums of the group's cells: lane group g writes rows g, g + 4, ...
           const int g4 = lane >> 4;
-          R* const pw = partr + (long long)(q * W + wv) * NOUT * nc;
+          R* const pw = partr + (long long)(q * W + wv) * NOUT_ALL * nc;
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const int c = t0 + tg + u - r;
@@ -783,7 +786,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
             if (w2 < W) acc += red[tt * red_tt + (w2 * NOUTP + m) * kRows + rr];
           const int i = sxi > 0 ? c : nx - 1 - c;
           const int jj = syi > 0 ? jr2 : ny - 1 - jr2;
-          partr[((long long)q * NOUT + m) * nc + (long long)jj * nx + i] = acc;
+          partr[((long long)q * NOUT_ALL + m) * nc + (long long)jj * nx + i] = acc;
         }
       }
     }
@@ -801,9 +804,23 @@ size_t lds_bytes(int cw, int W, int dslots, bool direct) {
   return (red + (size_t)2 * cw * kRows * NC + (size_t)cw * NF * dslots) * sizeof(R);
 }
 
+// The plain (no inflow data, default reconstruction) instantiations, with or without the
+// P_1 R rows of RLMDG.
+template <typename R, int S, int MAXW, bool DIRECT>
+void launch_plain(const SweepParams<R>& P, int grid, int W, size_t lds, hipStream_t st, bool p1r) {
+  if constexpr (S == LMDG_SCHEME_RLMDG) {
+    if (!p1r) {
+      hipLaunchKernelGGL((sweep2d_kernel<R, S, MAXW, DIRECT, false, false, false>), dim3(grid), dim3(64 * W), lds, st,
+                         P);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((sweep2d_kernel<R, S, MAXW, DIRECT>), dim3(grid), dim3(64 * W), lds, st, P);
+}
+
 template <typename R, int S>
 int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipStream_t st, bool defect, int qmask,
-                 bool psi_by_slot) {
+                 bool psi_by_slot, bool p1r) {
   SweepParams<R> P;
   P.nx = (int)h->n[0];
   P.ny = (int)h->n[1];
@@ -900,19 +917,19 @@ int launch_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipSt
       hipLaunchKernelGGL((sweep2d_kernel<R, S, kMaxWaves, false, true>), dim3(grid), dim3(64 * W), lds, st, P);
   } else if constexpr (sizeof(R) == 8) {
     if (direct && W <= 4) {
-      hipLaunchKernelGGL((sweep2d_kernel<R, S, 4, true>), dim3(grid), dim3(64 * W), lds, st, P);
+      launch_plain<R, S, 4, true>(P, grid, W, lds, st, p1r);
     } else if (direct) {
-      hipLaunchKernelGGL((sweep2d_kernel<R, S, kMaxWaves, true>), dim3(grid), dim3(64 * W), lds, st, P);
+      launch_plain<R, S, kMaxWaves, true>(P, grid, W, lds, st, p1r);
     } else if (W <= 4) {
-      hipLaunchKernelGGL((sweep2d_kernel<R, S, 4, false>), dim3(grid), dim3(64 * W), lds, st, P);
+      launch_plain<R, S, 4, false>(P, grid, W, lds, st, p1r);
     } else {
-      hipLaunchKernelGGL((sweep2d_kernel<R, S, kMaxWaves, false>), dim3(grid), dim3(64 * W), lds, st, P);
+      launch_plain<R, S, kMaxWaves, false>(P, grid, W, lds, st, p1r);
     }
   } else {
     if (W <= 4)
-      hipLaunchKernelGGL((sweep2d_kernel<R, S, 4, false>), dim3(grid), dim3(64 * W), lds, st, P);
+      launch_plain<R, S, 4, false>(P, grid, W, lds, st, p1r);
     else
-      hipLaunchKernelGGL((sweep2d_kernel<R, S, kMaxWaves, false>), dim3(grid), dim3(64 * W), lds, st, P);
+      launch_plain<R, S, kMaxWaves, false>(P, grid, W, lds, st, p1r);
   }
   if (ev_end) hipEventRecord(ev_end, st);
   h->epoch += 1;
@@ -932,20 +949,20 @@ int launch_sweep(lmdg_handle* h, int scheme, int prec, const double* x, bool use
   if (prec == LMDG_PREC_FP64) {
     switch (scheme) {
       case LMDG_SCHEME_STD:
-        return launch_typed<double, LMDG_SCHEME_STD>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
+        return launch_typed<double, LMDG_SCHEME_STD>(h, x, use_q, psi, st, defect, qmask, psi_by_slot, true);
       case LMDG_SCHEME_LMDG:
-        return launch_typed<double, LMDG_SCHEME_LMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
+        return launch_typed<double, LMDG_SCHEME_LMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot, true);
       default:
-        return launch_typed<double, LMDG_SCHEME_RLMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
+        return launch_typed<double, LMDG_SCHEME_RLMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot, p1r);
     }
   }
   switch (scheme) {
     case LMDG_SCHEME_STD:
-      return launch_typed<float, LMDG_SCHEME_STD>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
+      return launch_typed<float, LMDG_SCHEME_STD>(h, x, use_q, psi, st, defect, qmask, psi_by_slot, true);
     case LMDG_SCHEME_LMDG:
-      return launch_typed<float, LMDG_SCHEME_LMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
+      return launch_typed<float, LMDG_SCHEME_LMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot, true);
     default:
-      return launch_typed<float, LMDG_SCHEME_RLMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot);
+      return launch_typed<float, LMDG_SCHEME_RLMDG>(h, x, use_q, psi, st, defect, qmask, psi_by_slot, p1r);
   }
 }
 

@@ -209,9 +209,11 @@ def _random_problem(mesh, order=4, eps=0.3, seed=0, alpha=True):
                      eps, q=q, alpha=al)
 
 
-def test_sherman_morrison_reduced_route_std():
-    """eq-sndg-phi + eq-sndg-final-sweep reproduce the direct solve (Remark, Sec. 2.1.1)."""
-    prob = _random_problem(Mesh((6, 5)))
+@pytest.mark.parametrize("n", [(6, 5), (2, 3, 2)])
+def test_sherman_morrison_reduced_route_std(n):
+    """eq-sndg-phi + eq-sndg-final-sweep reproduce the direct solve (Remark, Sec. 2.1.1),
+    in 2D and 3D."""
+    prob = _random_problem(Mesh(n, (1.0,) * len(n)))
     psi = S.solve_std_direct(prob)
     psir, _ = S.StdReduced(prob).solve(tol=1e-14)
     assert np.abs(psi - psir).max() < 1e-11

@@ -238,7 +238,7 @@ __device__ __forceinline__ void cell_std3(const Dir3<R>& d, R wa, const int si[3
 // P1R: also the P_1 R rows of RLMDG (read by the recovery and by lmdg_sweep's output;
 // operator applications and right-hand sides skip them).  PSI: angular fluxes stored.
 template <typename R, int S, int MAXW, int CB, bool P1R, bool PSI>
-__global__ void __launch_bounds__(64 * MAXW) sweep3d_kernel(Sweep3Params<R> P) {
+__global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P) {
   constexpr int NOUT_ALL = Traits3<S>::NOUT;       // partial rows per cell (layout stride)
   constexpr int NOUT = (S == LMDG_SCHEME_RLMDG && !P1R) ? 7 : NOUT_ALL;  // rows produced
   constexpr int NOUTP = (NOUT + 3) & ~3;  // rows of red, padded to whole lane groups

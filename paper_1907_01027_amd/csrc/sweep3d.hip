@@ -295,7 +295,10 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
     for (int a = 0; a < 3; ++a) si[a] = ((o >> a) & 1) ? -1 : 1;
     const long long ro = (long long)rh * 8 + o;
     R* const partr = P.part + ro * NOUT_ALL * nc;
-    R* const xeb = P.xedge + ro * P.xedge_ostride;   // [nz][nstrips][nblk][16][ds][NF]
+    // [nz][nstrips][nblk][NF][ds][16]: a wave's lanes (16 rows x 4 slots) touch 256
+    // consecutive bytes per trace value (agent-scope accesses go through to memory, so a
+    // strided pattern would move whole lines for a quarter of their bytes)
+    R* const xeb = P.xedge + ro * P.xedge_ostride;
     R* const yeb = P.yedge + ro * P.yedge_ostride;   // [nz][nstrips][nx][ds][NF]
     unsigned long long* const progr = P.prog + ro * (long long)nstrips * nblk;
     double* const psir = PSI ? P.psi + rh * P.psi_rstride : nullptr;
@@ -412,9 +415,9 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
       {
         const int qx = p - (r >> LCB);
         const bool ok = b > 0 && row_ok && qx >= 0 && qx < nz;
-        const R* src = xeb + ((((long long)qx * nstrips + s) * nblk + (b - 1)) * kRows + r) * ds * NF + slot * NF;
+        const R* src = xeb + (((long long)qx * nstrips + s) * nblk + (b - 1)) * kRows * ds * NF + slot * kRows + r;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) xe[f] = ok ? load_agent(src + f) : R(0);
+        for (int f = 0; f < NF; ++f) xe[f] = ok ? load_agent(src + f * ds * kRows) : R(0);
       }
       if (p + 1 < nz) stage_load(p + 1);  // stays in flight through the steps
       lds_barrier();  // staged y traces visible; the loads above stay in flight
@@ -562,9 +565,9 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
       {
         const int qx = p - ((r + CB - 1) >> LCB);
         if (b + 1 < nblk && row_ok && qx >= 0 && qx < nz) {
-          R* dst = xeb + ((((long long)qx * nstrips + s) * nblk + b) * kRows + r) * ds * NF + slot * NF;
+          R* dst = xeb + (((long long)qx * nstrips + s) * nblk + b) * kRows * ds * NF + slot * kRows + r;
 #pragma unroll
-          for (int f = 0; f < NF; ++f) store_agent(dst + f, xsave[f]);
+          for (int f = 0; f < NF; ++f) store_agent(dst + f * ds * kRows, xsave[f]);
         }
       }
       // publish: planes below `done` are finished by every row of the block (their trace

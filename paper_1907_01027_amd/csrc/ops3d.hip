@@ -39,29 +39,30 @@ __device__ __forceinline__ double third_pow(int m) {
 // of u at xi_a = +-1 has tangential coefficients u[t] +- u[t | e_a] for the tangential
 // modes t (u[0] = 0: only slopes), and the face mass of mode t is A_a (1/3)^{#bits t}.
 // Mass term: eps sigma_a V (1/3)^{#bits m} u[m].
-__device__ __forceinline__ void b11_cell3(const double* x, long long nc, const Geo3& g, const int idx[3], long long p,
-                                          double absA, double y[8]) {
+// xs(m, a, side): slope moment m of the cell displaced by side (-1, 0, +1) along axis a;
+// called only for cells inside the mesh.
+template <typename XS>
+__device__ __forceinline__ void b11_cell3_acc(XS xs, const Geo3& g, const int idx[3], double absA, double y[8]) {
 #pragma unroll
-  for (int m = 1; m < 8; ++m) y[m] = absA * third_pow(m) * x[m * nc + p];
+  for (int m = 1; m < 8; ++m) y[m] = absA * third_pow(m) * xs(m, 0, 0);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int nb = 1 << a;
     const double A = g.A[a], cp = g.cp[a], cm = g.cm[a];
     const bool has_hi = idx[a] + 1 < g.n[a], has_lo = idx[a] > 0;
-    const long long ph = p + g.stride[a], pl = p - g.stride[a];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       if (t & nb) continue;
       const double fm = A * third_pow(t);
-      const double xt = t ? x[t * nc + p] : 0.0, xn = x[(t | nb) * nc + p];
+      const double xt = t ? xs(t, 0, 0) : 0.0, xn = xs(t | nb, 0, 0);
       {  // face at xi_a = +1: this cell is K-
-        const double un = has_hi ? (t ? x[t * nc + ph] : 0.0) - x[(t | nb) * nc + ph] : 0.0;
+        const double un = has_hi ? (t ? xs(t, a, 1) : 0.0) - xs(t | nb, a, 1) : 0.0;
         const double J = cp * (xt + xn) - cm * un;
         if (t) y[t] += fm * J;
         y[t | nb] += fm * J;
       }
       {  // face at xi_a = -1: this cell is K+
-        const double un = has_lo ? (t ? x[t * nc + pl] : 0.0) + x[(t | nb) * nc + pl] : 0.0;
+        const double un = has_lo ? (t ? xs(t, a, -1) : 0.0) + xs(t | nb, a, -1) : 0.0;
         const double J = cp * un - cm * (xt - xn);
         if (t) y[t] -= fm * J;
         y[t | nb] += fm * J;
@@ -71,6 +72,10 @@ __device__ __forceinline__ void b11_cell3(const double* x, long long nc, const G
     // together (register pressure of the fully unrolled form)
     __builtin_amdgcn_sched_barrier(0);
   }
+}
+__device__ __forceinline__ void b11_cell3(const double* x, long long nc, const Geo3& g, const int idx[3], long long p,
+                                          double absA, double y[8]) {
+  b11_cell3_acc([&](int m, int a, int side) { return x[m * nc + p + side * g.stride[a]]; }, g, idx, absA, y);
 }
 
 // G Sigma_0^T x_0 on one cell: the second block row applied to x_0 copied to every
@@ -91,9 +96,10 @@ __host__ __device__ constexpr int nb_index(int dx, int dy, int dz) {
                      : 21 + 2 * (dy < 0) + (dz < 0);
 }
 
-template <bool RLM>
-__device__ __forceinline__ void iso_g3(const double* __restrict__ x0, const Geo3& g, const int idx[3], long long p,
-                                       double absA, const OctMoments& om, double out[8]) {
+// x0at(dx, dy, dz): x_0 of the cell at offset (dx, dy, dz), called only inside the mesh.
+template <bool RLM, typename X0>
+__device__ __forceinline__ void iso_g3_acc(X0 x0at, const Geo3& g, const int idx[3], double absA,
+                                           const OctMoments& om, double out[8]) {
   constexpr int NNB = RLM ? 25 : 7;
   double nb[NNB];
 #pragma unroll
@@ -107,7 +113,7 @@ __device__ __forceinline__ void iso_g3(const double* __restrict__ x0, const Geo3
         double v = 0.0;
         const int ii = idx[0] + dx, jj = idx[1] + dy, kk = idx[2] + dz;
         if (ii >= 0 && ii < g.n[0] && jj >= 0 && jj < g.n[1] && kk >= 0 && kk < g.n[2])
-          v = x0[p + dx * g.stride[0] + dy * g.stride[1] + dz * g.stride[2]];
+          v = x0at(dx, dy, dz);
         nb[nb_index(dx, dy, dz)] = v;
       }
 #pragma unroll
@@ -169,27 +175,26 @@ __device__ __forceinline__ void iso_g3(const double* __restrict__ x0, const Geo3
         out[(1 << a) | (1 << b)] += (s[a] * g.A[a] * om.a[o][a] * (cba - c[b]) +
                                      s[b] * g.A[b] * om.a[o][b] * (cab - c[a])) / 3.0;
       }
+    // one octant at a time (register pressure)
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-// K x, right-hand side and recovery from the per-octant sweep sums (3D analogue of
-// combine_lm_kernel).  Sweep outputs s: [P_0, xi, eta, zeta rows (, xi eta, xi zeta,
-// eta zeta rows, P_1 R xi, eta, zeta)].
+// Right-hand side and recovery from the per-octant sweep sums (3D analogue of
+// combine_lm_kernel; K x is apply3_tiled_kernel below).  Sweep outputs s: [P_0, xi, eta,
+// zeta rows (, xi eta, xi zeta, eta zeta rows, P_1 R xi, eta, zeta)].
 template <typename R, bool RLM, int MODE>
-__global__ void __launch_bounds__(kBlock3) combine3_kernel(int nr, Geo3 g, OctMoments om, const double* __restrict__ x_all,
-                                const R* __restrict__ part_all, const double* __restrict__ absA,
-                                double* __restrict__ out_all) {
+__global__ void __launch_bounds__(kBlock3) combine3_kernel(int nr, long long nc, const double* __restrict__ x_all,
+                                                          const R* __restrict__ part_all, double* __restrict__ out_all) {
+  static_assert(MODE == kRhs || MODE == kRecover, "K x is apply3_tiled_kernel");
   constexpr int NOUT = RLM ? 10 : 4;
-  const long long nc = (long long)g.n[0] * g.n[1] * g.n[2];
   for (long long pr = blockIdx.x * (long long)blockDim.x + threadIdx.x; pr < nr * nc;
        pr += (long long)gridDim.x * blockDim.x) {
     const long long rh = pr / nc, p = pr - rh * nc;
-    const double* x = x_all ? x_all + rh * 8 * nc : nullptr;
     const R* part = part_all + rh * 8 * NOUT * nc;
     double* out = out_all + rh * 8 * nc;
-    // rows the mode reads: operator rows (P_0 and the slope rows) for K x and the
-    // right-hand side, P_0 and the P_1 R rows for the recovery (RLMDG sweeps produce
-    // the P_1 R rows only for the latter)
+    // rows the mode reads: P_0 and the slope rows for the right-hand side, P_0 and the
+    // P_1 R rows for the recovery (RLMDG sweeps produce the P_1 R rows only for the latter)
     double s[NOUT];
 #pragma unroll
     for (int m = 0; m < NOUT; ++m) {
@@ -201,42 +206,173 @@ __global__ void __launch_bounds__(kBlock3) combine3_kernel(int nr, Geo3 g, OctMo
       }
       s[m] = acc;
     }
-    // the sweep's slope rows already hold G Psi (Sigma M_1 P_1 R taken per direction)
-    double gr[8];
-    gr[0] = 0.0;
-    gr[1] = s[1];
-    gr[2] = s[2];
-    gr[4] = s[3];
-    gr[3] = RLM ? s[4] : 0.0;
-    gr[5] = RLM ? s[5] : 0.0;
-    gr[6] = RLM ? s[6] : 0.0;
-    gr[7] = 0.0;
-    const int idx[3] = {(int)(p % g.n[0]), (int)((p / g.n[0]) % g.n[1]), (int)(p / ((long long)g.n[0] * g.n[1]))};
-    if constexpr (MODE == kApply || MODE == kApplyDefect) {
-      double y[8], gi[8];
-      __builtin_amdgcn_sched_barrier(0);
-      b11_cell3(x, nc, g, idx, p, absA[p], y);
-      if constexpr (MODE == kApply) {
-        out[p] = x[p] - s[0];
-#pragma unroll
-        for (int m = 1; m < 8; ++m) out[m * nc + p] = y[m] - gr[m];
-      } else {
-        iso_g3<RLM>(x, g, idx, p, absA[p], om, gi);
-        out[p] = s[0];
-#pragma unroll
-        for (int m = 1; m < 8; ++m) out[m * nc + p] = y[m] - gi[m] + gr[m];
-      }
-    } else if constexpr (MODE == kRhs) {
-      out[p] = s[0];
-      for (int m = 1; m < 8; ++m) out[m * nc + p] = gr[m];
+    out[p] = s[0];
+    if constexpr (MODE == kRhs) {
+      // the sweep's slope rows already hold G Psi (Sigma M_1 P_1 R taken per direction)
+      out[1 * nc + p] = s[1];
+      out[2 * nc + p] = s[2];
+      out[4 * nc + p] = s[3];
+      out[3 * nc + p] = RLM ? s[4] : 0.0;
+      out[5 * nc + p] = RLM ? s[5] : 0.0;
+      out[6 * nc + p] = RLM ? s[6] : 0.0;
+      out[7 * nc + p] = 0.0;
     } else {  // recovery: Phi_1 = -X_1 + P_1 R Psi_0
-      out[p] = s[0];
+      const double* x = x_all + rh * 8 * nc;
       for (int m = 1; m < 8; ++m) {
         double v = -x[m * nc + p];
         if (RLM && (m == 1 || m == 2 || m == 4)) v += s[m == 1 ? 7 : (m == 2 ? 8 : 9)];
         out[m * nc + p] = v;
       }
     }
+  }
+}
+
+// K x (modes kApply and kApplyDefect) with the x stencils read from LDS.  A workgroup
+// owns a tile of kTX x kTY columns (one cell per thread and plane) and marches through
+// kZC planes of one right-hand side.  Per plane k it stages x_0 of planes k - 1, k, k + 1
+// with a halo of two cells in x and y (a ring of three planes) and the slope moments of
+// plane k with a halo of one; each thread keeps its own column's x_0 at k +- 2 and slopes
+// at k +- 1 in registers.  b11_cell3_acc and iso_g3_acc read the staged values through
+// accessors; the octant partials are streamed as in combine3_kernel.
+constexpr int kTX = 64, kTY = 4, kZC = 16;
+template <typename R, bool RLM, int MODE>
+__global__ void __launch_bounds__(kTX * kTY) apply3_tiled_kernel(int nr, Geo3 g, OctMoments om,
+                                                                 const double* __restrict__ x_all,
+                                                                 const R* __restrict__ part_all,
+                                                                 const double* __restrict__ absA,
+                                                                 double* __restrict__ out_all) {
+  constexpr int NOUT = RLM ? 10 : 4;
+  constexpr int H = 2;                                 // x_0 halo
+  constexpr int PX = kTX + 2 * H, PY = kTY + 2 * H;    // x_0 plane tile
+  constexpr int SX = kTX + 2, SY = kTY + 2;            // slope plane tile
+  constexpr int NT = kTX * kTY;
+  __shared__ double x0s[3][PY][PX];
+  __shared__ double sls[7][SY][SX];
+  // the octant moments are read from LDS inside the plane loop: its barriers keep the
+  // compiler from hoisting the per-octant products out of the loop into registers
+  __shared__ OctMoments oms;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const long long nxy = (long long)nx * ny, nc = nxy * nz;
+  const int ntx = (nx + kTX - 1) / kTX, nty = (ny + kTY - 1) / kTY, ntz = (nz + kZC - 1) / kZC;
+  // tiles in (x, y, z chunk, right-hand side) order.  Workgroups are dispatched to the
+  // eight XCDs in turn and each XCD has its own L2: consecutive tiles (which share
+  // halos) go to one XCD
+  const int G = gridDim.x, b = blockIdx.x;
+  const int lb = (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3);
+  if (lb >= ntx * nty * ntz * nr) return;
+  int rest = lb;
+  const int bx = rest % ntx;
+  rest /= ntx;
+  const int by = rest % nty;
+  rest /= nty;
+  const int bz = rest % ntz;
+  const int rh = rest / ntz;
+  const int tid = threadIdx.x, tx = tid % kTX, ty = tid / kTX;
+  const int i0 = bx * kTX, j0 = by * kTY, k0 = bz * kZC, k1 = min(nz, k0 + kZC);
+  const int i = i0 + tx, j = j0 + ty;
+  const bool act = i < nx && j < ny;
+  const double* x = x_all + (long long)rh * 8 * nc;
+  const R* part = part_all + (long long)rh * 8 * NOUT * nc;
+  double* out = out_all + (long long)rh * 8 * nc;
+  const long long col = (long long)j * nx + i;  // own column (valid where act)
+
+  // x_0 of plane kk (zeros outside the mesh) into ring slot kk mod 3
+  auto stage_x0 = [&](int kk) {
+    double(*dst)[PX] = x0s[(kk + 3) % 3];
+    for (int e = tid; e < PY * PX; e += NT) {
+      const int hy = e / PX, hx = e - hy * PX;
+      const int ii = i0 - H + hx, jj = j0 - H + hy;
+      double v = 0.0;
+      if (kk >= 0 && kk < nz && ii >= 0 && ii < nx && jj >= 0 && jj < ny) v = x[kk * nxy + (long long)jj * nx + ii];
+      dst[hy][hx] = v;
+    }
+  };
+  auto stage_slopes = [&](int kk) {
+    for (int e = tid; e < 7 * SY * SX; e += NT) {
+      const int m = e / (SY * SX), r2 = e - m * (SY * SX);
+      const int hy = r2 / SX, hx = r2 - hy * SX;
+      const int ii = i0 - 1 + hx, jj = j0 - 1 + hy;
+      double v = 0.0;
+      if (ii >= 0 && ii < nx && jj >= 0 && jj < ny) v = x[(m + 1) * nc + kk * nxy + (long long)jj * nx + ii];
+      sls[m][hy][hx] = v;
+    }
+  };
+  if (tid < 8) {
+    oms.w[tid] = om.w[tid];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) oms.a[tid][a] = om.a[tid][a];
+  }
+  double x0m2 = 0.0, x0p2 = 0.0, slm1[7], slp1[7];
+#pragma unroll
+  for (int m = 0; m < 7; ++m) slm1[m] = slp1[m] = 0.0;
+  if (act && k0 >= 2) x0m2 = x[(k0 - 2) * nxy + col];
+  if (act && k0 >= 1) {
+#pragma unroll
+    for (int m = 0; m < 7; ++m) slm1[m] = x[(m + 1) * nc + (k0 - 1) * nxy + col];
+  }
+  stage_x0(k0 - 1);
+  stage_x0(k0);
+  for (int k = k0; k < k1; ++k) {
+    const long long p = k * nxy + col;
+    // octant sums of the rows K x reads (the loads stay in flight through the staging)
+    double sv[7];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      double acc = 0;
+      if (act && (RLM || m < 4)) {
+#pragma unroll
+        for (int o = 0; o < 8; ++o) acc += (double)part[((long long)o * NOUT + m) * nc + p];
+      }
+      sv[m] = acc;
+    }
+    stage_x0(k + 1);
+    stage_slopes(k);
+    x0p2 = (act && k + 2 < nz) ? x[(k + 2) * nxy + col] : 0.0;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) slp1[m] = (act && k + 1 < nz) ? x[(m + 1) * nc + (k + 1) * nxy + col] : 0.0;
+    __syncthreads();
+    if (act) {
+      const int idx[3] = {i, j, k};
+      const int c0 = (k + 3) % 3, cm1 = (k + 2) % 3, cp1 = (k + 4) % 3;
+      auto xs = [&](int m, int a, int side) -> double {
+        if (a == 2 && side != 0) return side > 0 ? slp1[m - 1] : slm1[m - 1];
+        const int dx = a == 0 ? side : 0, dy = a == 1 ? side : 0;
+        return sls[m - 1][ty + 1 + dy][tx + 1 + dx];
+      };
+      auto x0at = [&](int dx, int dy, int dz) -> double {
+        if (dz == 2) return x0p2;
+        if (dz == -2) return x0m2;
+        const int sl = dz == 0 ? c0 : (dz > 0 ? cp1 : cm1);
+        return x0s[sl][ty + H + dy][tx + H + dx];
+      };
+      double y[8];
+      b11_cell3_acc(xs, g, idx, absA[p], y);
+      double gr[8];
+      gr[0] = 0.0;
+      gr[1] = sv[1];
+      gr[2] = sv[2];
+      gr[4] = sv[3];
+      gr[3] = RLM ? sv[4] : 0.0;
+      gr[5] = RLM ? sv[5] : 0.0;
+      gr[6] = RLM ? sv[6] : 0.0;
+      gr[7] = 0.0;
+      if constexpr (MODE == kApply) {
+        out[p] = x0at(0, 0, 0) - sv[0];
+#pragma unroll
+        for (int m = 1; m < 8; ++m) out[m * nc + p] = y[m] - gr[m];
+      } else {
+        double gi[8];
+        iso_g3_acc<RLM>(x0at, g, idx, absA[p], oms, gi);
+        out[p] = sv[0];
+#pragma unroll
+        for (int m = 1; m < 8; ++m) out[m * nc + p] = y[m] - gi[m] + gr[m];
+      }
+      // registers for the next plane: x_0 at k - 1 and the slopes at k
+      x0m2 = x0s[cm1][ty + H][tx + H];
+#pragma unroll
+      for (int m = 0; m < 7; ++m) slm1[m] = sls[m][ty + 1][tx + 1];
+    }
+    __syncthreads();
   }
 }
 
@@ -306,6 +442,9 @@ void launch_combine3(lmdg_handle* h, int scheme, int prec, int mode, const doubl
   }
   const int nr = h->n_rhs;
   const int grid = grid3(h->ncell * nr);
+  const long long tiles = (long long)((g.n[0] + kTX - 1) / kTX) * ((g.n[1] + kTY - 1) / kTY) *
+                          ((g.n[2] + kZC - 1) / kZC) * nr;
+  const int grid_t = (int)(tiles < 8 ? tiles : (tiles + 7) / 8 * 8);
   const bool rlm = scheme == LMDG_SCHEME_RLMDG;
   auto go = [&](auto r_tag, auto rlm_tag) {
     using R = decltype(r_tag);
@@ -313,20 +452,20 @@ void launch_combine3(lmdg_handle* h, int scheme, int prec, int mode, const doubl
     const R* part = (const R*)h->ws.part;
     switch (mode) {
       case kApply:
-        hipLaunchKernelGGL((combine3_kernel<R, RLM, kApply>), dim3(grid), dim3(kBlock3), 0, st, nr, g, om, x, part,
-                           h->d_absA, out);
-        break;
-      case kApplyDefect:
-        hipLaunchKernelGGL((combine3_kernel<R, RLM, kApplyDefect>), dim3(grid), dim3(kBlock3), 0, st, nr, g, om, x,
+        hipLaunchKernelGGL((apply3_tiled_kernel<R, RLM, kApply>), dim3(grid_t), dim3(kTX * kTY), 0, st, nr, g, om, x,
                            part, h->d_absA, out);
         break;
+      case kApplyDefect:
+        hipLaunchKernelGGL((apply3_tiled_kernel<R, RLM, kApplyDefect>), dim3(grid_t), dim3(kTX * kTY), 0, st, nr, g,
+                           om, x, part, h->d_absA, out);
+        break;
       case kRhs:
-        hipLaunchKernelGGL((combine3_kernel<R, RLM, kRhs>), dim3(grid), dim3(kBlock3), 0, st, nr, g, om, x, part,
-                           h->d_absA, out);
+        hipLaunchKernelGGL((combine3_kernel<R, RLM, kRhs>), dim3(grid), dim3(kBlock3), 0, st, nr, h->ncell, x, part,
+                           out);
         break;
       default:
-        hipLaunchKernelGGL((combine3_kernel<R, RLM, kRecover>), dim3(grid), dim3(kBlock3), 0, st, nr, g, om, x, part,
-                           h->d_absA, out);
+        hipLaunchKernelGGL((combine3_kernel<R, RLM, kRecover>), dim3(grid), dim3(kBlock3), 0, st, nr, h->ncell, x,
+                           part, out);
     }
   };
   if (prec == LMDG_PREC_FP64) {

@@ -121,6 +121,32 @@ def test_apply_and_rhs_3d(shape, order, scheme):
 
 
 @pytest.mark.parametrize("scheme", ["lmdg", "rlmdg"])
+def test_apply_3d_across_combine_tiles(scheme):
+    """K x on a mesh that spans two column tiles along x (64 + 1), two along y (4 + 1) and
+    two chunks of planes (16 + 1) of the combine kernel, whose stencils read x from
+    staged tiles with halos: FP64 at 1e-12 and FP32 at 2e-5 against the oracle."""
+    shape = (65, 5, 17)
+    print(f"case 3d apply tiles {scheme} {shape} S4", flush=True)
+    case = Case3(shape, 4, eps=0.02)
+    s = case.solver()
+    nc = case.ncell
+    x = np.random.default_rng(4).normal(size=8 * nc)
+    red = S.LowMemoryReduced(case.prob, scheme == "rlmdg")
+    ref_y = lm_to_abi(red.apply(abi_to_lm(x, nc)), nc)
+    y = torch.zeros(8 * nc, dtype=torch.float64, device=DEV)
+    try:
+        lmdg.lmdg_apply(s.h, scheme, "fp64", T(x), y)
+        e64 = rel_err(N(y), ref_y)
+        lmdg.lmdg_apply(s.h, scheme, "fp32", T(x), y)
+        e32 = rel_err(N(y), ref_y)
+    finally:
+        s.close()
+    print(f"FP64 {e64:.2e}, FP32 {e32:.2e}")
+    assert e64 < 1e-12
+    assert e32 < 2e-5
+
+
+@pytest.mark.parametrize("scheme", ["lmdg", "rlmdg"])
 @pytest.mark.parametrize("mode", ["fp64", "mixed"])
 def test_solve_3d_against_direct(scheme, mode):
     print(f"case 3d solve {scheme} {mode}", flush=True)

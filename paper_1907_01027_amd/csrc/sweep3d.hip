@@ -17,7 +17,9 @@
 //             of CB, and step u of a period reads and rewrites register slot u.
 // Row r trails row 0 by r steps, so in period p the rows cover planes p - L .. p with
 // L = ceil(15 / CB); plane q is complete after period q + L.  Per period the item stages
-// the coefficients of plane p + 1 in LDS (a ring of L + 2 plane buffers), sums its outputs
+// the coefficients of plane p + 1 in LDS (a ring of L + 2 plane buffers whose slot for a
+// cell is its sequence index lambda modulo (L + 2) CB: one add and a mask per step where
+// that is a power of two, an add, compare and select otherwise), sums its outputs
 // over the slots and waves of the octant, and publishes how many planes it has completed;
 // it waits for (s, b - 1) and (s - 1, b) to have completed plane p before period p.
 //
@@ -72,6 +74,8 @@ struct Dir3 {
 };
 
 __host__ __device__ constexpr int popc3(int m) { return (m & 1) + ((m >> 1) & 1) + ((m >> 2) & 1); }
+// staged plane buffers of the sweep: planes p - L .. p + 1
+__host__ __device__ constexpr int nbuf3(int L) { return L + 2; }
 // (1/3)^(number of linear factors of mode m): the L2 norm squared of b_m on [-1,1]^3 / 8
 template <typename R>
 __device__ __forceinline__ constexpr R mass3(int m) {
@@ -249,7 +253,8 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
   static_assert((1 << LCB) == CB, "CB is 4, 8 or 16");
   constexpr int CB16 = CB * kRows;
   constexpr int L = (kRows - 1 + CB - 1) / CB;  // periods by which row 15 trails row 0
-  constexpr int NBUF = L + 2;                   // staged planes: p - L .. p and p + 1
+  constexpr int NBUF = nbuf3(L);                // staged planes: p - L .. p and p + 1
+  constexpr int RING = NBUF * CB;               // staged cells per row (lambda modulo RING)
   constexpr int MAXC = (CB16 + 63) / 64;        // staged cells per thread (one wave at least)
   constexpr bool RLM = S == LMDG_SCHEME_RLMDG;
   constexpr bool STDS = S == LMDG_SCHEME_STD;
@@ -267,14 +272,14 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
   const long long nxy = (long long)nx * ny;
   const int ds = P.dslots;
   const double A[3] = {P.h[1] * P.h[2], P.h[0] * P.h[2], P.h[0] * P.h[1]};
-  // LDS: red [CB][W][NOUTP][16] (+1 pad per step) | cbuf [NBUF][NK][CB][16] | eds [CB][ds][NF]
+  // LDS: red [CB][W][NOUTP][16] (+1 pad per step) | cbuf [RING][NK][16] | eds [CB][ds][NF]
   //      | ybuf [CB][ds][NF] (the top row's y traces of the period, written out after the steps)
   R* red = reinterpret_cast<R*>(smem_raw);
   // one step's block of red holds W x NOUTP x 16 values plus one pad, so that the
   // reduction's reads of consecutive steps fall in different banks
   const int red_tt = W * NOUTP * kRows + 1;
   R* cbuf = red + (size_t)CB * red_tt;
-  R* eds = cbuf + (size_t)NBUF * NK * CB16;
+  R* eds = cbuf + (size_t)RING * NK * kRows;
   R* ybuf = eds + (size_t)CB * ds * NF;
 
   for (;;) {
@@ -360,9 +365,9 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
         const int e = tid + mc * (int)blockDim.x;
         if (e < CB16) {
           const int cl = e & (CB - 1), rr = e >> LCB;
-          R* dst = cbuf + (size_t)buf * NK * CB16 + cl * kRows + rr;
+          R* dst = cbuf + (size_t)(buf * CB + cl) * NK * kRows + rr;
 #pragma unroll
-          for (int k = 0; k < NK; ++k) dst[k * CB16] = stg[mc][k];
+          for (int k = 0; k < NK; ++k) dst[k * kRows] = stg[mc][k];
         }
       }
     };
@@ -376,8 +381,8 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
     }
     // plane buffers other than the first hold neutral values until staged (rows that
     // trail into planes before the first read them)
-    for (int e = CB16 * NK + tid; e < NBUF * NK * CB16; e += blockDim.x)
-      cbuf[e] = ((e / CB16) % NK == 0) ? R(1) : R(0);
+    for (int e = CB * NK * kRows + tid; e < RING * NK * kRows; e += blockDim.x)
+      cbuf[e] = ((e / kRows) % NK == 0) ? R(1) : R(0);
     stage_load(0);
     stage_store(0);
     int pb = 0;  // p % NBUF
@@ -423,129 +428,158 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
       lds_barrier();  // staged y traces visible; the loads above stay in flight
 
       // the row index passes through an empty asm once per period, so that the per-step
-      // offsets derived from it are recomputed here instead of being held in registers
+      // values derived from it are recomputed here instead of being held in registers
       // across the whole item
       int rp = r;
       asm volatile("" : "+v"(rp));
+      const int lbase = p * CB - rp;    // the lane's sequence index at step 0
+      const int rc = rp & (CB - 1);     // step at which its cell is in the block's first column
+      const int slot0 = (lbase + RING) % RING;  // its staged slot at step 0 (lbase > -RING)
+      // Cells outside the mesh (planes before 0 or from nz on, ragged rows and columns)
+      // are computed like the others from the neutral staged values; their rows and
+      // traces are never read.  Before plane 0 every source and inflow is zero, so those
+      // cells hand zero traces on, and plane 0 finds its zero z-inflow in the registers.
 #pragma unroll
       for (int u = 0; u < CB; ++u) {
-        const int dd = u - rp;
-        const int qo = dd >> LCB;  // 0, -1, .. -L: the plane relative to p
-        const int cl = dd & (CB - 1);
-        const int q = p + qo;
-        const int c = c0 + cl;
-        const bool act = row_ok && q >= 0 && q < nz && c < nx;
-        int qb = pb + qo;
-        if (qb < 0) qb += NBUF;
-        const R* cf = cbuf + (size_t)qb * NK * CB16 + cl * kRows + r;
-        R xi[NF], yd[NF], zi[NF];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          xi[f] = (cl == 0) ? xe[f] : xin[f];
-          const R v = shr1(yprev[f]);
-          yd[f] = (r == 0) ? eds[(u * ds + slot) * NF + f] : v;
-          zi[f] = (q <= 0) ? R(0) : zreg[u][f];
-        }
-        R o[NOUT_ALL], xo[NF], yo[NF], zo[NF];
-        // the weight of an inactive lane-step is zero, so its (finite) values add nothing
-        const R wa = act ? d.w : R(0);
-        if constexpr (STDS) {
-          R src[8], cm[8];
-#pragma unroll
-          for (int m = 0; m < 8; ++m) src[m] = cf[(1 + m) * CB16];
-          cell_std3<R>(d, wa, si, src, cf[0], xi, yd, zi, xo, yo, zo, o, cm);
-          if (PSI && act && d.idx >= 0) {
-            const int i = si[0] > 0 ? c : nx - 1 - c;
-            const int kk = si[2] > 0 ? q : nz - 1 - q;
-            const long long cell = (long long)kk * nxy + (long long)j * nx + i;
-#pragma unroll
-            for (int m = 0; m < 8; ++m) psir[((long long)d.idx * 8 + m) * nc + cell] = (double)cm[m];
-          }
-        } else {
-          const R sig = cf[0];
-          const R src = cf[CB16] + d.ao[0] * cf[2 * CB16] + d.ao[1] * cf[3 * CB16] + d.ao[2] * cf[4 * CB16];
-          R psi;
-          if constexpr (!RLM) {
-            const R inv = recip(sig + d.aA[0] + d.aA[1] + d.aA[2]);
-            psi = (src + d.aA[0] * xi[0] + d.aA[1] * yd[0] + d.aA[2] * zi[0]) * inv;
-            xo[0] = yo[0] = zo[0] = psi;
-            o[0] = wa * psi;
-            o[1] = wa * d.oA[0] * (xi[0] - psi);
-            o[2] = wa * d.oA[1] * (yd[0] - psi);
-            o[3] = wa * d.oA[2] * (zi[0] - psi);
+          const int lam = lbase + u;                    // sequence index: plane * CB + column
+          const bool first = rc == u;                   // column 0 of the block
+          const bool last = rc == ((u + 1) & (CB - 1)); // column CB - 1 of the block
+          const bool plane0 = (unsigned)lam < (unsigned)CB;
+          int sl;
+          if constexpr ((RING & (RING - 1)) == 0) {
+            sl = lam & (RING - 1);
           } else {
-            // traces per axis: [outflow face value, two tangential slopes, cell value];
-            // tangential slopes in axis order: x carries (c_y, c_z), y (c_x, c_z), z (c_x, c_y)
-            const R kx = (c == 0) ? R(1) : R(0.5);
-            const R kz = (q == 0) ? R(1) : R(0.5);
-            const R third = R(1) / R(3);
-            const R inv = recip(sig + d.aA[0] * (R(1) + kx) + d.aA[1] * (R(1) + ky) + d.aA[2] * (R(1) + kz));
-            psi = (src + d.aA[0] * (xi[0] + kx * xi[3]) + d.aA[1] * (yd[0] + ky * yd[3]) +
-                   d.aA[2] * (zi[0] + kz * zi[3])) *
-                  inv;
-            const R cx = R(si[0]) * kx * (psi - xi[3]);
-            const R cy = R(si[1]) * ky * (psi - yd[3]);
-            const R cz = R(si[2]) * kz * (psi - zi[3]);
-            xo[0] = psi + kx * (psi - xi[3]);
-            xo[1] = cy;
-            xo[2] = cz;
-            xo[3] = psi;
-            yo[0] = psi + ky * (psi - yd[3]);
-            yo[1] = cx;
-            yo[2] = cz;
-            yo[3] = psi;
-            zo[0] = psi + kz * (psi - zi[3]);
-            zo[1] = cx;
-            zo[2] = cy;
-            zo[3] = psi;
-            // eps sigma_a V / 3: sigma_t V / 3 of L_11 R minus (sigma_s/eps) V / 3 of M_1 P_1 R
-            const R sV3 = cf[5 * CB16];
-            o[0] = wa * psi;
-            o[1] = wa * (d.oA[0] * (xi[0] - psi) + (sV3 + d.aA[0]) * cx +
-                         third * (d.aA[1] * (cx - yd[1]) + d.aA[2] * (cx - zi[1])));
-            o[2] = wa * (d.oA[1] * (yd[0] - psi) + (sV3 + d.aA[1]) * cy +
-                         third * (d.aA[0] * (cy - xi[1]) + d.aA[2] * (cy - zi[2])));
-            o[3] = wa * (d.oA[2] * (zi[0] - psi) + (sV3 + d.aA[2]) * cz +
-                         third * (d.aA[0] * (cz - xi[2]) + d.aA[1] * (cz - yd[2])));
-            o[4] = wa * third * (d.oA[0] * (xi[1] - cy) + d.oA[1] * (yd[1] - cx));
-            o[5] = wa * third * (d.oA[0] * (xi[2] - cz) + d.oA[2] * (zi[1] - cx));
-            o[6] = wa * third * (d.oA[1] * (yd[2] - cz) + d.oA[2] * (zi[2] - cy));
-            if constexpr (P1R) {
-              o[7] = wa * cx;
-              o[8] = wa * cy;
-              o[9] = wa * cz;
+            sl = slot0 + u;
+            if (sl >= RING) sl -= RING;
+          }
+          const R* cf = cbuf + (size_t)sl * (NK * kRows) + r;
+          // y-inflow: the row below (DPP row shift); row 0 takes the y-outflow of strip
+          // s - 1.  FP32: every lane reads the staged trace and the shift keeps it in row 0;
+          // FP64: row 0 alone reads it (four doubles per lane and step cost more LDS
+          // bandwidth than the select saves)
+          R xi[NF], yd[NF], zi[NF];
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            xi[f] = first ? xe[f] : xin[f];
+            if constexpr (sizeof(R) == 4) {
+              yd[f] = shr1_or(yprev[f], eds[(u * ds + slot) * NF + f]);
+            } else {
+              const R v = shr1(yprev[f]);
+              yd[f] = (r == 0) ? eds[(u * ds + slot) * NF + f] : v;
+            }
+            zi[f] = zreg[u][f];
+          }
+          R o[NOUT_ALL], xo[NF], yo[NF], zo[NF];
+          // angular fluxes are stored only for cells inside the mesh
+          auto in_mesh = [&](int& q_out, int& c_out) {
+            q_out = lam >> LCB;
+            c_out = c0 + (lam & (CB - 1));
+            return row_ok && q_out >= 0 && q_out < nz && c_out < nx;
+          };
+          if constexpr (STDS) {
+            R src[8], cm[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) src[m] = cf[(1 + m) * kRows];
+            cell_std3<R>(d, d.w, si, src, cf[0], xi, yd, zi, xo, yo, zo, o, cm);
+            if constexpr (PSI) {
+              int q, c;
+              if (in_mesh(q, c) && d.idx >= 0) {
+                const int i = si[0] > 0 ? c : nx - 1 - c;
+                const int kk = si[2] > 0 ? q : nz - 1 - q;
+                const long long cell = (long long)kk * nxy + (long long)j * nx + i;
+#pragma unroll
+                for (int m = 0; m < 8; ++m) psir[((long long)d.idx * 8 + m) * nc + cell] = (double)cm[m];
+              }
+            }
+          } else {
+            const R sig = cf[0];
+            const R src = cf[kRows] + d.ao[0] * cf[2 * kRows] + d.ao[1] * cf[3 * kRows] + d.ao[2] * cf[4 * kRows];
+            const R w = d.w;
+            R psi;
+            if constexpr (!RLM) {
+              const R inv = recip(sig + d.aA[0] + d.aA[1] + d.aA[2]);
+              psi = (src + d.aA[0] * xi[0] + d.aA[1] * yd[0] + d.aA[2] * zi[0]) * inv;
+              xo[0] = yo[0] = zo[0] = psi;
+              o[0] = w * psi;
+              o[1] = w * d.oA[0] * (xi[0] - psi);
+              o[2] = w * d.oA[1] * (yd[0] - psi);
+              o[3] = w * d.oA[2] * (zi[0] - psi);
+            } else {
+              // traces per axis: [outflow face value, two tangential slopes, cell value];
+              // tangential slopes in axis order: x carries (c_y, c_z), y (c_x, c_z), z (c_x, c_y)
+              const R kx = (b == 0 && first) ? R(1) : R(0.5);
+              const R kz = plane0 ? R(1) : R(0.5);
+              const R third = R(1) / R(3);
+              const R inv = recip(sig + d.aA[0] * (R(1) + kx) + d.aA[1] * (R(1) + ky) + d.aA[2] * (R(1) + kz));
+              psi = (src + d.aA[0] * (xi[0] + kx * xi[3]) + d.aA[1] * (yd[0] + ky * yd[3]) +
+                     d.aA[2] * (zi[0] + kz * zi[3])) *
+                    inv;
+              const R cx = R(si[0]) * kx * (psi - xi[3]);
+              const R cy = R(si[1]) * ky * (psi - yd[3]);
+              const R cz = R(si[2]) * kz * (psi - zi[3]);
+              xo[0] = psi + kx * (psi - xi[3]);
+              xo[1] = cy;
+              xo[2] = cz;
+              xo[3] = psi;
+              yo[0] = psi + ky * (psi - yd[3]);
+              yo[1] = cx;
+              yo[2] = cz;
+              yo[3] = psi;
+              zo[0] = psi + kz * (psi - zi[3]);
+              zo[1] = cx;
+              zo[2] = cy;
+              zo[3] = psi;
+              // eps sigma_a V / 3: sigma_t V / 3 of L_11 R minus (sigma_s/eps) V / 3 of M_1 P_1 R
+              const R sV3 = cf[5 * kRows];
+              o[0] = w * psi;
+              o[1] = w * (d.oA[0] * (xi[0] - psi) + (sV3 + d.aA[0]) * cx +
+                          third * (d.aA[1] * (cx - yd[1]) + d.aA[2] * (cx - zi[1])));
+              o[2] = w * (d.oA[1] * (yd[0] - psi) + (sV3 + d.aA[1]) * cy +
+                          third * (d.aA[0] * (cy - xi[1]) + d.aA[2] * (cy - zi[2])));
+              o[3] = w * (d.oA[2] * (zi[0] - psi) + (sV3 + d.aA[2]) * cz +
+                          third * (d.aA[0] * (cz - xi[2]) + d.aA[1] * (cz - yd[2])));
+              o[4] = w * third * (d.oA[0] * (xi[1] - cy) + d.oA[1] * (yd[1] - cx));
+              o[5] = w * third * (d.oA[0] * (xi[2] - cz) + d.oA[2] * (zi[1] - cx));
+              o[6] = w * third * (d.oA[1] * (yd[2] - cz) + d.oA[2] * (zi[2] - cy));
+              if constexpr (P1R) {
+                o[7] = w * cx;
+                o[8] = w * cy;
+                o[9] = w * cz;
+              }
+            }
+            if constexpr (PSI) {
+              int q, c;
+              if (in_mesh(q, c) && d.idx >= 0) {
+                const int i = si[0] > 0 ? c : nx - 1 - c;
+                const int kk = si[2] > 0 ? q : nz - 1 - q;
+                psir[(long long)d.idx * nc + (long long)kk * nxy + (long long)j * nx + i] = (double)psi;
+              }
             }
           }
-          if (PSI && act && d.idx >= 0) {
-            const int i = si[0] > 0 ? c : nx - 1 - c;
-            const int kk = si[2] > 0 ? q : nz - 1 - q;
-            psir[(long long)d.idx * nc + (long long)kk * nxy + (long long)j * nx + i] = (double)psi;
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            xin[f] = xo[f];
+            yprev[f] = yo[f];
+            zreg[u][f] = zo[f];
+            xsave[f] = last ? xo[f] : xsave[f];
           }
-        }
+          // top row: y traces for strip s + 1, staged in LDS for one store pass per period
+          if (r == kRows - 1) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          xin[f] = xo[f];
-          yprev[f] = yo[f];
-          zreg[u][f] = zo[f];
-          xsave[f] = (cl == CB - 1) ? xo[f] : xsave[f];
-        }
-        // top row: y traces for strip s + 1, staged in LDS for one store pass per period
-        if (r == kRows - 1) {
+            for (int f = 0; f < NF; ++f) ybuf[(u * ds + slot) * NF + f] = yo[f];
+          }
+          // sums over the four direction slots of the wave, four rows at a time: lane
+          // group g receives row m0 + g
+          R om[NOUTP];
 #pragma unroll
-          for (int f = 0; f < NF; ++f) ybuf[(u * ds + slot) * NF + f] = yo[f];
-        }
-        // sums over the four direction slots of the wave, four rows at a time: lane group
-        // g receives row m0 + g
-        R om[NOUTP];
+          for (int m = 0; m < NOUTP; ++m) om[m] = m < NOUT ? o[m < NOUT ? m : 0] : R(0);
 #pragma unroll
-        for (int m = 0; m < NOUTP; ++m) om[m] = m < NOUT ? o[m < NOUT ? m : 0] : R(0);
-#pragma unroll
-        for (int m0 = 0; m0 < NOUTP; m0 += 4) {
-          const R v = quad_sum4(om[m0], om[m0 + 1], om[m0 + 2], om[m0 + 3]);
-          red[u * red_tt + (wv * NOUTP + m0 + (lane >> 4)) * kRows + r] = v;
-        }
-        // keep each step's loads next to its arithmetic (bounds the registers held)
-        __builtin_amdgcn_sched_barrier(0);
+          for (int m0 = 0; m0 < NOUTP; m0 += 4) {
+            const R v = quad_sum4(om[m0], om[m0 + 1], om[m0 + 2], om[m0 + 3]);
+            red[u * red_tt + (wv * NOUTP + m0 + (lane >> 4)) * kRows + r] = v;
+          }
+          // keep each step's loads next to its arithmetic (bounds the registers held)
+          __builtin_amdgcn_sched_barrier(0);
       }
       // y traces of the period's top-row cells for strip s + 1 (row 15 handled the cell
       // lambda = u - 15 at step u)
@@ -610,7 +644,7 @@ size_t lds_bytes3(int cb, int W, int dslots) {
   constexpr int NOUT = (S == LMDG_SCHEME_RLMDG && !P1R) ? 7 : Traits3<S>::NOUT;
   constexpr int NOUTP = (NOUT + 3) & ~3;
   const int L = (kRows - 1 + cb - 1) / cb;
-  return ((size_t)cb * (W * NOUTP * kRows + 1) + (size_t)(L + 2) * Traits3<S>::NK * cb * kRows +
+  return ((size_t)cb * (W * NOUTP * kRows + 1) + (size_t)nbuf3(L) * Traits3<S>::NK * cb * kRows +
           (size_t)2 * cb * dslots * Traits3<S>::NF) *
          sizeof(R);
 }

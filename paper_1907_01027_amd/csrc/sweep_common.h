@@ -16,6 +16,16 @@ __device__ __forceinline__ double shr1(double v) {
   hi = __builtin_amdgcn_update_dpp(0, hi, 0x111, 0xf, 0xf, false);
   return __hiloint2double(hi, lo);
 }
+// Value of lane l - 1 within each row of 16 lanes; lane 0 of a row gets its own `first`.
+__device__ __forceinline__ float shr1_or(float v, float first) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(first), __float_as_int(v), 0x111, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double shr1_or(double v, double first) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(__double2loint(first), lo, 0x111, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(__double2hiint(first), hi, 0x111, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
 
 // Sums over the four 16-lane groups (direction slots) of four values at once: lane
 // group g receives the sum of its g-th argument over the four groups.  A row swap of two

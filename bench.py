@@ -33,6 +33,10 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (packed) peak, TFLOP/s
+# floating-point work of one 3D RLMDG cell-direction update in the FP32 sweep kernel: its
+# step executes 80 FP32 VALU instructions (34 of them FMAs, counted twice) per lane
+FLOPS_PER_UPDATE_RLMDG3 = 114
 
 
 def _progress(msg):
@@ -469,6 +473,7 @@ def main():
     _progress(f"timed steps done ({args.steps} operator applications)")
     nbytes = sweep_bytes_per_launch(ncell, scheme, 3, n_rhs, 4)
     achieved = nbytes / (sweep_ms * 1e-3) / 1e9
+    alu_tflops = FLOPS_PER_UPDATE_RLMDG3 * ncell * len(w) * n_rhs / (sweep_ms * 1e-3) / 1e12
     del x, y
     out = {
         "metric": "sweep cell-direction updates/s + GMRES solve time to 1e-8, FP64 vs mixed",
@@ -492,7 +497,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(5),
                      "kernel": "sweep3d_kernel<float, RLMDG>", "kernel_ms": sweep_ms,
-                     "bytes_per_launch": nbytes},
+                     "bytes_per_launch": nbytes,
+                     # the sweep's arithmetic against the FP32 vector peak (its step issues no
+                     # packed FP32 instructions, whose rate the peak assumes)
+                     "alu": {"flops_per_update": FLOPS_PER_UPDATE_RLMDG3,
+                             "achieved_tflops": alu_tflops, "peak_tflops": FP32_VECTOR_PEAK_TFLOPS,
+                             "frac": alu_tflops / FP32_VECTOR_PEAK_TFLOPS}},
     }
     if not args.no_solve:
         out["solve"] = {"tol": 1e-8, "restart": 30, "max_iter": 400,

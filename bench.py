@@ -35,8 +35,8 @@ import numpy as np
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (packed) peak, TFLOP/s
 # floating-point work of one 3D RLMDG cell-direction update in the FP32 sweep kernel: its
-# step executes 80 FP32 VALU instructions (34 of them FMAs, counted twice) per lane
-FLOPS_PER_UPDATE_RLMDG3 = 114
+# step executes 72 FP32 VALU instructions (35 of them FMAs, counted twice) per lane
+FLOPS_PER_UPDATE_RLMDG3 = 107
 
 
 def _progress(msg):

@@ -69,9 +69,21 @@ struct Dir3 {
   R ao[3];   // |Omega_a|
   R aA[3];   // |Omega_a| A_a
   R oA[3];   // Omega_a A_a
+  R woA[3];  // w Omega_a A_a   (FP32 RLMDG rows: the weight folded into the constants)
+  R w3A[3];  // w |Omega_a| A_a / 3
   R w;
   int idx;
 };
+
+// 1 / d in the sweep: FP32 takes the hardware reciprocal (1 ulp), far inside the FP32
+// sweep's accuracy; FP64 refines it (recip)
+template <typename R>
+__device__ __forceinline__ R recip3(R d) {
+  if constexpr (sizeof(R) == 4)
+    return __builtin_amdgcn_rcpf(d);
+  else
+    return recip(d);
+}
 
 __host__ __device__ constexpr int popc3(int m) { return (m & 1) + ((m >> 1) & 1) + ((m >> 2) & 1); }
 // staged plane buffers of the sweep: planes p - L .. p + 1
@@ -318,6 +330,8 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
         d.ao[a] = (R)fabs(e[a]);
         d.aA[a] = (R)(fabs(e[a]) * A[a]);
         d.oA[a] = (R)(e[a] * A[a]);
+        d.woA[a] = (R)(e[3] * e[a] * A[a]);
+        d.w3A[a] = (R)(e[3] * fabs(e[a]) * A[a] / 3.0);
       }
       d.w = (R)e[3];
       d.idx = (int)e[4];
@@ -497,7 +511,7 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
             const R w = d.w;
             R psi;
             if constexpr (!RLM) {
-              const R inv = recip(sig + d.aA[0] + d.aA[1] + d.aA[2]);
+              const R inv = recip3(sig + d.aA[0] + d.aA[1] + d.aA[2]);
               psi = (src + d.aA[0] * xi[0] + d.aA[1] * yd[0] + d.aA[2] * zi[0]) * inv;
               xo[0] = yo[0] = zo[0] = psi;
               o[0] = w * psi;
@@ -510,7 +524,7 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
               const R kx = (b == 0 && first) ? R(1) : R(0.5);
               const R kz = plane0 ? R(1) : R(0.5);
               const R third = R(1) / R(3);
-              const R inv = recip(sig + d.aA[0] * (R(1) + kx) + d.aA[1] * (R(1) + ky) + d.aA[2] * (R(1) + kz));
+              const R inv = recip3(sig + d.aA[0] * (R(1) + kx) + d.aA[1] * (R(1) + ky) + d.aA[2] * (R(1) + kz));
               psi = (src + d.aA[0] * (xi[0] + kx * xi[3]) + d.aA[1] * (yd[0] + ky * yd[3]) +
                      d.aA[2] * (zi[0] + kz * zi[3])) *
                     inv;
@@ -532,15 +546,30 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
               // eps sigma_a V / 3: sigma_t V / 3 of L_11 R minus (sigma_s/eps) V / 3 of M_1 P_1 R
               const R sV3 = cf[5 * kRows];
               o[0] = w * psi;
-              o[1] = w * (d.oA[0] * (xi[0] - psi) + (sV3 + d.aA[0]) * cx +
-                          third * (d.aA[1] * (cx - yd[1]) + d.aA[2] * (cx - zi[1])));
-              o[2] = w * (d.oA[1] * (yd[0] - psi) + (sV3 + d.aA[1]) * cy +
-                          third * (d.aA[0] * (cy - xi[1]) + d.aA[2] * (cy - zi[2])));
-              o[3] = w * (d.oA[2] * (zi[0] - psi) + (sV3 + d.aA[2]) * cz +
-                          third * (d.aA[0] * (cz - xi[2]) + d.aA[1] * (cz - yd[2])));
-              o[4] = w * third * (d.oA[0] * (xi[1] - cy) + d.oA[1] * (yd[1] - cx));
-              o[5] = w * third * (d.oA[0] * (xi[2] - cz) + d.oA[2] * (zi[1] - cx));
-              o[6] = w * third * (d.oA[1] * (yd[2] - cz) + d.oA[2] * (zi[2] - cy));
+              if constexpr (sizeof(R) == 4) {
+                // FP32: the weight enters through the direction constants woA, w3A (fewer
+                // instructions; FP64 keeps the product form, which needs fewer registers)
+                const R wsV3 = w * sV3;
+                o[1] = d.woA[0] * (xi[0] - psi) + (wsV3 + R(3) * d.w3A[0]) * cx + d.w3A[1] * (cx - yd[1]) +
+                       d.w3A[2] * (cx - zi[1]);
+                o[2] = d.woA[1] * (yd[0] - psi) + (wsV3 + R(3) * d.w3A[1]) * cy + d.w3A[0] * (cy - xi[1]) +
+                       d.w3A[2] * (cy - zi[2]);
+                o[3] = d.woA[2] * (zi[0] - psi) + (wsV3 + R(3) * d.w3A[2]) * cz + d.w3A[0] * (cz - xi[2]) +
+                       d.w3A[1] * (cz - yd[2]);
+                o[4] = third * (d.woA[0] * (xi[1] - cy) + d.woA[1] * (yd[1] - cx));
+                o[5] = third * (d.woA[0] * (xi[2] - cz) + d.woA[2] * (zi[1] - cx));
+                o[6] = third * (d.woA[1] * (yd[2] - cz) + d.woA[2] * (zi[2] - cy));
+              } else {
+                o[1] = w * (d.oA[0] * (xi[0] - psi) + (sV3 + d.aA[0]) * cx +
+                            third * (d.aA[1] * (cx - yd[1]) + d.aA[2] * (cx - zi[1])));
+                o[2] = w * (d.oA[1] * (yd[0] - psi) + (sV3 + d.aA[1]) * cy +
+                            third * (d.aA[0] * (cy - xi[1]) + d.aA[2] * (cy - zi[2])));
+                o[3] = w * (d.oA[2] * (zi[0] - psi) + (sV3 + d.aA[2]) * cz +
+                            third * (d.aA[0] * (cz - xi[2]) + d.aA[1] * (cz - yd[2])));
+                o[4] = w * third * (d.oA[0] * (xi[1] - cy) + d.oA[1] * (yd[1] - cx));
+                o[5] = w * third * (d.oA[0] * (xi[2] - cz) + d.oA[2] * (zi[1] - cx));
+                o[6] = w * third * (d.oA[1] * (yd[2] - cz) + d.oA[2] * (zi[2] - cy));
+              }
               if constexpr (P1R) {
                 o[7] = w * cx;
                 o[8] = w * cy;

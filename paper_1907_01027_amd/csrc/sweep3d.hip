@@ -424,11 +424,9 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
       // y traces of strip s - 1 at plane p for the block's columns (row 0's inflow)
       if (p < nz) {
         const int ne = CB * ds * NF;
+        const int ne_in = s > 0 ? min(CB, nx - c0) * ds * NF : 0;  // entries of columns inside the mesh
         const R* src = yeb + (((long long)p * nstrips + (s - 1)) * nx + c0) * ds * NF;
-        for (int e = tid; e < ne; e += blockDim.x) {
-          const int c = c0 + e / (ds * NF);
-          eds[e] = (s > 0 && c < nx) ? load_agent(src + e) : R(0);
-        }
+        for (int e = tid; e < ne; e += blockDim.x) eds[e] = e < ne_in ? load_agent(src + e) : R(0);
       }
       // x traces of block b - 1 for this row, at the plane where the row enters the block
       {
@@ -642,24 +640,29 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
       if (tid == 0 && publish) store_agent(progr + (long long)s * nblk + b, (P.epoch << 32) | (unsigned long long)done);
       const int pb1 = (pb + 1 == NBUF) ? 0 : pb + 1;
       if (p + 1 < nz) stage_store(pb1);
-      // the period's outputs: one cell per (row, column of the block)
-      for (int e = tid; e < NOUT * CB16; e += blockDim.x) {
-        const int cl = e & (CB - 1);
-        const int rr = (e >> LCB) & (kRows - 1);
-        const int m = e >> (LCB + 4);
+      // the period's outputs: one cell per (row, column of the block) and thread, its
+      // NOUT rows summed over the waves
+      for (int t = tid; t < CB16; t += blockDim.x) {
+        const int cl = t & (CB - 1), rr = t >> LCB;
         const int u = (rr + cl) & (CB - 1);
         const int q = p + ((u - rr) >> LCB);
         const int c = c0 + cl;
         const int jr2 = s * kRows + rr;
         if (q >= 0 && q < nz && c < nx && jr2 < ny) {
-          R acc = 0;
-#pragma unroll
-          for (int w2 = 0; w2 < MAXW; ++w2)
-            if (w2 < W) acc += red[u * red_tt + (w2 * NOUTP + m) * kRows + rr];
+          const R* src = red + u * red_tt + rr;
           const int i = si[0] > 0 ? c : nx - 1 - c;
           const int jj = si[1] > 0 ? jr2 : ny - 1 - jr2;
           const int kk = si[2] > 0 ? q : nz - 1 - q;
-          partr[(long long)m * nc + (long long)kk * nxy + (long long)jj * nx + i] = acc;
+          R acc[NOUT];
+#pragma unroll
+          for (int m = 0; m < NOUT; ++m) acc[m] = src[m * kRows];
+          for (int w2 = 1; w2 < W; ++w2) {
+#pragma unroll
+            for (int m = 0; m < NOUT; ++m) acc[m] += src[(w2 * NOUTP + m) * kRows];
+          }
+          R* dst = partr + (long long)kk * nxy + (long long)jj * nx + i;
+#pragma unroll
+          for (int m = 0; m < NOUT; ++m) dst[(long long)m * nc] = acc[m];
         }
       }
       pb = pb1;

@@ -589,6 +589,9 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
             yprev[f] = yo[f];
             zreg[u][f] = zo[f];
             xsave[f] = last ? xo[f] : xsave[f];
+            // taken here: otherwise the selects sink below the last step and every
+            // step's outflow stays live across the period
+            asm volatile("" : "+v"(xsave[f]));
           }
           // top row: y traces for strip s + 1, staged in LDS for one store pass per period
           if (r == kRows - 1) {

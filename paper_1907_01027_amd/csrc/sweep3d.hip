@@ -268,6 +268,8 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
   constexpr int NBUF = nbuf3(L);                // staged planes: p - L .. p and p + 1
   constexpr int RING = NBUF * CB;               // staged cells per row (lambda modulo RING)
   constexpr int MAXC = (CB16 + 63) / 64;        // staged cells per thread (one wave at least)
+  // y-trace values of a period per thread: CB ds NF of them over 64 ceil(ds / 4) threads
+  constexpr int MAXE = (CB * NF + 15) / 16 > 0 ? (CB * NF + 15) / 16 : 1;
   constexpr bool RLM = S == LMDG_SCHEME_RLMDG;
   constexpr bool STDS = S == LMDG_SCHEME_STD;
   extern __shared__ unsigned char smem_raw[];
@@ -421,23 +423,39 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
         }
       }
       __syncthreads();
-      // y traces of strip s - 1 at plane p for the block's columns (row 0's inflow)
-      if (p < nz) {
-        const int ne = CB * ds * NF;
-        const int ne_in = s > 0 ? min(CB, nx - c0) * ds * NF : 0;  // entries of columns inside the mesh
-        const R* src = yeb + (((long long)p * nstrips + (s - 1)) * nx + c0) * ds * NF;
-        for (int e = tid; e < ne; e += blockDim.x) eds[e] = e < ne_in ? load_agent(src + e) : R(0);
-      }
-      // x traces of block b - 1 for this row, at the plane where the row enters the block
+      // y traces of strip s - 1 at plane p for the block's columns (row 0's inflow) and x
+      // traces of block b - 1 for this row at the plane where the row enters the block,
+      // issued together: every address is clamped into the buffers and values that do not
+      // exist (first strip or block, planes outside the mesh, ragged columns) are replaced
+      // by zero afterwards, so that the loads carry no branches and one memory latency
+      // covers both before the y traces go to LDS
       {
+        const int ne = CB * ds * NF;
+        const int ne_in = (s > 0 && p < nz) ? min(CB, nx - c0) * ds * NF : 0;  // columns inside the mesh
+        const R* ysrc = yeb + (((long long)min(p, nz - 1) * nstrips + max(s - 1, 0)) * nx + c0) * ds * NF;
+        R ev[MAXE];
+#pragma unroll
+        for (int k = 0; k < MAXE; ++k) {
+          const int e = tid + k * (int)blockDim.x;
+          const R v = load_agent(ysrc + (e < ne_in ? e : 0));
+          ev[k] = e < ne_in ? v : R(0);
+        }
         const int qx = p - (r >> LCB);
         const bool ok = b > 0 && row_ok && qx >= 0 && qx < nz;
-        const R* src = xeb + (((long long)qx * nstrips + s) * nblk + (b - 1)) * kRows * ds * NF + slot * kRows + r;
+        const R* xsrc = xeb + (((long long)min(max(qx, 0), nz - 1) * nstrips + s) * nblk + max(b - 1, 0)) * kRows * ds * NF +
+                        slot * kRows + r;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) xe[f] = ok ? load_agent(src + f * ds * kRows) : R(0);
+        for (int f = 0; f < NF; ++f) {
+          const R v = load_agent(xsrc + f * ds * kRows);
+          xe[f] = ok ? v : R(0);
+        }
+#pragma unroll
+        for (int k = 0; k < MAXE; ++k) {
+          const int e = tid + k * (int)blockDim.x;
+          if (e < ne) eds[e] = ev[k];
+        }
       }
-      if (p + 1 < nz) stage_load(p + 1);  // stays in flight through the steps
-      lds_barrier();  // staged y traces visible; the loads above stay in flight
+      lds_barrier();  // staged y traces visible
 
       // the row index passes through an empty asm once per period, so that the per-step
       // values derived from it are recomputed here instead of being held in registers
@@ -610,6 +628,9 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
           }
           // keep each step's loads next to its arithmetic (bounds the registers held)
           __builtin_amdgcn_sched_barrier(0);
+          // the next plane's coefficients: issued after the first step, whose x-inflow
+          // needs the x traces above, and in flight through the other steps
+          if (u == 0 && p + 1 < nz) stage_load(p + 1);
       }
       // y traces of the period's top-row cells for strip s + 1 (row 15 handled the cell
       // lambda = u - 15 at step u)

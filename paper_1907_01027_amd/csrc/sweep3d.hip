@@ -389,6 +389,7 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
     };
 
     R zreg[CB][NF], xin[NF], yprev[NF], xe[NF], xsave[NF];
+    unsigned long long seen_b = 0, seen_s = 0;  // progress words last read (thread 0)
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       xin[f] = yprev[f] = xsave[f] = R(0);
@@ -403,20 +404,19 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
     stage_store(0);
     int pb = 0;  // p % NBUF
     for (int p = 0; p < nz + L; ++p) {
+      // wait until (s, b - 1) and (s - 1, b) have completed plane p: thread 0 keeps the
+      // progress words it last read and reads a word again only while that falls short,
+      // both words at once
       if (tid == 0 && (s > 0 || b > 0)) {
         const int need = min(p + 1, nz);
         const unsigned long long target = ((P.epoch + P.wait_bias) << 32) | (unsigned long long)need;
+        const unsigned long long* fb = progr + (long long)s * nblk + (b - 1);
+        const unsigned long long* fs = progr + (long long)(s - 1) * nblk + b;
         long long spins = 0;
-        if (b > 0) {
-          const unsigned long long* flag = progr + (long long)s * nblk + (b - 1);
-          while (load_agent(flag) < target) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > P.spin_limit) { atomicOr(P.err, 1); break; }
-          }
-        }
-        if (s > 0) {
-          const unsigned long long* flag = progr + (long long)(s - 1) * nblk + b;
-          while (load_agent(flag) < target) {
+        while ((b > 0 && seen_b < target) || (s > 0 && seen_s < target)) {
+          if (b > 0 && seen_b < target) seen_b = load_agent(fb);
+          if (s > 0 && seen_s < target) seen_s = load_agent(fs);
+          if ((b > 0 && seen_b < target) || (s > 0 && seen_s < target)) {
             __builtin_amdgcn_s_sleep(2);
             if (++spins > P.spin_limit) { atomicOr(P.err, 1); break; }
           }

@@ -655,13 +655,8 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
           for (int f = 0; f < NF; ++f) store_agent(dst + f * ds * kRows, xsave[f]);
         }
       }
-      // publish: planes below `done` are finished by every row of the block (their trace
-      // stores included); waves wait for their own stores before the barrier
-      const int done = min(p + 1 - L, nz);
-      const bool publish = done > 0 && (s + 1 < nstrips || b + 1 < nblk);
-      if (publish) __builtin_amdgcn_s_waitcnt(kWaitVmem);
-      __syncthreads();
-      if (tid == 0 && publish) store_agent(progr + (long long)s * nblk + b, (P.epoch << 32) | (unsigned long long)done);
+      // the next plane's coefficients to LDS and the period's outputs before the progress
+      // word: the write-through of the trace stores above completes meanwhile
       const int pb1 = (pb + 1 == NBUF) ? 0 : pb + 1;
       if (p + 1 < nz) stage_store(pb1);
       // the period's outputs: one cell per (row, column of the block) and thread, its
@@ -689,6 +684,13 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
           for (int m = 0; m < NOUT; ++m) dst[(long long)m * nc] = acc[m];
         }
       }
+      // publish: planes below `done` are finished by every row of the block (their trace
+      // stores included); waves wait for their own stores before the barrier
+      const int done = min(p + 1 - L, nz);
+      const bool publish = done > 0 && (s + 1 < nstrips || b + 1 < nblk);
+      if (publish) __builtin_amdgcn_s_waitcnt(kWaitVmem);
+      __syncthreads();
+      if (tid == 0 && publish) store_agent(progr + (long long)s * nblk + b, (P.epoch << 32) | (unsigned long long)done);
       pb = pb1;
     }
     __syncthreads();

@@ -479,6 +479,9 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
   constexpr int NRAW = SrcTraitsV<S, VAR>::NRAW;
   // staged cells per thread: the 9-wave variant has threads for a whole chunk
   constexpr int MAXC = MAXW > 4 ? 1 : SrcTraits<S>::MAXC;
+  // strip-below traces of a chunk per thread: cw NF dslots of them over 64 W threads
+  // (dslots = 4 W, chunks of at most 16 columns)
+  constexpr int MAXE = NF;
   constexpr bool LM = S != LMDG_SCHEME_STD;
   extern __shared__ unsigned char smem_raw[];
   __shared__ int s_item;
@@ -574,6 +577,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
     R xin[NF], yprev[NF], gx[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) { xin[f] = 0; yprev[f] = 0; gx[f] = 0; }
+    unsigned long long seen = 0;  // progress word of strip s - 1 last read (thread 0)
     if constexpr (DATA) {
       // ghost trace at the x-inflow face of this lane's row (mesh row j)
       if (P.alpha && row_ok && d.idx >= 0) {
@@ -588,25 +592,43 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
     for (int k = 0; k < P.nchunks; ++k) {
       const int t0 = k << lcw;
       const int buf = k & 1;
+      // wait until strip s - 1 has completed the chunk's columns: thread 0 keeps the
+      // progress word it last read and reads it again only while that falls short
       if (s > 0 && tid == 0) {
         const int need = min(nx, t0 + cw);
         const unsigned long long target = ((P.epoch + P.wait_bias) << 32) | (unsigned long long)need;
-        const unsigned long long* flag = progr + (long long)q * P.nstrips + (s - 1);
-        long long spins = 0;
-        while (load_agent(flag) < target) {
-          __builtin_amdgcn_s_sleep(2);
-          if (++spins > P.spin_limit) { atomicOr(P.err, 1); break; }
+        if (seen < target) {
+          const unsigned long long* flag = progr + (long long)q * P.nstrips + (s - 1);
+          long long spins = 0;
+          while ((seen = load_agent(flag)) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > P.spin_limit) { atomicOr(P.err, 1); break; }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       __syncthreads();
-      // traces of the strip below for the columns of this chunk (zero for the first strip)
+      // traces of the strip below for the columns of this chunk (zero for the first strip):
+      // all of a thread's loads issued at once (addresses clamped into the buffer, values
+      // outside the mesh replaced by zero afterwards), then written to LDS, so that the
+      // chunk waits for one memory latency
       {
         const int ne = (cw * NF) * P.dslots;
-        const R* src = edger + (((long long)q * P.nstrips + (s - 1)) * nx + t0) * NF * P.dslots;
-        for (int e = tid; e < ne; e += blockDim.x) {
+        const int ne_in = s > 0 ? max(0, min(cw, nx - t0)) * NF * P.dslots : 0;  // columns inside the mesh
+        const R* src = edger + (((long long)q * P.nstrips + max(s - 1, 0)) * nx + (t0 < nx ? t0 : 0)) * NF * P.dslots;
+        R ev[MAXE];
+#pragma unroll
+        for (int kk = 0; kk < MAXE; ++kk) {
+          const int e = tid + kk * (int)blockDim.x;
+          const R v = load_agent(src + (e < ne_in ? e : 0));
+          ev[kk] = e < ne_in ? v : R(0);
+        }
+#pragma unroll
+        for (int kk = 0; kk < MAXE; ++kk) {
+          const int e = tid + kk * (int)blockDim.x;
+          if (e >= ne) continue;
           const int c = t0 + e / (NF * P.dslots);
-          R v = (s > 0 && c < nx) ? load_agent(src + e) : R(0);
+          R v = ev[kk];
           if constexpr (DATA) {
             // ghost traces below the y-inflow faces of the first strip
             if (s == 0 && P.alpha && c < nx) {

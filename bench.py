@@ -505,7 +505,9 @@ def main():
                              "frac": alu_tflops / FP32_VECTOR_PEAK_TFLOPS}},
     }
     if not args.no_solve:
-        out["solve"] = {"tol": 1e-8, "restart": 30, "max_iter": 400,
+        # mixed mode: four digits per inner FP32 solve (two refinement passes instead of three)
+        lmdg.lmdg_set_refinement(h, 1e-4)
+        out["solve"] = {"tol": 1e-8, "restart": 30, "max_iter": 400, "mixed_inner_tol": 1e-4,
                         **_solve_pair(torch, lmdg, h, scheme, N, 1e-8, 30, 400, dev, "128^3")}
     solver.close()
     if not args.no_extra:

@@ -316,6 +316,18 @@ int lmdg_set_reconstruction(lmdg_t* h, int stencil, int suppress);
 int lmdg_set_augment(lmdg_t* h, int k);
 
 /*
+ * Iterative refinement of mode MIXED (lmdg_solve, lmdg_adjoint_solve): each pass
+ * computes the FP64 residual r and solves K d = r with FP32 sweeps until the inner
+ * relative residual is inner_tol (or the FP32 operator stops making progress); fewer
+ * digits per pass mean more passes, each of which restarts the Krylov space, more
+ * digits mean longer inner solves.  Which is faster depends on the system: 1e-3
+ * (the default) suits the preconditioned 2D solves, 1e-4 the 3D ones.
+ *   inner_tol  1e-6 .. 0.5 (FP32 sweeps carry about 1e-6 relative error)
+ * Errors: INVALID_ARG (inner_tol outside that range).
+ */
+int lmdg_set_refinement(lmdg_t* h, double inner_tol);
+
+/*
  * Preconditioner of the handle's GMRES solves of the reduced LMDG and RLMDG systems
  * (lmdg_solve, the LMDG adjoint solve and the inner solves of mode MIXED), applied on
  * the right: GMRES works on K M^{-1} u = b and the iterate is X = M^{-1} u, so the

@@ -1174,9 +1174,10 @@ static int solve_impl(lmdg_t* h, int scheme, int mode, double tol, int restart, 
       if (relres <= tol) { conv = true; break; }
       passes += 1;
       lmdg::vec_fill(d, 0.0, N, st);
-      // FP32 sweeps carry about 1e-6 relative error, so each pass asks for three
-      // digits at most and the FP64 residual of the next pass corrects the rest
-      const double inner = std::max(1e-3, 0.5 * tol / relres);
+      // FP32 sweeps carry about 1e-6 relative error, so each pass asks for a few digits
+      // (three unless lmdg_set_refinement says otherwise) and the FP64 residual of the
+      // next pass corrects the rest
+      const double inner = std::max(h->ir_inner, 0.5 * tol / relres);
       bool iconv = false;
       double irel = 1;
       const int before = stats.iterations;
@@ -1457,6 +1458,13 @@ int lmdg_set_augment(lmdg_t* h, int k) {
   if (!h) return LMDG_INVALID_ARG;
   if (k < 0 || k > kMaxRestart - 1) return set_error(h, LMDG_INVALID_ARG, "augmentation count out of range");
   h->augment = k;
+  return LMDG_OK;
+}
+
+int lmdg_set_refinement(lmdg_t* h, double inner_tol) {
+  if (!h) return LMDG_INVALID_ARG;
+  if (!(inner_tol >= 1e-6 && inner_tol <= 0.5)) return set_error(h, LMDG_INVALID_ARG, "inner tolerance out of range");
+  h->ir_inner = inner_tol;
   return LMDG_OK;
 }
 

@@ -215,6 +215,7 @@ struct lmdg_handle {
   double* h_small = nullptr;       // pinned host mirror
   size_t small_doubles = 0;
   int augment = 0;                 // LGMRES: stored corrections searched per restart cycle
+  double ir_inner = 1e-3;          // mode MIXED: residual reduction asked of each inner FP32 solve
   unsigned long long mat_version = 0;   // bumped by lmdg_set_materials
   int pc_kind = 0;                 // LMDG_PRECOND_* used by the solves
   int pc_cycles = 1;               // V-cycles per application of the two-level preconditioner

@@ -32,7 +32,7 @@ EXPORTED = ["lmdg_status_string", "lmdg_last_error", "lmdg_quadrature_level_symm
             "lmdg_recover", "lmdg_solve", "lmdg_set_augment", "lmdg_adjoint_solve", "lmdg_profile",
             "lmdg_sweep_kernel_time", "lmdg_synchronize", "lmdg_set_wait_limit", "lmdg_set_source_moments",
             "lmdg_workspace_bytes", "lmdg_apply_noalloc", "lmdg_set_reconstruction", "lmdg_set_preconditioner",
-            "lmdg_precond_apply"]
+            "lmdg_precond_apply", "lmdg_set_refinement"]
 
 
 class LmdgInfo(ctypes.Structure):
@@ -70,6 +70,7 @@ def _load():
         "lmdg_solve": (I, [P, I, I, D, I, I, P, P, P, ctypes.POINTER(LmdgInfo), P]),
         "lmdg_adjoint_solve": (I, [P, I, I, P, D, I, I, P, P, P, ctypes.POINTER(D), ctypes.POINTER(LmdgInfo), P]),
         "lmdg_set_augment": (I, [P, I]),
+        "lmdg_set_refinement": (I, [P, D]),
         "lmdg_profile": (I, [P, I]),
         "lmdg_sweep_kernel_time": (I, [P, ctypes.POINTER(D), ctypes.POINTER(I)]),
         "lmdg_synchronize": (I, [P, P]),
@@ -245,6 +246,11 @@ def lmdg_precond_apply(h, scheme, r, z, stream=None):
 def lmdg_set_augment(h, k):
     """Number of earlier restart corrections each GMRES cycle also searches (LGMRES); 0 = plain GMRES."""
     _check(_lib.lmdg_set_augment(h, int(k)), h)
+
+
+def lmdg_set_refinement(h, inner_tol):
+    """Residual reduction each inner FP32 solve of mode "mixed" aims for (default 1e-3)."""
+    _check(_lib.lmdg_set_refinement(h, float(inner_tol)), h)
 
 
 def lmdg_profile(h, enable):

@@ -163,6 +163,34 @@ def test_solve_3d_against_direct(scheme, mode):
     s.close()
 
 
+def test_mixed_refinement_digits():
+    """lmdg_set_refinement: mixed solves that ask each inner FP32 solve for two and for
+    four digits both reach the oracle's direct solution, the latter in fewer FP64
+    passes; values outside [1e-6, 0.5] are refused."""
+    case = Case3((6, 7, 5), 4, eps=0.1)
+    s = case.solver()
+    nc = case.ncell
+    ref = S.scalar_flux_lm(case.prob, *S.solve_rlmdg_direct(case.prob))
+    passes = {}
+    try:
+        for inner in (1e-2, 1e-4):
+            lmdg.lmdg_set_refinement(s.h, inner)
+            x = torch.zeros(8 * nc, dtype=torch.float64, device=DEV)
+            phi = torch.zeros_like(x)
+            info = lmdg.lmdg_solve(s.h, "rlmdg", "mixed", 1e-12, 40, 4000, x, phi)
+            e = rel_err(N(phi).reshape(8, nc).T, ref)
+            print(f"inner {inner}: {info['iterations']} applications, {info['ir_passes']} passes, {e:.2e}")
+            assert info["converged"] == 1 and e < 1e-9
+            passes[inner] = info["ir_passes"]
+        for bad in (0.0, 1e-7, 0.6):
+            with pytest.raises(lmdg.LmdgError) as err:
+                lmdg.lmdg_set_refinement(s.h, bad)
+            assert err.value.status == lmdg.LMDG_INVALID_ARG
+    finally:
+        s.close()
+    assert passes[1e-4] < passes[1e-2]
+
+
 def test_multi_source_3d_equals_single():
     case = Case3((5, 18, 4), 4, eps=0.2)
     nc = case.ncell

@@ -691,6 +691,18 @@ int ensure_small(lmdg_t* h, size_t doubles) {
   return rc;
 }
 
+// Workspace of one GMRES call, in doubles: the basis (mt + 1 vectors of NT values, FP64,
+// or FP32 with an FP32 operator), r; with augmentation k stored corrections, their
+// images, the cycle's correction and its image; with the preconditioner two more; with
+// an FP32 basis the new Krylov vector and the operator's input in FP64.
+size_t krylov_basis_doubles(int mt, bool lowv, long long NT) {
+  return lowv ? ((size_t)(mt + 1) * NT + 1) / 2 : (size_t)(mt + 1) * NT;
+}
+size_t krylov_doubles(int mt, int ka, bool pc, bool lowv, long long NT) {
+  return krylov_basis_doubles(mt, lowv, NT) +
+         (size_t)(1 + (ka > 0 ? 2 * ka + 2 : 0) + (pc ? 2 : 0) + (lowv ? 2 : 0)) * NT;
+}
+
 int ensure_krylov(lmdg_t* h, size_t doubles) {
   if (h->krylov_doubles >= doubles) return LMDG_OK;
   if (h->d_krylov) hipFree(h->d_krylov);
@@ -790,22 +802,46 @@ int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, doubl
   const SmallLayout L = small_layout(nr);
   // right preconditioning (lmdg_set_preconditioner) where it covers the system
   const bool pc = h->pc_kind != LMDG_PRECOND_NONE && lmdg::pc_supported(h, scheme, nullptr);
-  // V (mt + 1), r; with augmentation also Z, K Z (ka_max each), the correction and its image;
-  // with the preconditioner two more (M^{-1} of a basis vector, of the cycle's combination)
-  const size_t base_vecs = (size_t)(mt + 2 + (ka_max > 0 ? 2 * ka_max + 2 : 0));
+  // with an FP32 operator (the inner solves of mode MIXED) the basis is stored in FP32:
+  // the orthogonalisation reads it twice per step, and the inner solves aim at a few
+  // digits only; products, sums, the new vector and the corrections stay FP64
+  const bool lowv = prec == LMDG_PREC_FP32;
+  const size_t basis_d = krylov_basis_doubles(mt, lowv, NT);
   const double* prev_krylov = h->d_krylov;
-  int rc = ensure_krylov(h, (base_vecs + (pc ? 2 : 0)) * NT);
+  int rc = ensure_krylov(h, krylov_doubles(mt, ka_max, pc, lowv, NT));
   if (h->d_krylov != prev_krylov) stats.n_aug = stats.aug_next = 0;  // store lost with the old buffer
   if (rc == LMDG_OK) rc = ensure_small(h, L.total);
   if (rc != LMDG_OK) return rc;
-  double* V = h->d_krylov;                 // mt + 1 basis vectors of length NT
-  double* r = V + (size_t)(mt + 1) * NT;   // residual work vector
+  double* V = lowv ? nullptr : h->d_krylov;                   // mt + 1 basis vectors of length NT
+  float* Vf = lowv ? reinterpret_cast<float*>(h->d_krylov) : nullptr;
+  double* r = h->d_krylov + basis_d;       // residual work vector
   double* Z = r + NT;                      // ka_max stored corrections
   double* AZ = Z + (size_t)ka_max * NT;    // their images
   double* dz = ka_max > 0 ? AZ + (size_t)ka_max * NT : x;  // this cycle's correction (x itself
   double* adz = dz + NT;                                     // without augmentation), its image
-  double* pt = h->d_krylov + base_vecs * NT;                 // preconditioner input / output
+  double* tail = r + (size_t)(1 + (ka_max > 0 ? 2 * ka_max + 2 : 0)) * NT;
+  double* pt = tail;                                         // preconditioner input / output
   double* pz = pt + NT;
+  double* wv = tail + (pc ? 2 : 0) * NT;   // FP32 basis: the new Krylov vector in FP64
+  double* vin = wv + NT;                   // FP32 basis: the basis vector the operator takes
+  // basis operations for either storage
+  auto basis_dots = [&](int nv, const double* w) {
+    if (lowv) lmdg::vec_dots(Vf, NT, nv, w, N, h->d_small + L.part, h->d_small + L.coef, st, nr);
+    else lmdg::vec_dots(V, NT, nv, w, N, h->d_small + L.part, h->d_small + L.coef, st, nr);
+  };
+  auto basis_axpy = [&](double* w, int nv, const double* coef, double sign) {
+    if (lowv) lmdg::vec_axpy_multi(w, Vf, NT, nv, coef, sign, N, st, nr);
+    else lmdg::vec_axpy_multi(w, V, NT, nv, coef, sign, N, st, nr);
+  };
+  auto basis_store = [&](int j, const double* src, const double* scale) {  // V_j = scale * src
+    if (lowv) lmdg::vec_scale_seg(Vf + (size_t)j * NT, src, scale, N, nr, st);
+    else lmdg::vec_scale_seg(V + (size_t)j * NT, src, scale, N, nr, st);
+  };
+  auto basis_vec = [&](int j) -> const double* {  // V_j in FP64 (widened into vin)
+    if (!lowv) return V + (size_t)j * NT;
+    lmdg::vec_widen(vin, Vf + (size_t)j * NT, NT, st);
+    return vin;
+  };
   double* dcoef = h->d_small + L.coef;
   double* dscal = h->d_small + L.scal;
   double* part = h->d_small + L.part;
@@ -879,18 +915,19 @@ int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, doubl
     }
     rc = upload_scales();
     if (rc != LMDG_OK) break;
-    lmdg::vec_scale_seg(V, r, dscal, N, nr, st);
+    basis_store(0, r, dscal);
     const int steps = m + n_aug;
     for (int j = 0; j < steps; ++j) {
       const bool krylov = j < m;
       if (krylov && stats.iterations >= max_iter) break;
-      double* w = V + (size_t)(j + 1) * NT;
+      double* w = lowv ? wv : V + (size_t)(j + 1) * NT;
       if (krylov) {
+        const double* vj = basis_vec(j);
         if (pc) {  // w = K M^{-1} v_j
-          rc = lmdg::pc_apply(h, scheme, V + (size_t)j * NT, pz, st);
+          rc = lmdg::pc_apply(h, scheme, vj, pz, st);
           if (rc != LMDG_OK) break;
         }
-        rc = timed_apply(prec, pc ? pz : V + (size_t)j * NT, w);
+        rc = timed_apply(prec, pc ? pz : vj, w);
         if (rc != LMDG_OK) break;
         stats.iterations += 1;
       } else {
@@ -901,8 +938,8 @@ int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, doubl
       // classical Gram-Schmidt, coefficients kept on the device; a second pass only where
       // the first cancelled: ||w'|| < ||w|| / sqrt(2), i.e. ||w'||^2 < sum_i h_i^2 with
       // w' = w - V h (Daniel, Gragg, Kaufman and Stewart 1976)
-      lmdg::vec_dots(V, NT, j + 1, w, N, part, dcoef, st, nr);
-      lmdg::vec_axpy_multi(w, V, NT, j + 1, dcoef, -1.0, N, st, nr);
+      basis_dots(j + 1, w);
+      basis_axpy(w, j + 1, dcoef, -1.0);
       rc = check_hip(h, hipMemcpyAsync(hc, dcoef, (j + 1) * nr * sizeof(double), hipMemcpyDeviceToHost, st), "h");
       if (rc != LMDG_OK) break;
       rc = seg_norms(h, w, N, nr, hn.data(), st);  // synchronises: hc is valid afterwards
@@ -916,8 +953,8 @@ int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, doubl
       }
       double* hc2 = hc + (size_t)(mt + 1) * nr;
       if (second) {
-        lmdg::vec_dots(V, NT, j + 1, w, N, part, dcoef, st, nr);
-        lmdg::vec_axpy_multi(w, V, NT, j + 1, dcoef, -1.0, N, st, nr);
+        basis_dots(j + 1, w);
+        basis_axpy(w, j + 1, dcoef, -1.0);
         rc = check_hip(h, hipMemcpyAsync(hc2, dcoef, (j + 1) * nr * sizeof(double), hipMemcpyDeviceToHost, st),
                        "h2");
         if (rc != LMDG_OK) break;
@@ -969,7 +1006,7 @@ int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, doubl
       // (the image of the cycle's correction uses it also when that one just finished)
       rc = upload_scales();
       if (rc != LMDG_OK) break;
-      lmdg::vec_scale_seg(w, w, dscal, N, nr, st);
+      basis_store(j + 1, w, dscal);
       if (all_done) break;
     }
     if (rc != LMDG_OK) break;
@@ -998,14 +1035,14 @@ int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, doubl
     if (pc) {
       // Krylov part of the correction: M^{-1} (sum_j y_j V_j)
       lmdg::vec_fill(pt, 0.0, NT, st);
-      lmdg::vec_axpy_multi(pt, V, NT, nkry, dcoef, 1.0, N, st, nr);
+      basis_axpy(pt, nkry, dcoef, 1.0);
       rc = lmdg::pc_apply(h, scheme, pt, pz, st);
       if (rc != LMDG_OK) break;
       if (ka_max > 0) lmdg::vec_copy(dz, pz, NT, st);
       else lmdg::vec_axpby(x, 1.0, pz, 1.0, NT, st);
     } else {
       if (ka_max > 0) lmdg::vec_fill(dz, 0.0, NT, st);
-      lmdg::vec_axpy_multi(dz, V, NT, nkry, dcoef, 1.0, N, st, nr);
+      basis_axpy(dz, nkry, dcoef, 1.0);
     }
     if (kmax > m) {
       // stored corrections: coefficients by ring slot (step m + l used slot aug_next - 1 - l)
@@ -1039,7 +1076,7 @@ int gmres(lmdg_t* h, int scheme, int prec, int true_prec, const double* b, doubl
                                      st), "hy");
     if (rc != LMDG_OK) break;
     lmdg::vec_fill(adz, 0.0, NT, st);
-    lmdg::vec_axpy_multi(adz, V, NT, kmax + 1, dcoef, 1.0, N, st, nr);
+    basis_axpy(adz, kmax + 1, dcoef, 1.0);
     rc = seg_norms(h, dz, N, nr, zn.data(), st);
     if (rc != LMDG_OK) break;
     for (int k = 0; k < nr; ++k) hscal[k] = zn[k] > 0 ? 1.0 / zn[k] : 0.0;
@@ -1420,8 +1457,10 @@ int lmdg_workspace_bytes(const lmdg_t* h, int restart, int64_t* held, int64_t* s
   *held = (int64_t)b;
   // what a solve with this restart (and the handle's augmentation) allocates beyond that
   const int ka = std::max(0, std::min(h->augment, kMaxRestart - restart));
-  const size_t kry = (size_t)(restart + ka + 2 + (ka > 0 ? 2 * ka + 2 : 0) + (h->pc_kind ? 2 : 0)) * h->np * nc *
-                     h->n_rhs;
+  const long long NT = (long long)h->np * nc * h->n_rhs;
+  const bool pcs = h->pc_kind != LMDG_PRECOND_NONE;
+  const size_t kry = std::max(krylov_doubles(restart + ka, ka, pcs, false, NT),   // FP64 solves
+                              krylov_doubles(restart + ka, ka, pcs, true, NT));   // inner solves of MIXED
   const size_t small = small_layout(h->n_rhs).total;
   *solve = (int64_t)((kry > h->krylov_doubles ? kry : 0) + (small > h->small_doubles ? small : 0)) * (int64_t)d;
   return LMDG_OK;

@@ -278,6 +278,13 @@ void vec_dots(const double* V, long long ld, int nvec, const double* w, long lon
 void vec_axpy_multi(double* w, const double* V, long long ld, int nvec, const double* coef,
                     double sign, long long n, hipStream_t st, int nr = 1);
 void vec_scale_seg(double* y, const double* x, const double* scale, long long n, int nr, hipStream_t st);
+// FP32 Krylov basis (the inner solves of mode MIXED): products and sums in FP64
+void vec_dots(const float* V, long long ld, int nvec, const double* w, long long n, double* partial, double* out,
+              hipStream_t st, int nr = 1);
+void vec_axpy_multi(double* w, const float* V, long long ld, int nvec, const double* coef, double sign,
+                    long long n, hipStream_t st, int nr = 1);
+void vec_scale_seg(float* y, const double* x, const double* scale, long long n, int nr, hipStream_t st);
+void vec_widen(double* y, const float* x, long long n, hipStream_t st);
 void vec_axpby(double* y, double a, const double* x, double b, long long n, hipStream_t st);
 void vec_copy(double* y, const double* x, long long n, hipStream_t st);
 void vec_fill(double* y, double v, long long n, hipStream_t st);

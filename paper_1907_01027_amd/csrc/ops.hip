@@ -380,8 +380,11 @@ constexpr int kDotBlocks = 240;
 // up to kDotGroup basis vectors v0 + 0.. (blockIdx.y) and segment rz (blockIdx.z):
 // partial[(v * nr + rz) * kDotBlocks + b] = block b's share of V_v[rz] . w[rz]; each
 // element of w is read once per group.
+// The basis may be stored in FP32 (TV = float: the inner solves of mode MIXED); products
+// and sums are FP64.
 constexpr int kDotGroup = 8;
-__global__ void dots_partial_kernel(const double* __restrict__ V, long long ld, int nvec,
+template <typename TV>
+__global__ void dots_partial_kernel(const TV* __restrict__ V, long long ld, int nvec,
                                     const double* __restrict__ w_all, long long n, double* __restrict__ partial) {
   const int v0 = blockIdx.y * kDotGroup;
   const int nv = min(kDotGroup, nvec - v0);
@@ -395,7 +398,7 @@ __global__ void dots_partial_kernel(const double* __restrict__ V, long long ld, 
     const double we = w[e];
 #pragma unroll
     for (int k = 0; k < kDotGroup; ++k)
-      if (k < nv) acc[k] += V[(v0 + k) * ld + rz * n + e] * we;
+      if (k < nv) acc[k] += (double)V[(v0 + k) * ld + rz * n + e] * we;
   }
   __shared__ double sh[kDotGroup][kBlock];
 #pragma unroll
@@ -426,23 +429,32 @@ __global__ void dots_final_kernel(const double* __restrict__ partial, int nparts
 }
 
 // w[rz] += sign * sum_v coef[v * nr + rz] V_v[rz] over stacked segments of length n
-__global__ void axpy_multi_kernel(double* __restrict__ w, const double* __restrict__ V, long long ld, int nvec,
+template <typename TV>
+__global__ void axpy_multi_kernel(double* __restrict__ w, const TV* __restrict__ V, long long ld, int nvec,
                                   const double* __restrict__ coef, double sign, long long n, int nr) {
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n * nr;
        e += (long long)gridDim.x * blockDim.x) {
     const long long rz = e / n;
     double acc = 0;
-    for (int v = 0; v < nvec; ++v) acc += coef[(long long)v * nr + rz] * V[v * ld + e];
+    for (int v = 0; v < nvec; ++v) acc += coef[(long long)v * nr + rz] * (double)V[v * ld + e];
     w[e] += sign * acc;
   }
 }
 
-// y[rz] = scale[rz] * x[rz] over stacked segments of length n (scale on the device)
-__global__ void scale_seg_kernel(double* __restrict__ y, const double* __restrict__ x,
+// y[rz] = scale[rz] * x[rz] over stacked segments of length n (scale on the device),
+// rounded to the type of y
+template <typename TY>
+__global__ void scale_seg_kernel(TY* __restrict__ y, const double* __restrict__ x,
                                  const double* __restrict__ scale, long long n, int nr) {
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n * nr;
        e += (long long)gridDim.x * blockDim.x)
-    y[e] = scale[e / n] * x[e];
+    y[e] = (TY)(scale[e / n] * x[e]);
+}
+
+__global__ void widen_kernel(double* __restrict__ y, const float* __restrict__ x, long long n) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    y[e] = (double)x[e];
 }
 
 __global__ void axpby_kernel(double* __restrict__ y, double a, const double* __restrict__ x, double b,
@@ -556,22 +568,44 @@ void launch_gradients(lmdg_handle* h, int npsi, const double* bil, const double*
                      h->area, gs, ga, gq);
 }
 
+template <typename TV>
+static void dots_impl(const TV* V, long long ld, int nvec, const double* w, long long n, double* partial, double* out,
+                      hipStream_t st, int nr) {
+  hipLaunchKernelGGL(dots_partial_kernel<TV>, dim3(kDotBlocks, (nvec + kDotGroup - 1) / kDotGroup, nr), dim3(kBlock),
+                     0, st, V, ld, nvec, w, n, partial);
+  hipLaunchKernelGGL(dots_final_kernel, dim3(nvec * nr), dim3(kBlock), 0, st, partial, kDotBlocks, out);
+}
 void vec_dots(const double* V, long long ld, int nvec, const double* w, long long n, double* partial,
               double* out, hipStream_t st, int nr) {
-  hipLaunchKernelGGL(dots_partial_kernel, dim3(kDotBlocks, (nvec + kDotGroup - 1) / kDotGroup, nr), dim3(kBlock), 0,
-                     st, V, ld, nvec, w, n, partial);
-  hipLaunchKernelGGL(dots_final_kernel, dim3(nvec * nr), dim3(kBlock), 0, st, partial, kDotBlocks, out);
+  dots_impl(V, ld, nvec, w, n, partial, out, st, nr);
+}
+void vec_dots(const float* V, long long ld, int nvec, const double* w, long long n, double* partial,
+              double* out, hipStream_t st, int nr) {
+  dots_impl(V, ld, nvec, w, n, partial, out, st, nr);
 }
 
 void vec_scale_seg(double* y, const double* x, const double* scale, long long n, int nr, hipStream_t st) {
-  hipLaunchKernelGGL(scale_seg_kernel, dim3(std::min(grid_for(n * nr), 4096)), dim3(kBlock), 0, st, y, x, scale, n,
-                     nr);
+  hipLaunchKernelGGL(scale_seg_kernel<double>, dim3(std::min(grid_for(n * nr), 4096)), dim3(kBlock), 0, st, y, x,
+                     scale, n, nr);
+}
+void vec_scale_seg(float* y, const double* x, const double* scale, long long n, int nr, hipStream_t st) {
+  hipLaunchKernelGGL(scale_seg_kernel<float>, dim3(std::min(grid_for(n * nr), 4096)), dim3(kBlock), 0, st, y, x,
+                     scale, n, nr);
 }
 
 void vec_axpy_multi(double* w, const double* V, long long ld, int nvec, const double* coef, double sign,
                     long long n, hipStream_t st, int nr) {
-  hipLaunchKernelGGL(axpy_multi_kernel, dim3(std::min(grid_for(n * nr), 4096)), dim3(kBlock), 0, st, w, V, ld, nvec,
-                     coef, sign, n, nr);
+  hipLaunchKernelGGL(axpy_multi_kernel<double>, dim3(std::min(grid_for(n * nr), 4096)), dim3(kBlock), 0, st, w, V,
+                     ld, nvec, coef, sign, n, nr);
+}
+void vec_axpy_multi(double* w, const float* V, long long ld, int nvec, const double* coef, double sign,
+                    long long n, hipStream_t st, int nr) {
+  hipLaunchKernelGGL(axpy_multi_kernel<float>, dim3(std::min(grid_for(n * nr), 4096)), dim3(kBlock), 0, st, w, V,
+                     ld, nvec, coef, sign, n, nr);
+}
+
+void vec_widen(double* y, const float* x, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(widen_kernel, dim3(std::min(grid_for(n), 4096)), dim3(kBlock), 0, st, y, x, n);
 }
 
 void vec_axpby(double* y, double a, const double* x, double b, long long n, hipStream_t st) {

@@ -266,7 +266,9 @@ int lmdg_recover(lmdg_t* h, int scheme, int prec, const double* x, double* phi,
  * Solve K x = b with restarted GMRES(restart) from x0 (device, NULL = 0) until the
  * true FP64 relative residual ||b - K x|| / ||b|| <= tol, then recover the scalar
  * flux.  mode FP64: FP64 sweeps.  mode MIXED: an FP64 refinement loop around inner
- * GMRES solves that use FP32 sweeps; the FP64 operator defines the residual.  The
+ * GMRES solves that use FP32 sweeps and keep their Krylov basis in FP32 (products and
+ * sums in FP64, lmdg_set_refinement sets their target); the FP64 operator defines the
+ * residual.  The
  * restarts are augmented with earlier corrections when lmdg_set_augment set k > 0.
  *   x_out    device moment vector (solution of the reduced system)
  *   phi_out  device moment vector (scalar flux), NULL to skip

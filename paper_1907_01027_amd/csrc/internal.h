@@ -89,7 +89,7 @@ struct Sweep3Params {
   long long xedge_ostride, yedge_ostride;   // per (rhs, octant)
   double* psi;           // optional angular flux [n_rhs][n_dir][(8 moments, STD)][ncell]
   long long psi_rstride;
-  unsigned long long* prog;   // [n_rhs][8][nstrips][nblk] planes completed
+  unsigned long long* prog;   // [n_rhs][8][nstrips][nblk] periods completed (epoch in the high word)
   unsigned int* ticket;
   int* err;
   unsigned long long epoch;

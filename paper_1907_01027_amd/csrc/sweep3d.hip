@@ -20,8 +20,12 @@
 // the coefficients of plane p + 1 in LDS (a ring of L + 2 plane buffers whose slot for a
 // cell is its sequence index lambda modulo (L + 2) CB: one add and a mask per step where
 // that is a power of two, an add, compare and select otherwise), sums its outputs
-// over the slots and waves of the octant, and publishes how many planes it has completed;
-// it waits for (s, b - 1) and (s - 1, b) to have completed plane p before period p.
+// over the slots and waves of the octant, and publishes how many periods it has completed.
+// Before period p it waits for (s - 1, b) to have completed period p + L (row 15 of the
+// strip below has then passed every cell of plane p that row 0 handles in period p) and
+// for (s, b - 1) to have completed period p + 1 only: the x traces a row takes in period
+// p, the last column of plane p - (r >> log2 CB), leave block b - 1 by its period p + 1
+// for every row r.
 //
 // Exchange through global memory uses agent-scope atomic loads and stores only (edge
 // traces and progress words), so no cache maintenance is needed: a wave waits for its own
@@ -251,6 +255,19 @@ __device__ __forceinline__ void cell_std3(const Dir3<R>& d, R wa, const int si[3
   for (int n = 0; n < 8; ++n) o[n] = wa * c[n];
 }
 
+// Periods by which block b - 1 must lead block b: row r takes, in period p, the x trace
+// of plane p - (r >> LCB), which block b - 1 produces in its period p - (r >> LCB) +
+// ((CB - 1 + r) >> LCB) (the cell in its last column).
+constexpr int x_lead3(int cb, int lcb) {
+  int m = 0;
+  for (int r = 0; r < kRows; ++r) {
+    const int lead = ((cb - 1 + r) >> lcb) - (r >> lcb);
+    m = lead > m ? lead : m;
+  }
+  return m;
+}
+static_assert(x_lead3(4, 2) == 1 && x_lead3(8, 3) == 1 && x_lead3(16, 4) == 1, "x traces of block b - 1");
+
 // P1R: also the P_1 R rows of RLMDG (read by the recovery and by lmdg_sweep's output;
 // operator applications and right-hand sides skip them).  PSI: angular fluxes stored.
 template <typename R, int S, int MAXW, int CB, bool P1R, bool PSI>
@@ -266,6 +283,7 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
   constexpr int CB16 = CB * kRows;
   constexpr int L = (kRows - 1 + CB - 1) / CB;  // periods by which row 15 trails row 0
   constexpr int NBUF = nbuf3(L);                // staged planes: p - L .. p and p + 1
+  constexpr int XLEAD = x_lead3(CB, LCB);        // periods of block b - 1 ahead of block b
   constexpr int RING = NBUF * CB;               // staged cells per row (lambda modulo RING)
   constexpr int MAXC = (CB16 + 63) / 64;        // staged cells per thread (one wave at least)
   // y-trace values of a period per thread: CB ds NF of them over 64 ceil(ds / 4) threads
@@ -404,19 +422,20 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
     stage_store(0);
     int pb = 0;  // p % NBUF
     for (int p = 0; p < nz + L; ++p) {
-      // wait until (s, b - 1) and (s - 1, b) have completed plane p: thread 0 keeps the
-      // progress words it last read and reads a word again only while that falls short,
-      // both words at once
+      // wait until (s, b - 1) has completed period p + XLEAD and (s - 1, b) period p + L
+      // (both clamped to the last period): thread 0 keeps the progress words it last read
+      // and reads a word again only while that falls short, both words at once
       if (tid == 0 && (s > 0 || b > 0)) {
-        const int need = min(p + 1, nz);
-        const unsigned long long target = ((P.epoch + P.wait_bias) << 32) | (unsigned long long)need;
+        const unsigned long long tag = (P.epoch + P.wait_bias) << 32;
+        const unsigned long long tb = tag | (unsigned long long)min(p + 1 + XLEAD, nz + L);
+        const unsigned long long ts = tag | (unsigned long long)min(p + 1 + L, nz + L);
         const unsigned long long* fb = progr + (long long)s * nblk + (b - 1);
         const unsigned long long* fs = progr + (long long)(s - 1) * nblk + b;
         long long spins = 0;
-        while ((b > 0 && seen_b < target) || (s > 0 && seen_s < target)) {
-          if (b > 0 && seen_b < target) seen_b = load_agent(fb);
-          if (s > 0 && seen_s < target) seen_s = load_agent(fs);
-          if ((b > 0 && seen_b < target) || (s > 0 && seen_s < target)) {
+        while ((b > 0 && seen_b < tb) || (s > 0 && seen_s < ts)) {
+          if (b > 0 && seen_b < tb) seen_b = load_agent(fb);
+          if (s > 0 && seen_s < ts) seen_s = load_agent(fs);
+          if ((b > 0 && seen_b < tb) || (s > 0 && seen_s < ts)) {
             __builtin_amdgcn_s_sleep(2);
             if (++spins > P.spin_limit) { atomicOr(P.err, 1); break; }
           }
@@ -684,13 +703,12 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
           for (int m = 0; m < NOUT; ++m) dst[(long long)m * nc] = acc[m];
         }
       }
-      // publish: planes below `done` are finished by every row of the block (their trace
-      // stores included); waves wait for their own stores before the barrier
-      const int done = min(p + 1 - L, nz);
-      const bool publish = done > 0 && (s + 1 < nstrips || b + 1 < nblk);
+      // publish: periods 0 .. p are finished by every row of the block (their trace stores
+      // included); waves wait for their own stores before the barrier
+      const bool publish = s + 1 < nstrips || b + 1 < nblk;
       if (publish) __builtin_amdgcn_s_waitcnt(kWaitVmem);
       __syncthreads();
-      if (tid == 0 && publish) store_agent(progr + (long long)s * nblk + b, (P.epoch << 32) | (unsigned long long)done);
+      if (tid == 0 && publish) store_agent(progr + (long long)s * nblk + b, (P.epoch << 32) | (unsigned long long)(p + 1));
       pb = pb1;
     }
     __syncthreads();

@@ -674,12 +674,19 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
           for (int f = 0; f < NF; ++f) store_agent(dst + f * ds * kRows, xsave[f]);
         }
       }
-      // the next plane's coefficients to LDS and the period's outputs before the progress
-      // word: the write-through of the trace stores above completes meanwhile
+      // the next plane's coefficients to LDS before the progress word: the write-through of
+      // the trace stores above completes meanwhile
       const int pb1 = (pb + 1 == NBUF) ? 0 : pb + 1;
       if (p + 1 < nz) stage_store(pb1);
-      // the period's outputs: one cell per (row, column of the block) and thread, its
-      // NOUT rows summed over the waves
+      // publish: periods 0 .. p are finished by every row of the block (their trace stores
+      // included); waves wait for their own stores before the barrier
+      const bool publish = s + 1 < nstrips || b + 1 < nblk;
+      if (publish) __builtin_amdgcn_s_waitcnt(kWaitVmem);
+      __syncthreads();
+      if (tid == 0 && publish) store_agent(progr + (long long)s * nblk + b, (P.epoch << 32) | (unsigned long long)(p + 1));
+      // the period's outputs after the progress word (the wait before it covers the trace
+      // stores only): one cell per (row, column of the block) and thread, its NOUT rows
+      // summed over the waves; the next period writes red after its first barrier
       for (int t = tid; t < CB16; t += blockDim.x) {
         const int cl = t & (CB - 1), rr = t >> LCB;
         const int u = (rr + cl) & (CB - 1);
@@ -703,12 +710,6 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
           for (int m = 0; m < NOUT; ++m) dst[(long long)m * nc] = acc[m];
         }
       }
-      // publish: periods 0 .. p are finished by every row of the block (their trace stores
-      // included); waves wait for their own stores before the barrier
-      const bool publish = s + 1 < nstrips || b + 1 < nblk;
-      if (publish) __builtin_amdgcn_s_waitcnt(kWaitVmem);
-      __syncthreads();
-      if (tid == 0 && publish) store_agent(progr + (long long)s * nblk + b, (P.epoch << 32) | (unsigned long long)(p + 1));
       pb = pb1;
     }
     __syncthreads();

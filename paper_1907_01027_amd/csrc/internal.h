@@ -84,7 +84,7 @@ struct Sweep3Params {
   const double* dirs;    // [8][dslots][kDirStride]: Ox, Oy, Oz, w, index
   const R* coef;         // per-cell coefficients (coef3_kernel layout)
   R* part;               // [n_rhs][8][NOUT][ncell]
-  R* xedge;              // [n_rhs][8][nz][nstrips][nblk][NF][dslots][16] last-column traces
+  R* xedge;              // [n_rhs][8][nz + L][nstrips][nblk][NF][dslots][16] last-column traces by period
   R* yedge;              // [n_rhs][8][nz][nstrips][nx][dslots][NF] top-row traces
   long long xedge_ostride, yedge_ostride;   // per (rhs, octant)
   double* psi;           // optional angular flux [n_rhs][n_dir][(8 moments, STD)][ncell]

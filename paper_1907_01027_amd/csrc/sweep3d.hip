@@ -459,10 +459,12 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
           const R v = load_agent(ysrc + (e < ne_in ? e : 0));
           ev[k] = e < ne_in ? v : R(0);
         }
+        // row r takes the trace of plane p - (r >> LCB), which block b - 1 stored in its
+        // period p + XL(r)
         const int qx = p - (r >> LCB);
         const bool ok = b > 0 && row_ok && qx >= 0 && qx < nz;
-        const R* xsrc = xeb + (((long long)min(max(qx, 0), nz - 1) * nstrips + s) * nblk + max(b - 1, 0)) * kRows * ds * NF +
-                        slot * kRows + r;
+        const int px = min(p + ((r + CB - 1) >> LCB) - (r >> LCB), nz + L - 1);
+        const R* xsrc = xeb + (((long long)px * nstrips + s) * nblk + max(b - 1, 0)) * kRows * ds * NF + slot * kRows + r;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
           const R v = load_agent(xsrc + f * ds * kRows);
@@ -665,14 +667,13 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
             store_agent(yeb + (((long long)q * nstrips + s) * nx + c) * ds * NF + (e - u * ds * NF), ybuf[e]);
         }
       }
-      // x traces for block b + 1: the period's cell in the block's last column
-      {
-        const int qx = p - ((r + CB - 1) >> LCB);
-        if (b + 1 < nblk && row_ok && qx >= 0 && qx < nz) {
-          R* dst = xeb + (((long long)qx * nstrips + s) * nblk + b) * kRows * ds * NF + slot * kRows + r;
+      // x traces for block b + 1: the period's cell in the block's last column, stored
+      // under the period for every row (rows whose cell lies outside the mesh hold finite
+      // values nobody reads), so that each wave writes whole 64-byte runs of 16 rows
+      if (b + 1 < nblk) {
+        R* dst = xeb + (((long long)p * nstrips + s) * nblk + b) * kRows * ds * NF + slot * kRows + r;
 #pragma unroll
-          for (int f = 0; f < NF; ++f) store_agent(dst + f * ds * kRows, xsave[f]);
-        }
+        for (int f = 0; f < NF; ++f) store_agent(dst + f * ds * kRows, xsave[f]);
       }
       // the next plane's coefficients to LDS before the progress word: the write-through of
       // the trace stores above completes meanwhile
@@ -755,6 +756,9 @@ int launch_kernel3(lmdg_handle* h, const Sweep3Params<R>& P, int W, hipStream_t 
   return LMDG_OK;
 }
 
+// x traces are stored per period of the producing block: nz + L periods, L = ceil(15 / CB).
+constexpr int x_periods_extra3(int cb) { return (kRows - 1 + cb - 1) / cb; }
+
 // Column block width: 8 for FP32 sweeps, 4 for FP64 (the register ring holds CB x NF
 // values; wider blocks raise the register count past three waves per SIMD).
 constexpr int kMinBlockCols3 = 4;
@@ -812,7 +816,7 @@ int launch3_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipS
   P.part = reinterpret_cast<R*>(h->ws.part);
   h->last_nsl = 8;
   P.xedge = reinterpret_cast<R*>(h->ws.edge);
-  P.xedge_ostride = (long long)P.nz * P.nstrips * P.nblk * kRows * h->dslots * NF;
+  P.xedge_ostride = (long long)(P.nz + x_periods_extra3(CB)) * P.nstrips * P.nblk * kRows * h->dslots * NF;
   P.yedge = P.xedge + 8LL * h->n_rhs * P.xedge_ostride;
   P.yedge_ostride = (long long)P.nz * P.nstrips * P.nx * h->dslots * NF;
   P.psi = psi;
@@ -852,7 +856,9 @@ int launch3_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipS
 // coefficients, progress words.
 size_t sweep3d_edge_bytes(const lmdg_handle* h) {
   const long long nblk = (h->n[0] + kMinBlockCols3 - 1) / kMinBlockCols3;
-  return (size_t)8 * h->n[2] * h->nstrips * (nblk * kRows + h->n[0]) * h->dslots * 4 * sizeof(double);
+  const long long nz = h->n[2];
+  return (size_t)8 * h->nstrips * ((nz + x_periods_extra3(kMinBlockCols3)) * nblk * kRows + nz * h->n[0]) *
+         h->dslots * 4 * sizeof(double);
 }
 size_t sweep3d_coef_bytes(const lmdg_handle* h) { return (size_t)9 * h->ncell * sizeof(double); }
 size_t sweep3d_prog_words(const lmdg_handle* h) {

@@ -85,7 +85,7 @@ struct Sweep3Params {
   const R* coef;         // per-cell coefficients (coef3_kernel layout)
   R* part;               // [n_rhs][8][NOUT][ncell]
   R* xedge;              // [n_rhs][8][nz + L][nstrips][nblk][NF][dslots][16] last-column traces by period
-  R* yedge;              // [n_rhs][8][nz][nstrips][nx][dslots][NF] top-row traces
+  R* yedge;              // [n_rhs][8][nz + L][nstrips][nblk][CB][dslots][NF] top-row traces by period
   long long xedge_ostride, yedge_ostride;   // per (rhs, octant)
   double* psi;           // optional angular flux [n_rhs][n_dir][(8 moments, STD)][ncell]
   long long psi_rstride;

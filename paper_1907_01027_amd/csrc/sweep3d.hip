@@ -336,7 +336,7 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
     // consecutive bytes per trace value (agent-scope accesses go through to memory, so a
     // strided pattern would move whole lines for a quarter of their bytes)
     R* const xeb = P.xedge + ro * P.xedge_ostride;
-    R* const yeb = P.yedge + ro * P.yedge_ostride;   // [nz][nstrips][nx][ds][NF]
+    R* const yeb = P.yedge + ro * P.yedge_ostride;   // [nz + L][nstrips][nblk][CB][ds][NF]
     unsigned long long* const progr = P.prog + ro * (long long)nstrips * nblk;
     double* const psir = PSI ? P.psi + rh * P.psi_rstride : nullptr;
     const R* const cf_rh = P.coef + (long long)rh * NA * nc;
@@ -451,12 +451,16 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
       {
         const int ne = CB * ds * NF;
         const int ne_in = (s > 0 && p < nz) ? min(CB, nx - c0) * ds * NF : 0;  // columns inside the mesh
-        const R* ysrc = yeb + (((long long)min(p, nz - 1) * nstrips + max(s - 1, 0)) * nx + c0) * ds * NF;
+        // row 15 of strip s - 1 passed the cell in column 0 at the last step of its period
+        // p + L - 1 and the cells in columns 1 .. CB - 1 at steps 0 .. CB - 2 of period p + L
+        const long long yblk = (long long)max(s - 1, 0) * nblk + b;
+        const R* ya = yeb + ((long long)min(p + L - 1, nz + L - 1) * nstrips * nblk + yblk) * ne + (CB - 1) * ds * NF;
+        const R* yb = yeb + ((long long)min(p + L, nz + L - 1) * nstrips * nblk + yblk) * ne - ds * NF;
         R ev[MAXE];
 #pragma unroll
         for (int k = 0; k < MAXE; ++k) {
           const int e = tid + k * (int)blockDim.x;
-          const R v = load_agent(ysrc + (e < ne_in ? e : 0));
+          const R v = load_agent(e < ne_in ? (e < ds * NF ? ya : yb) + e : yeb);
           ev[k] = e < ne_in ? v : R(0);
         }
         // row r takes the trace of plane p - (r >> LCB), which block b - 1 stored in its
@@ -654,18 +658,13 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
           if (u == 0 && p + 1 < nz) stage_load(p + 1);
       }
       // y traces of the period's top-row cells for strip s + 1 (row 15 handled the cell
-      // lambda = u - 15 at step u)
+      // lambda = u - 15 at step u), stored under the period in one contiguous run (cells
+      // outside the mesh hold finite values nobody reads)
       lds_barrier();
       if (s + 1 < nstrips) {
         const int ne = CB * ds * NF;
-        for (int e = tid; e < ne; e += blockDim.x) {
-          const int u = e / (ds * NF);
-          const int dd = u - (kRows - 1);
-          const int q = p + (dd >> LCB);
-          const int c = c0 + (dd & (CB - 1));
-          if (q >= 0 && q < nz && c < nx)
-            store_agent(yeb + (((long long)q * nstrips + s) * nx + c) * ds * NF + (e - u * ds * NF), ybuf[e]);
-        }
+        R* dst = yeb + (((long long)p * nstrips + s) * nblk + b) * ne;
+        for (int e = tid; e < ne; e += blockDim.x) store_agent(dst + e, ybuf[e]);
       }
       // x traces for block b + 1: the period's cell in the block's last column, stored
       // under the period for every row (rows whose cell lies outside the mesh hold finite
@@ -756,7 +755,7 @@ int launch_kernel3(lmdg_handle* h, const Sweep3Params<R>& P, int W, hipStream_t 
   return LMDG_OK;
 }
 
-// x traces are stored per period of the producing block: nz + L periods, L = ceil(15 / CB).
+// Edge traces are stored per period of the producing item: nz + L periods, L = ceil(15 / CB).
 constexpr int x_periods_extra3(int cb) { return (kRows - 1 + cb - 1) / cb; }
 
 // Column block width: 8 for FP32 sweeps, 4 for FP64 (the register ring holds CB x NF
@@ -818,7 +817,7 @@ int launch3_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipS
   P.xedge = reinterpret_cast<R*>(h->ws.edge);
   P.xedge_ostride = (long long)(P.nz + x_periods_extra3(CB)) * P.nstrips * P.nblk * kRows * h->dslots * NF;
   P.yedge = P.xedge + 8LL * h->n_rhs * P.xedge_ostride;
-  P.yedge_ostride = (long long)P.nz * P.nstrips * P.nx * h->dslots * NF;
+  P.yedge_ostride = (long long)(P.nz + x_periods_extra3(CB)) * P.nstrips * P.nblk * CB * h->dslots * NF;
   P.psi = psi;
   P.psi_rstride = (long long)h->ndir * (S == LMDG_SCHEME_STD ? 8 : 1) * h->ncell;
   P.prog = h->ws.prog;
@@ -857,7 +856,7 @@ int launch3_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipS
 size_t sweep3d_edge_bytes(const lmdg_handle* h) {
   const long long nblk = (h->n[0] + kMinBlockCols3 - 1) / kMinBlockCols3;
   const long long nz = h->n[2];
-  return (size_t)8 * h->nstrips * ((nz + x_periods_extra3(kMinBlockCols3)) * nblk * kRows + nz * h->n[0]) *
+  return (size_t)8 * h->nstrips * (nz + x_periods_extra3(kMinBlockCols3)) * nblk * (kRows + kMinBlockCols3) *
          h->dslots * 4 * sizeof(double);
 }
 size_t sweep3d_coef_bytes(const lmdg_handle* h) { return (size_t)9 * h->ncell * sizeof(double); }

@@ -407,10 +407,13 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
     };
 
     R zreg[CB][NF], xin[NF], yprev[NF], xe[NF], xsave[NF];
+    // FP32: x traces block b - 1 stored in period p + 1, loaded in period p by every row
+    // (one whole 64-byte run per slot); rows that take them in period p + 1 hold them
+    R xhold[NF];
     unsigned long long seen_b = 0, seen_s = 0;  // progress words last read (thread 0)
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      xin[f] = yprev[f] = xsave[f] = R(0);
+      xin[f] = yprev[f] = xsave[f] = xhold[f] = R(0);
 #pragma unroll
       for (int u = 0; u < CB; ++u) zreg[u][f] = R(0);
     }
@@ -467,12 +470,30 @@ __global__ void __launch_bounds__(64 * MAXW, 3) sweep3d_kernel(Sweep3Params<R> P
         // period p + XL(r)
         const int qx = p - (r >> LCB);
         const bool ok = b > 0 && row_ok && qx >= 0 && qx < nz;
-        const int px = min(p + ((r + CB - 1) >> LCB) - (r >> LCB), nz + L - 1);
-        const R* xsrc = xeb + (((long long)px * nstrips + s) * nblk + max(b - 1, 0)) * kRows * ds * NF + slot * kRows + r;
+        if constexpr (sizeof(R) == 4) {
+          const bool later = ((r + CB - 1) >> LCB) == (r >> LCB);
+          const long long xrow = ((long long)s * nblk + max(b - 1, 0)) * kRows * ds * NF + slot * kRows + r;
+          const R* xsrc = xeb + (long long)min(p + 1, nz + L - 1) * nstrips * nblk * kRows * ds * NF + xrow;
+          R xl[NF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          const R v = load_agent(xsrc + f * ds * kRows);
-          xe[f] = ok ? v : R(0);
+          for (int f = 0; f < NF; ++f) xl[f] = load_agent(xsrc + f * ds * kRows);
+          if (p == 0) {  // the rows that take period 0's traces in period 0
+#pragma unroll
+            for (int f = 0; f < NF; ++f) xhold[f] = load_agent(xeb + xrow + f * ds * kRows);
+          }
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            xe[f] = ok ? (later ? xhold[f] : xl[f]) : R(0);
+            xhold[f] = xl[f];
+          }
+        } else {
+          const int px = min(p + ((r + CB - 1) >> LCB) - (r >> LCB), nz + L - 1);
+          const R* xsrc = xeb + (((long long)px * nstrips + s) * nblk + max(b - 1, 0)) * kRows * ds * NF + slot * kRows + r;
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            const R v = load_agent(xsrc + f * ds * kRows);
+            xe[f] = ok ? v : R(0);
+          }
         }
 #pragma unroll
         for (int k = 0; k < MAXE; ++k) {

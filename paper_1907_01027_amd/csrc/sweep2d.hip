@@ -483,6 +483,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
   // (dslots = 4 W, chunks of at most 16 columns)
   constexpr int MAXE = NF;
   constexpr bool LM = S != LMDG_SCHEME_STD;
+  constexpr bool YRUN = sizeof(R) == 4;  // strip-top traces staged in LDS and stored per chunk
   extern __shared__ unsigned char smem_raw[];
   __shared__ int s_item;
 
@@ -498,6 +499,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
   const int cw = 1 << lcw;
   const int ncells = kRows << lcw;  // cells staged per chunk
   // LDS: red [cw][W][NOUTP][16] (not with DIRECT) | coef [2][NC][cw][16] | eds [cw][NF][dslots]
+  //      | FP32: ybuf [cw][NF][dslots] (row 15's traces of the chunk, written out after its steps)
   // (coefficients structure-of-arrays: the 16 rows of one value are contiguous, so
   // 64-bit reads by the 16 rows of a wave hit distinct banks)
   R* red = reinterpret_cast<R*>(smem_raw);
@@ -506,6 +508,7 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
   const int red_tt = W * NOUTP * kRows + 1;
   R* coef = red + (DIRECT ? 0 : (size_t)cw * red_tt);
   R* eds = coef + (size_t)2 * ncells * NC;
+  R* ybuf = eds + (size_t)cw * NF * P.dslots;
   const int nsl = DIRECT ? 4 * W : 4;  // slices of the partials per right-hand side
 
   for (;;) {
@@ -752,13 +755,20 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
           }
         }
         if (r == kRows - 1 && s + 1 < P.nstrips) {
+          if constexpr (YRUN) {
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int c = t0 + tg + u - r;
-            if (row_ok && c >= 0 && c < nx) {
-              R* e = edger + ((((long long)q * P.nstrips + s) * nx + c) * NF) * P.dslots + slot;
+            for (int u = 0; u < U; ++u)
 #pragma unroll
-              for (int f = 0; f < NF; ++f) store_agent(e + (long long)f * P.dslots, yo_g[u][f]);
+              for (int f = 0; f < NF; ++f) ybuf[((tg + u) * NF + f) * P.dslots + slot] = yo_g[u][f];
+          } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const int c = t0 + tg + u - r;
+              if (row_ok && c >= 0 && c < nx) {
+                R* e = edger + ((((long long)q * P.nstrips + s) * nx + c) * NF) * P.dslots + slot;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) store_agent(e + (long long)f * P.dslots, yo_g[u][f]);
+              }
             }
           }
         }
@@ -779,6 +789,17 @@ __global__ void __launch_bounds__(64 * MAXW) sweep2d_kernel(SweepParams<R> P) {
             }
           }
         }
+      }
+      // FP32: the chunk's strip-top traces, columns t0 - 15 .. t0 + cw - 16 inside the mesh,
+      // as one contiguous run (stored from row 15 per step, each wave's direction slots
+      // fall into short pieces of a column's run; in FP64 the extra barrier and LDS cost
+      // more than the pieces)
+      if (YRUN && s + 1 < P.nstrips) {
+        lds_barrier();
+        const int nds = NF * P.dslots;
+        const int e_lo = max(0, kRows - 1 - t0) * nds, e_hi = min(cw, nx - t0 + kRows - 1) * nds;
+        const long long base = (((long long)q * P.nstrips + s) * nx + (t0 - (kRows - 1))) * nds;
+        for (int e = e_lo + tid; e < e_hi; e += blockDim.x) store_agent(edger + (base + e), ybuf[e]);
       }
       // publish this chunk's strip-top traces before the staging and reduction below,
       // which the strip above does not wait for: every wave waits for its own trace
@@ -823,7 +844,8 @@ size_t lds_bytes(int cw, int W, int dslots, bool direct) {
   constexpr int NC = SrcTraitsV<S, VAR>::NC;
   constexpr int NOUTP = (NOUT + 3) & ~3;
   const size_t red = direct ? 0 : (size_t)cw * (W * NOUTP * kRows + 1);  // cross-wave sums
-  return (red + (size_t)2 * cw * kRows * NC + (size_t)cw * NF * dslots) * sizeof(R);
+  const size_t edges = (sizeof(R) == 4 ? 2 : 1) * (size_t)cw * NF * dslots;  // eds (and ybuf in FP32)
+  return (red + (size_t)2 * cw * kRows * NC + edges) * sizeof(R);
 }
 
 // The plain (no inflow data, default reconstruction) instantiations, with or without the

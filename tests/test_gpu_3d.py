@@ -147,6 +147,35 @@ def test_apply_3d_across_combine_tiles(scheme):
 
 
 @pytest.mark.parametrize("scheme", ["lmdg", "rlmdg"])
+def test_apply_3d_block_and_strip_chains(scheme):
+    """K x on a mesh of three strips (16 + 16 + 1 rows) and four blocks of 8 columns (FP32)
+    or seven of 4 (FP64), ragged in every direction: the x traces pass along chains of
+    blocks and the y traces up the strips, both stored under the producing period.  FP64
+    at 1e-12 and FP32 at 2e-5 against the oracle, twice in a row."""
+    shape = (25, 33, 3)
+    print(f"case 3d apply block and strip chains {scheme} {shape} S4", flush=True)
+    case = Case3(shape, 4, eps=0.05)
+    s = case.solver()
+    nc = case.ncell
+    red = S.LowMemoryReduced(case.prob, scheme == "rlmdg")
+    y = torch.zeros(8 * nc, dtype=torch.float64, device=DEV)
+    errs = []
+    try:
+        for seed in (11, 12):
+            x = np.random.default_rng(seed).normal(size=8 * nc)
+            ref_y = lm_to_abi(red.apply(abi_to_lm(x, nc)), nc)
+            for prec in ("fp64", "fp32"):
+                y.zero_()
+                lmdg.lmdg_apply(s.h, scheme, prec, T(x), y)
+                errs.append((prec, rel_err(N(y), ref_y)))
+    finally:
+        s.close()
+    print(errs)
+    for prec, e in errs:
+        assert e < (1e-12 if prec == "fp64" else 2e-5)
+
+
+@pytest.mark.parametrize("scheme", ["lmdg", "rlmdg"])
 @pytest.mark.parametrize("mode", ["fp64", "mixed"])
 def test_solve_3d_against_direct(scheme, mode):
     print(f"case 3d solve {scheme} {mode}", flush=True)

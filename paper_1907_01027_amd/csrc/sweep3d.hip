@@ -129,56 +129,68 @@ __global__ void coef3_kernel(Coef3Params P, R* __restrict__ out) {
   constexpr int NA = Traits3<S>::NA;
   const long long nc = P.ncell;
   const long long stride[3] = {1, P.n[0], (long long)P.n[0] * P.n[1]};
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < P.n_rhs * nc;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int rh = (int)(e / nc);
-    const long long cell = e - rh * nc;
-    const double* x = P.x ? P.x + (long long)rh * 8 * nc : nullptr;
-    const double qA = P.qA ? P.qA[(long long)rh * nc + cell] : 0.0;
-    R* o = out + (long long)rh * NA * nc + cell;
-    if constexpr (S == LMDG_SCHEME_STD) {
-      const double scat = P.scatA[cell];
-#pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        const double v = x ? scat * mass3<double>(m) * x[m * nc + cell] : 0.0;
-        o[m * nc] = (R)(m == 0 ? v + qA : v);
-      }
-      if (rh == 0) out[(long long)P.n_rhs * NA * nc + cell] = (R)P.sigtA[cell];
+  // one cell per thread and loop trip, all sources in turn: the cell's indices are formed
+  // once (32-bit divisions where the mesh allows; 64-bit ones cost several times more)
+  for (long long cell = blockIdx.x * (long long)blockDim.x + threadIdx.x; cell < nc;
+       cell += (long long)gridDim.x * blockDim.x) {
+    int idx[3];
+    if (nc <= 0xffffffffll) {
+      const unsigned c = (unsigned)cell, n0 = (unsigned)P.n[0], n1 = (unsigned)P.n[1];
+      const unsigned t = c / n0;
+      idx[0] = (int)(c - t * n0);
+      idx[1] = (int)(t % n1);
+      idx[2] = (int)(t / n1);
     } else {
-      const int idx[3] = {(int)(cell % P.n[0]), (int)((cell / P.n[0]) % P.n[1]),
-                          (int)(cell / ((long long)P.n[0] * P.n[1]))};
-      const double x0 = x ? x[cell] : 0.0;
-      o[0] = (R)((P.defect ? P.absA[cell] : P.scatA[cell]) * x0 + qA);
+      idx[0] = (int)(cell % P.n[0]);
+      idx[1] = (int)((cell / P.n[0]) % P.n[1]);
+      idx[2] = (int)(cell / ((long long)P.n[0] * P.n[1]));
+    }
+    for (int rh = 0; rh < P.n_rhs; ++rh) {
+      const double* x = P.x ? P.x + (long long)rh * 8 * nc : nullptr;
+      const double qA = P.qA ? P.qA[(long long)rh * nc + cell] : 0.0;
+      R* o = out + (long long)rh * NA * nc + cell;
+      if constexpr (S == LMDG_SCHEME_STD) {
+        const double scat = P.scatA[cell];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int sm = 1 << a;  // slope moment of axis a
-#pragma unroll
-        for (int sg = 0; sg < 2; ++sg) {
-          const int sgn = sg ? -1 : 1;
-          const int pos = sgn > 0 ? idx[a] : P.n[a] - 1 - idx[a];  // upwind cells inside the mesh
-          double b = 0.0;
-          if (x) {
-            const long long up = cell - sgn * stride[a];
-            const double u1 = pos >= 1 ? x[up] : 0.0;
-            const double u2 = pos >= 2 ? x[up - sgn * stride[a]] : 0.0;
-            const double sl = x[sm * nc + cell], slu = pos >= 1 ? x[sm * nc + up] : 0.0;
-            const double ds = sgn * P.A[a] * (sl - slu);
-            b = ds;
-            if (P.defect) {
-              double t = x0, tu = u1;
-              if (S == LMDG_SCHEME_RLMDG) {
-                t = x0 + (pos == 0 ? 1.0 : 0.5) * (x0 - u1);
-                tu = pos > 0 ? u1 + (pos == 1 ? 1.0 : 0.5) * (u1 - u2) : 0.0;
-              }
-              b = -ds + P.A[a] * (t - tu);
-            }
-          }
-          o[(1 + 2 * a + sg) * nc] = (R)b;
+        for (int m = 0; m < 8; ++m) {
+          const double v = x ? scat * mass3<double>(m) * x[m * nc + cell] : 0.0;
+          o[m * nc] = (R)(m == 0 ? v + qA : v);
         }
-      }
-      if (rh == 0) {
-        out[(long long)P.n_rhs * NA * nc + cell] = (R)P.sigtA[cell];
-        out[((long long)P.n_rhs * NA + 1) * nc + cell] = (R)(P.absA[cell] * (1.0 / 3.0));
+        if (rh == 0) out[(long long)P.n_rhs * NA * nc + cell] = (R)P.sigtA[cell];
+      } else {
+        const double x0 = x ? x[cell] : 0.0;
+        o[0] = (R)((P.defect ? P.absA[cell] : P.scatA[cell]) * x0 + qA);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int sm = 1 << a;  // slope moment of axis a
+#pragma unroll
+          for (int sg = 0; sg < 2; ++sg) {
+            const int sgn = sg ? -1 : 1;
+            const int pos = sgn > 0 ? idx[a] : P.n[a] - 1 - idx[a];  // upwind cells inside the mesh
+            double b = 0.0;
+            if (x) {
+              const long long up = cell - sgn * stride[a];
+              const double u1 = pos >= 1 ? x[up] : 0.0;
+              const double u2 = pos >= 2 ? x[up - sgn * stride[a]] : 0.0;
+              const double sl = x[sm * nc + cell], slu = pos >= 1 ? x[sm * nc + up] : 0.0;
+              const double ds = sgn * P.A[a] * (sl - slu);
+              b = ds;
+              if (P.defect) {
+                double t = x0, tu = u1;
+                if (S == LMDG_SCHEME_RLMDG) {
+                  t = x0 + (pos == 0 ? 1.0 : 0.5) * (x0 - u1);
+                  tu = pos > 0 ? u1 + (pos == 1 ? 1.0 : 0.5) * (u1 - u2) : 0.0;
+                }
+                b = -ds + P.A[a] * (t - tu);
+              }
+            }
+            o[(1 + 2 * a + sg) * nc] = (R)b;
+          }
+        }
+        if (rh == 0) {
+          out[(long long)P.n_rhs * NA * nc + cell] = (R)P.sigtA[cell];
+          out[((long long)P.n_rhs * NA + 1) * nc + cell] = (R)(P.absA[cell] * (1.0 / 3.0));
+        }
       }
     }
   }
@@ -827,7 +839,7 @@ int launch3_typed(lmdg_handle* h, const double* x, bool use_q, double* psi, hipS
     C.sigtA = h->d_sigtA;
     C.scatA = h->d_scatA;
     C.absA = h->d_absA;
-    const long long n = h->ncell * h->n_rhs;
+    const long long n = h->ncell;  // one thread per cell, all sources
     const int g = (int)std::min<long long>(std::max<long long>((n + 255) / 256, 1), 8192);
     hipLaunchKernelGGL((coef3_kernel<R, S>), dim3(g), dim3(256), 0, st, C, coef);
     (void)NA;
